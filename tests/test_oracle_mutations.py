@@ -1,0 +1,106 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case copies ``oracle/fd_oracle.c`` to a temporary directory, plants one
+mistake by text substitution (a wrong sign, index, spacing, term or weight),
+compiles the copy, points the oracle wrapper at it, and runs pin tests that
+must now fail.  The committed oracle source is never modified.
+"""
+import contextlib
+import subprocess
+from pathlib import Path
+
+import pytest
+
+import oracle
+from tests import test_oracle_acoustic as ta
+from tests import test_oracle_tti as tt
+from tests import test_oracle_weights as tw
+
+SRC = Path(oracle.__file__).resolve().parent / "fd_oracle.c"
+
+
+@contextlib.contextmanager
+def mutant(tmp_path, old, new):
+    text = SRC.read_text()
+    assert text.count(old) >= 1, old
+    so = tmp_path / "liboracle_mutant.so"
+    c = tmp_path / "fd_oracle_mutant.c"
+    c.write_text(text.replace(old, new, 1))
+    subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                    "-o", str(so), str(c), "-lm"], check=True)
+    saved = (oracle._LIB, oracle._lib_handle)
+    oracle._LIB, oracle._lib_handle = so, None
+    try:
+        yield
+    finally:
+        oracle._LIB, oracle._lib_handle = saved
+
+
+def caught(checks):
+    for fn in checks:
+        try:
+            fn()
+        except Exception:
+            return True
+    return False
+
+
+ACOUSTIC = [
+    lambda: ta.test_bruteforce_2d(4),
+    lambda: ta.test_bruteforce_3d(4),
+    lambda: ta.test_plane_wave_exact(3, 4),
+]
+TTI = [
+    lambda: tt.test_rotated_operators_sum_to_laplacian(4),
+    lambda: tt.test_rotated_operators_dense_geometric(2),
+    lambda: tt.test_tti_plane_wave_exact(4),
+    tt.test_dense_bruteforce_tti_run,
+]
+
+MUTANTS = [
+    # weights: wrong alternation of the second-derivative weights
+    ("w2 sign", "double sgn = (j % 2 == 1) ? 1.0 : -1.0;\n        w[j] = 2.0",
+     "double sgn = (j % 2 == 0) ? 1.0 : -1.0;\n        w[j] = 2.0",
+     [lambda: tw.test_second_derivative_polynomial_exactness(8)]),
+    # weights: first derivative divided by j^2 instead of j
+    ("w1 power", "w[j] = sgn * fact_ratio(r, j) / (double)j;",
+     "w[j] = sgn * fact_ratio(r, j) / ((double)j * (double)j);",
+     [lambda: tw.test_first_derivative_polynomial_exactness(4)]),
+    # CFL with a1 = 2
+    ("cfl a1", "return sqrt(4.0 / denom) / vmax;", "return sqrt(2.0 / denom) / vmax;",
+     [tw.test_table2_dt_column]),
+    # Laplacian: z term scaled with the x spacing
+    ("lap spacing", "L += sz / (h[2] * h[2]);", "L += sz / (h[0] * h[2]);", ACOUSTIC),
+    # Laplacian: off-by-one neighbour along z
+    ("lap z index", "sz += w[j] * (at(u, n, ix, iy, iz + j) + at(u, n, ix, iy, iz - j));",
+     "sz += w[j] * (at(u, n, ix, iy, iz + j) + at(u, n, ix, iy, iz - j + 1));", ACOUSTIC),
+    # Laplacian: y term dropped
+    ("lap y dropped", "        L += sy / (h[1] * h[1]);\n", "", ACOUSTIC),
+    # damping: wrong sign on the previous level
+    ("damping sign", "return (2.0 * fget(uc, i) - (1.0 - s) * fget(up, i) + A * L) / (1.0 + s);",
+     "return (2.0 * fget(uc, i) - (1.0 + s) * fget(up, i) + A * L) / (1.0 + s);", ACOUSTIC),
+    # source: forgetting the cell volume
+    ("source volume", "un[idx[c]] += w[c] * A * (double)q[s] / (hp * (1.0 + sg));",
+     "un[idx[c]] += w[c] * A * (double)q[s] / (1.0 + sg);", ACOUSTIC),
+    # interpolation: corner weights swapped along x
+    ("interp swap", "w[m] = (dx ? fx : 1.0 - fx) * (dz ? fz : 1.0 - fz);",
+     "w[m] = (dx ? 1.0 - fx : fx) * (dz ? fz : 1.0 - fz);", ACOUSTIC),
+    # TTI: sign of the xy term of G_xbar_xbar
+    ("Gxx xy sign", "+ s2p * ct * ct * d.dxy - sp * s2t * d.dyz",
+     "- s2p * ct * ct * d.dxy - sp * s2t * d.dyz", TTI),
+    # TTI: yz cross derivative taken along xz
+    ("dyz axes", "syz += wa * wb * at(f, n, ix, iy + a, iz + b);",
+     "syz += wa * wb * at(f, n, ix + a, iy, iz + b);", TTI),
+    # TTI: the coupling factor sqrt(1 + 2 delta) dropped in the p equation
+    ("tti coupling", "A * (e2 * hp + sd * gr.gzz)", "A * (e2 * hp + gr.gzz)", TTI),
+    # TTI: Gzz coefficient of dzz uses sin instead of cos
+    ("Gzz dzz", "+ ct * ct * d.dzz\n", "+ st * st * d.dzz\n", TTI),
+]
+
+
+@pytest.mark.parametrize("name,old,new,checks", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(tmp_path, name, old, new, checks):
+    with mutant(tmp_path, old, new):
+        assert caught(checks), f"planted mistake '{name}' passed every pin"
+    # the real oracle still passes the same checks
+    assert not caught(checks)
