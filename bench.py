@@ -1,0 +1,194 @@
+"""Benchmark: 3D acoustic finite-difference time stepping on one MI355X.
+
+Workload: the 512^3 physical grid (h = 10 m) with a 40-point damping layer
+(592^3 = 207.5 M points updated per step), two-layer velocity 1.5 / 3.5 km/s
+with a smooth +-5 % perturbation, 10 Hz Ricker point source, 512 x 512
+surface receivers, swept over space orders 4, 8, 12 and 16.
+
+A step is one time step of the whole path for one order: the stencil update
+with damping, the source injection and the receiver sampling.  Each order runs
+``--warmup`` untimed steps and then ``--steps`` timed steps (inputs resident
+in HBM, timed with events on the launch stream between two synchronisations).
+
+Printed (one JSON line): value = Gpt/s over the sweep (total point updates /
+total time), the per-order figures, the roofline of the stencil kernel
+(algorithmic 16 bytes per point update / the kernel's average launch time,
+measured in a second timed loop that launches only the stencil), and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+BYTES_PER_POINT = 16           # read u^n, u^{n-1}, dt^2 v^2; write u^{n+1}
+ORDERS = (4, 8, 12, 16)
+
+
+def paper_flops(so: int) -> int:
+    """FLOPs per point update of the acoustic stencil, 6k + 4 with k = so + 1
+    points per 1D stencil (Table 1)."""
+    return 6 * (so + 1) + 4
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--orders", type=str, default=",".join(map(str, ORDERS)))
+    ap.add_argument("--phys", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def timed(fn, stream_events):
+    import torch
+
+    start, end = stream_events
+    torch.cuda.synchronize()
+    start.record()
+    fn()
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / 1e3
+
+
+def cpu_baseline(problem, seconds: float):
+    """The FP64 oracle on a z-slab of the workload (full x-y extent)."""
+    import oracle
+
+    threads = max(1, min(os.cpu_count() or 1, 16))
+    oracle.set_threads(threads)
+    p = problem
+    slab = 48
+    vel = np.ascontiguousarray(p.vel[:slab])
+    eta = np.ascontiguousarray(p.eta[:slab])
+    pts = vel.size
+    rates = {}
+    t_total = 0.0
+    budget = seconds / len(ORDERS)
+    for so in ORDERS:
+        from workloads import DT
+        dt = DT[("acoustic_3d", so)]
+        up = np.zeros(vel.shape)
+        uc = np.zeros(vel.shape)
+        uc[slab // 2, vel.shape[1] // 2, vel.shape[2] // 2] = 1.0
+        steps = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget:
+            _, up, uc = oracle.acoustic_forward(3, 0, p.spacing, dt, so, vel, eta, [],
+                                                np.zeros((1, 0)), [], 1, up, uc)
+            steps += 1
+        el = time.perf_counter() - t0
+        t_total += el
+        rates[so] = pts * steps / el / 1e9
+    oracle.set_threads(1)
+    agg = len(ORDERS) / sum(1.0 / r for r in rates.values())
+    return {
+        "value": round(agg, 5), "unit": "Gpt/s", "cores": threads, "kind": "oracle",
+        "sample": (f"FP64 oracle, {vel.shape[2]}x{vel.shape[1]}x{slab} slab of the workload, "
+                   f"so 4/8/12/16, ~{seconds:.0f} s total; per order Gpt/s "
+                   + ", ".join(f"so{k} {v:.4f}" for k, v in rates.items())),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not "
+                                   "supported (the solver has no multi-GPU path)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1608_03984_amd as P
+    from paper_1608_03984_amd.solver import Solver
+    from workloads import DT, acoustic_3d
+
+    orders = [int(s) for s in args.orders.split(",")]
+    t0 = time.perf_counter()
+    prob = acoustic_3d(so=8, phys=args.phys, nbl=40, nt=1, receivers="surface")
+    print(f"# model generated in {time.perf_counter() - t0:.1f} s, padded {prob.padded}",
+          file=sys.stderr, flush=True)
+    npts = prob.npoints
+    dev = torch.device("cuda:0")
+    rec = prob.rec
+    per = []
+    tot_pts = 0.0
+    tot_time = 0.0
+    tot_kernel = 0.0
+    for so in orders:
+        dt = DT[("acoustic_3d", so)]
+        from workloads import ricker
+        nt = args.warmup + args.steps
+        wav = torch.from_numpy(ricker(10.0, dt, nt)[:, None]).to(dev)
+        traces = torch.empty((nt, rec.shape[0]), dtype=torch.float32, device=dev)
+        s = Solver(3, prob.shape, prob.spacing, prob.nbl, so, dt, prob.vel, prob.eta,
+                   max_points=1 + rec.shape[0], device=dev)
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        # warm-up (also uploads the point tables)
+        s.forward(args.warmup, prob.src, wav[:args.warmup], rec, traces=traces[:args.warmup])
+        tw = timed(lambda: s.forward(args.steps, prob.src, wav[args.warmup:], rec,
+                                     zero_state=False, traces=traces[args.warmup:]), ev)
+        # the stencil kernel alone (no sparse points): its average launch time
+        s.forward(args.warmup, zero_state=False)
+        tk = timed(lambda: s.forward(args.steps, zero_state=False), ev)
+        ok = bool(torch.isfinite(traces).all().item())
+        s.close()
+        del s, traces
+        torch.cuda.empty_cache()
+        gpts = npts * args.steps / tw / 1e9
+        kernel_ms = tk / args.steps * 1e3
+        achieved = BYTES_PER_POINT * npts / (kernel_ms / 1e3) / 1e9
+        per.append({"so": so, "gpts": round(gpts, 2), "ms_per_step": round(tw / args.steps * 1e3, 4),
+                    "stencil_ms": round(kernel_ms, 4), "stencil_gbs": round(achieved, 1),
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "gflops_paper": round(paper_flops(so) * npts / (kernel_ms / 1e3) / 1e9, 1),
+                    "finite": ok})
+        print(f"# so{so}: {gpts:.1f} Gpt/s, stencil {kernel_ms:.3f} ms = {achieved:.0f} GB/s",
+              file=sys.stderr, flush=True)
+        tot_pts += npts * args.steps
+        tot_time += tw
+        tot_kernel += tk
+    value = tot_pts / tot_time / 1e9
+    ach = BYTES_PER_POINT * tot_pts / tot_kernel / 1e9
+    line = {
+        "metric": "Gpt/s, % roofline (3D acoustic SO4-16)",
+        "value": round(value, 3),
+        "unit": "Gpt/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(tot_time / (args.steps * len(orders)) * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"3D isotropic acoustic, {args.phys}^3 + 40-pt layer "
+                               f"({prob.padded[0]}^3 points), h=10 m, two-layer v with +-5% "
+                               f"smooth perturbation, 1 Ricker source, {rec.shape[0]} receivers",
+                   "space_orders": orders, "points": npts},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "acoustic3d_tiled (sweep aggregate)"},
+        "per_order": per,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * fd.h -- C ABI of the MI355X (gfx950) explicit finite-difference wave
+ * propagation library (libfd.so).
+ *
+ * The library implements the time-stepping scheme of Louboutin et al.,
+ * "Performance prediction of finite-difference solvers for different computer
+ * architectures": Algorithm 1 (section 2) -- a second-order leapfrog update of
+ * the wavefield by a symmetric k-point stencil, followed by source injection --
+ * for
+ *   - the acoustic equation of Appendix A, Eq. (Acou): m u_tt - lap u = q with
+ *     m = 1/v^2 and zero initial state, and
+ *   - the TTI pseudo-acoustic system of Appendix A, Eq. (TTI), whose rotated
+ *     operators are those of Eq. (DiffOp),
+ * with an absorbing layer (the paper leaves boundary treatment outside its
+ * model, section 2) and receivers sampled from the updated field.
+ *
+ * Conventions
+ *   - Space order "so" is the order of the central stencils; the 1D stencil
+ *     has k = so + 1 points (section 4.1) and radius r = so / 2.
+ *   - Every field the caller passes or receives is float32, C-order
+ *     [Nz][Ny][Nx] with x contiguous (2D: [Nz][Nx]), over the padded array
+ *     N_a = n_a + 2 nbl (physical points plus the layer on both sides).
+ *   - Coordinates are double, metres from the physical origin (the first
+ *     physical grid point), ordered (x, y, z) in 3D and (x, z) in 2D.
+ *   - Points beyond the padded array read as zero (homogeneous Dirichlet).
+ *   - Sparse points are interpolated multilinearly: along each axis the cell
+ *     index is i = floor(c/h + nbl) clamped to [0, N-2], weights 1-f and f.
+ *
+ * Ownership and threading
+ *   - The caller owns every device buffer, including the workspace; the
+ *     library never allocates device memory.  It owns only the small host
+ *     context returned by fd_setup (freed by fd_destroy).
+ *   - All device work is enqueued asynchronously on the hipStream_t passed as
+ *     `stream` (NULL = default stream); calls return without waiting, except
+ *     where stated.  Synchronise on that stream before reading results.
+ *   - One context serves one stream at a time and is not thread-safe.  There is
+ *     no global mutable state.
+ *
+ * Errors: every entry point returns an int32 status (FD_OK = 0).  No exception
+ * crosses the ABI and nothing is printed.  fd_last_error() gives a
+ * per-context message for the last failure.
+ */
+#ifndef FD_H
+#define FD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define FD_OK 0
+#define FD_ERR_INVALID_ARG 1 /* bad pointer, shape, order, point or count */
+#define FD_ERR_UNSTABLE_DT 2 /* dt above the CFL bound of Eq. (stability) */
+#define FD_ERR_UNSUPPORTED 3 /* space order or physics not built */
+#define FD_ERR_WORKSPACE 4   /* workspace too small or misaligned */
+#define FD_ERR_DEVICE 5      /* a HIP runtime call failed */
+#define FD_ERR_NONFINITE 6   /* non-finite or non-positive model values */
+
+/* Physics. */
+#define FD_ACOUSTIC 0 /* Eq. (Acou), 2D or 3D */
+#define FD_TTI 1      /* Eq. (TTI) with Eq. (DiffOp), 3D */
+
+/* Wavefield selectors for fd_get_field / fd_set_field.  Acoustic uses the
+ * first two; TTI uses all four (p and r). */
+#define FD_FIELD_PREV 0   /* u^{n-1}  (TTI: p^{n-1}) */
+#define FD_FIELD_CUR 1    /* u^{n}    (TTI: p^{n})   */
+#define FD_FIELD_R_PREV 2 /* TTI r^{n-1} */
+#define FD_FIELD_R_CUR 3  /* TTI r^{n}   */
+
+/* fd_forward flags. */
+#define FD_ZERO_STATE 1 /* start from the zero state of Eq. (Acou)/(TTI) */
+
+/* Largest supported space order (radius 8). */
+#define FD_MAX_SPACE_ORDER 16
+
+typedef struct fd_grid {
+    int32_t ndim;        /* 2 or 3 */
+    int32_t space_order; /* even, 2..FD_MAX_SPACE_ORDER */
+    int32_t physics;     /* FD_ACOUSTIC or FD_TTI (TTI needs ndim == 3) */
+    int32_t nbl;         /* absorbing-layer points added on both sides of each axis */
+    int64_t shape[3];    /* physical points (nx, ny, nz); ny must be 1 in 2D */
+    double spacing[3];   /* (hx, hy, hz) in metres; hy ignored in 2D */
+    double dt;           /* time step in seconds */
+} fd_grid;
+
+/* Device pointers to float32 fields on the padded shape.  They are read only
+ * by fd_setup and may be released once `stream` has passed it. */
+typedef struct fd_model {
+    const float* vel;     /* P velocity v (m/s), v > 0; m = 1/v^2 */
+    const float* eta;     /* damping rate (1/s) of u_tt + eta u_t = v^2 (lap u + q);
+                             NULL = no damping */
+    const float* epsilon; /* TTI: Thomsen epsilon (NULL for acoustic) */
+    const float* delta;   /* TTI: Thomsen delta, 0 <= ... <= epsilon is required */
+    const float* theta;   /* TTI: tilt from the vertical (radians) */
+    const float* phi;     /* TTI: azimuth (radians) */
+} fd_model;
+
+/* A set of sparse points (sources or receivers). */
+typedef struct fd_points {
+    int32_t n;            /* number of points (0 allowed) */
+    const double* coords; /* host [n][ndim] metres, see Conventions */
+    float* data;          /* device [nt][n]: wavelet (sources, read) or traces
+                             (receivers, overwritten) */
+} fd_points;
+
+typedef struct fd_ctx fd_ctx;
+
+/* Bytes of device workspace fd_setup needs for this grid with room for up to
+ * `max_points` sparse points per fd_forward call (sources + receivers).
+ * Pure host computation.  Returns FD_ERR_INVALID_ARG / FD_ERR_UNSUPPORTED for
+ * grids fd_setup would reject. */
+int32_t fd_workspace_bytes(const fd_grid* grid, int32_t max_points, uint64_t* bytes);
+
+/* Validates the grid, derives the per-point coefficients the time loop reads
+ * (dt^2 v^2, eta dt/2 and, for TTI, the Thomsen and rotation factors) into
+ * `workspace` (device, 256-byte aligned, at least fd_workspace_bytes), checks
+ * the model (finite, v > 0, TTI: delta <= epsilon) and the CFL bound of
+ * Eq. (stability) at the model's fastest speed (for TTI the horizontal P
+ * speed v sqrt(1 + 2 epsilon)), and sets the wavefields to zero.  This call
+ * synchronises `stream` once to read the model reduction back.  On success
+ * *out receives a context; the workspace must stay allocated until
+ * fd_destroy. */
+int32_t fd_setup(const fd_grid* grid, const fd_model* model, void* workspace,
+                 uint64_t workspace_bytes, int32_t max_points, void* stream, fd_ctx** out);
+
+/* Runs nt time steps of Algorithm 1: for each step n, the stencil update of
+ * every point (with the damping layer), then the source term q[n] added to
+ * the new level (Algorithm 1, "Add Source"; for TTI into both p and r), then
+ * receivers sampled from the new level into rec->data[n] (TTI: from p).
+ * The point-source amplitude q enters as dt^2 v^2 q / (prod h) / (1 + eta dt/2)
+ * spread over the multilinear corners.  flags & FD_ZERO_STATE starts from
+ * zero; otherwise the run continues from the held state (fd_set_field or a
+ * previous call).  src or rec may be NULL.  Asynchronous on `stream`, except
+ * that new point coordinates are uploaded with one synchronisation. */
+int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_points* rec,
+                   int32_t flags, void* stream);
+
+/* Copy a wavefield level between the context and a dense device array of the
+ * padded shape ([Nz][Ny][Nx] float32).  Asynchronous on `stream`. */
+int32_t fd_get_field(fd_ctx* ctx, int32_t which, float* dst, void* stream);
+int32_t fd_set_field(fd_ctx* ctx, int32_t which, const float* src, void* stream);
+
+/* Host helpers (no device work).
+ * fd_stencil_weights: central weights of order space_order for derivative
+ *   `deriv` (1 or 2) on unit spacing, w[0..r] (w[-j] = w[j] for deriv 2,
+ *   -w[j] for deriv 1), section 4.1.
+ * fd_cfl_dt: largest dt allowed by Eq. (stability) with a1 = 4 for a wave
+ *   speed vmax on this grid. */
+int32_t fd_stencil_weights(int32_t space_order, int32_t deriv, double* w);
+int32_t fd_cfl_dt(const fd_grid* grid, double vmax, double* dt_max);
+
+/* Tuning options (kernel variant / launch shape), mainly for benchmarking.
+ * FD_OPT_KERNEL: 0 = tiled (default), 1 = direct global-memory kernel.
+ * FD_OPT_ZCHUNK: z-planes per thread block of the tiled 3D kernels (0 = auto).
+ * FD_OPT_VY: rows per thread of the tiled acoustic kernel (0 = auto). */
+#define FD_OPT_KERNEL 1
+#define FD_OPT_ZCHUNK 2
+#define FD_OPT_VY 3
+int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value);
+
+/* Frees the host context (not the workspace). NULL is accepted. */
+int32_t fd_destroy(fd_ctx* ctx);
+
+/* Static description of a status code. */
+const char* fd_strerror(int32_t status);
+
+/* Message for the last failure on this context ("" if none). */
+const char* fd_last_error(const fd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FD_H */

@@ -1,0 +1,206 @@
+"""ctypes binding of libfd (include/fd.h): the same entry points, argument
+marshalling only.  Every step of the solver runs in the HIP kernels of
+libfd.so; nothing here computes on the CPU.  Loading fails loudly when the
+library has not been built."""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import numpy as np
+
+_LIBPATH = Path(__file__).resolve().parent / "libfd.so"
+
+FD_OK = 0
+FD_ERR_INVALID_ARG = 1
+FD_ERR_UNSTABLE_DT = 2
+FD_ERR_UNSUPPORTED = 3
+FD_ERR_WORKSPACE = 4
+FD_ERR_DEVICE = 5
+FD_ERR_NONFINITE = 6
+
+FD_ACOUSTIC = 0
+FD_TTI = 1
+
+FD_FIELD_PREV = 0
+FD_FIELD_CUR = 1
+FD_FIELD_R_PREV = 2
+FD_FIELD_R_CUR = 3
+
+FD_ZERO_STATE = 1
+FD_MAX_SPACE_ORDER = 16
+
+FD_OPT_KERNEL = 1
+FD_OPT_ZCHUNK = 2
+FD_OPT_VY = 3
+
+EXPORTS = (
+    "fd_workspace_bytes", "fd_setup", "fd_forward", "fd_get_field", "fd_set_field",
+    "fd_stencil_weights", "fd_cfl_dt", "fd_set_option", "fd_destroy", "fd_strerror",
+    "fd_last_error",
+)
+
+
+class FdGrid(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("space_order", ctypes.c_int32),
+        ("physics", ctypes.c_int32),
+        ("nbl", ctypes.c_int32),
+        ("shape", ctypes.c_int64 * 3),
+        ("spacing", ctypes.c_double * 3),
+        ("dt", ctypes.c_double),
+    ]
+
+
+class FdModel(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("vel", "eta", "epsilon", "delta", "theta", "phi")]
+
+
+class FdPoints(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("coords", ctypes.POINTER(ctypes.c_double)),
+        ("data", ctypes.c_void_p),
+    ]
+
+
+class FdError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str = ""):
+        self.code = code
+        msg = f"{where}: {fd_strerror(code)} (status {code})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+_lib_handle = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libfd.so; raises if it has not been built."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not _LIBPATH.exists():
+            raise RuntimeError(f"{_LIBPATH} is missing: build it with __graft_entry__.build() "
+                               "(python -m paper_1608_03984_amd._build)")
+        L = ctypes.CDLL(str(_LIBPATH))
+        i32, u64p, vp = ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p
+        gp, mp, pp = ctypes.POINTER(FdGrid), ctypes.POINTER(FdModel), ctypes.POINTER(FdPoints)
+        sig = {
+            "fd_workspace_bytes": (i32, [gp, i32, u64p]),
+            "fd_setup": (i32, [gp, mp, vp, ctypes.c_uint64, i32, vp, ctypes.POINTER(vp)]),
+            "fd_forward": (i32, [vp, i32, pp, pp, i32, vp]),
+            "fd_get_field": (i32, [vp, i32, vp, vp]),
+            "fd_set_field": (i32, [vp, i32, vp, vp]),
+            "fd_stencil_weights": (i32, [i32, i32, ctypes.POINTER(ctypes.c_double)]),
+            "fd_cfl_dt": (i32, [gp, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
+            "fd_set_option": (i32, [vp, i32, ctypes.c_int64]),
+            "fd_destroy": (i32, [vp]),
+            "fd_strerror": (ctypes.c_char_p, [i32]),
+            "fd_last_error": (ctypes.c_char_p, [vp]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib_handle = L
+    return _lib_handle
+
+
+def make_grid(ndim, shape, spacing, nbl, space_order, dt, physics=FD_ACOUSTIC) -> FdGrid:
+    """fd_grid from Python values; shape/spacing are (x, y, z) (ny = 1 in 2D)."""
+    g = FdGrid()
+    g.ndim = int(ndim)
+    g.space_order = int(space_order)
+    g.physics = int(physics)
+    g.nbl = int(nbl)
+    for a in range(3):
+        g.shape[a] = int(shape[a])
+        g.spacing[a] = float(spacing[a])
+    g.dt = float(dt)
+    return g
+
+
+def _check(code: int, where: str, ctx=None):
+    if code != FD_OK:
+        detail = fd_last_error(ctx) if ctx else ""
+        raise FdError(code, where, detail)
+
+
+def fd_strerror(code: int) -> str:
+    return lib().fd_strerror(int(code)).decode()
+
+
+def fd_last_error(ctx) -> str:
+    return lib().fd_last_error(ctx).decode() if ctx else ""
+
+
+def fd_workspace_bytes(grid: FdGrid, max_points: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check(lib().fd_workspace_bytes(ctypes.byref(grid), int(max_points), ctypes.byref(out)),
+           "fd_workspace_bytes")
+    return int(out.value)
+
+
+def fd_setup(grid: FdGrid, model: FdModel, workspace_ptr: int, workspace_bytes: int,
+             max_points: int, stream: int):
+    ctx = ctypes.c_void_p(0)
+    _check(lib().fd_setup(ctypes.byref(grid), ctypes.byref(model), ctypes.c_void_p(workspace_ptr),
+                          int(workspace_bytes), int(max_points), ctypes.c_void_p(stream),
+                          ctypes.byref(ctx)), "fd_setup")
+    return ctx
+
+
+def _points(coords, data_ptr):
+    if coords is None:
+        return None, None
+    c = np.ascontiguousarray(coords, dtype=np.float64)
+    p = FdPoints()
+    p.n = int(c.shape[0]) if c.size else 0
+    p.coords = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.data = ctypes.c_void_p(int(data_ptr) if data_ptr else 0)
+    return p, c
+
+
+def fd_forward(ctx, nt: int, src_coords, src_data_ptr, rec_coords, rec_data_ptr, flags: int,
+               stream: int):
+    sp, keep_s = _points(src_coords, src_data_ptr)
+    rp, keep_r = _points(rec_coords, rec_data_ptr)
+    code = lib().fd_forward(ctx, int(nt), ctypes.byref(sp) if sp else None,
+                            ctypes.byref(rp) if rp else None, int(flags), ctypes.c_void_p(stream))
+    del keep_s, keep_r
+    _check(code, "fd_forward", ctx)
+
+
+def fd_get_field(ctx, which: int, dst_ptr: int, stream: int):
+    _check(lib().fd_get_field(ctx, int(which), ctypes.c_void_p(dst_ptr), ctypes.c_void_p(stream)),
+           "fd_get_field", ctx)
+
+
+def fd_set_field(ctx, which: int, src_ptr: int, stream: int):
+    _check(lib().fd_set_field(ctx, int(which), ctypes.c_void_p(src_ptr), ctypes.c_void_p(stream)),
+           "fd_set_field", ctx)
+
+
+def fd_set_option(ctx, option: int, value: int):
+    _check(lib().fd_set_option(ctx, int(option), int(value)), "fd_set_option", ctx)
+
+
+def fd_destroy(ctx):
+    if ctx:
+        lib().fd_destroy(ctx)
+
+
+def fd_stencil_weights(space_order: int, deriv: int) -> np.ndarray:
+    w = np.zeros(space_order // 2 + 1)
+    _check(lib().fd_stencil_weights(int(space_order), int(deriv),
+                                    w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "fd_stencil_weights")
+    return w
+
+
+def fd_cfl_dt(grid: FdGrid, vmax: float) -> float:
+    out = ctypes.c_double(0.0)
+    _check(lib().fd_cfl_dt(ctypes.byref(grid), float(vmax), ctypes.byref(out)), "fd_cfl_dt")
+    return float(out.value)

@@ -1,0 +1,635 @@
+// fd_abi.cpp -- host runtime and C ABI of libfd (see include/fd.h).
+//
+// Validates problems, derives stencil weights (Fornberg's recursion, in
+// double, rounded once to float), lays the volumes out in the caller's
+// workspace, and enqueues the per-step launch sequence of Algorithm 1:
+// stencil update -> source injection -> receiver sampling -> level swap.
+#include "fd.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fd_internal.h"
+
+using fd::Layout;
+using fd::SparsePoint;
+
+struct fd_ctx {
+    fd_grid g;
+    int radius;
+    Layout L;
+    bool damping;
+    bool tti;
+    int32_t max_points;
+    // workspace regions
+    uint32_t* reduce;
+    float* A;
+    float* sig;
+    float* e;
+    float* d;
+    float* c[6];
+    float* u[2];  // acoustic u / TTI p: two levels
+    float* r[2];  // TTI r: two levels
+    uint8_t* dflag;
+    SparsePoint* pts;
+    int cur;  // index of the level holding u^n in u[]/r[]
+    // derived stencil coefficients (float, already divided by h or h^2)
+    float w2[3][fd::kMaxRadius + 1];
+    float w1[3][fd::kMaxRadius + 1];
+    // launch configuration
+    int variant;
+    int vy;
+    int zchunk_opt;
+    int tile_y;
+    bool flags_stale;
+    // cached sparse-point coordinates of the last upload
+    std::vector<double> src_coords, rec_coords;
+    int nsrc_dev, nrec_dev;
+    std::string err;
+};
+
+namespace {
+
+int32_t fail(fd_ctx* ctx, int32_t code, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int32_t hip_fail(fd_ctx* ctx, hipError_t e, const char* where) {
+    if (ctx) ctx->err = std::string(where) + ": " + hipGetErrorString(e);
+    return FD_ERR_DEVICE;
+}
+
+// Fornberg (1988) recursion for finite-difference weights at z over nodes
+// x[0..n-1], derivatives 0..m.  c[j*(m+1)+k] = weight of node j for d^k/dx^k.
+void fornberg(double z, const double* x, int n, int m, double* c) {
+    for (int i = 0; i < n * (m + 1); ++i) c[i] = 0.0;
+    double c1 = 1.0, c4 = x[0] - z;
+    c[0] = 1.0;
+    for (int i = 1; i < n; ++i) {
+        const int mn = i < m ? i : m;
+        double c2 = 1.0;
+        const double c5 = c4;
+        c4 = x[i] - z;
+        for (int j = 0; j < i; ++j) {
+            const double c3 = x[i] - x[j];
+            c2 *= c3;
+            if (j == i - 1) {
+                for (int k = mn; k >= 1; --k)
+                    c[i * (m + 1) + k] =
+                        c1 * (k * c[(i - 1) * (m + 1) + k - 1] - c5 * c[(i - 1) * (m + 1) + k]) / c2;
+                c[i * (m + 1)] = -c1 * c5 * c[(i - 1) * (m + 1)] / c2;
+            }
+            for (int k = mn; k >= 1; --k)
+                c[j * (m + 1) + k] = (c4 * c[j * (m + 1) + k] - k * c[j * (m + 1) + k - 1]) / c3;
+            c[j * (m + 1)] = c4 * c[j * (m + 1)] / c3;
+        }
+        c1 = c2;
+    }
+}
+
+// Central weights w[0..r] of the derivative `deriv` on unit spacing, nodes
+// ordered 0, -1, +1, -2, +2, ... so that the recursion adds symmetric pairs.
+bool central_weights(int so, int deriv, double* w) {
+    if (so < 2 || so > 2 * fd::kMaxRadius || so % 2 || (deriv != 1 && deriv != 2)) return false;
+    const int r = so / 2, n = 2 * r + 1;
+    double x[2 * fd::kMaxRadius + 1];
+    double c[(2 * fd::kMaxRadius + 1) * 3];
+    x[0] = 0.0;
+    for (int j = 1; j <= r; ++j) {
+        x[2 * j - 1] = -j;
+        x[2 * j] = j;
+    }
+    fornberg(0.0, x, n, 2, c);
+    w[0] = c[0 * 3 + deriv];
+    for (int j = 1; j <= r; ++j) {
+        const double wp = c[(2 * j) * 3 + deriv], wm = c[(2 * j - 1) * 3 + deriv];
+        // symmetrise against rounding: the exact weights are (anti)symmetric
+        w[j] = deriv == 2 ? 0.5 * (wp + wm) : 0.5 * (wp - wm);
+    }
+    if (deriv == 1) w[0] = 0.0;
+    return true;
+}
+
+int32_t validate_grid(const fd_grid* g, std::string& msg) {
+    if (!g) return msg = "grid is NULL", FD_ERR_INVALID_ARG;
+    if (g->ndim != 2 && g->ndim != 3) return msg = "ndim must be 2 or 3", FD_ERR_INVALID_ARG;
+    if (g->space_order < 2 || g->space_order % 2)
+        return msg = "space_order must be even and >= 2", FD_ERR_INVALID_ARG;
+    if (g->space_order > FD_MAX_SPACE_ORDER)
+        return msg = "space_order above 16 is not built", FD_ERR_UNSUPPORTED;
+    if (g->physics != FD_ACOUSTIC && g->physics != FD_TTI)
+        return msg = "unknown physics", FD_ERR_INVALID_ARG;
+    if (g->physics == FD_TTI && g->ndim != 3)
+        return msg = "TTI is built for 3D grids only", FD_ERR_UNSUPPORTED;
+    if (g->nbl < 0 || g->nbl > (1 << 20)) return msg = "nbl out of range", FD_ERR_INVALID_ARG;
+    for (int a = 0; a < 3; ++a)
+        if (g->shape[a] < 1 || g->shape[a] > (1 << 20))
+            return msg = "shape out of range", FD_ERR_INVALID_ARG;
+    if (g->ndim == 2 && g->shape[1] != 1) return msg = "2D grids need shape[1] == 1", FD_ERR_INVALID_ARG;
+    for (int a = 0; a < 3; ++a) {
+        if (g->ndim == 2 && a == 1) continue;
+        if (!(g->spacing[a] > 0.0) || !std::isfinite(g->spacing[a]))
+            return msg = "spacing must be positive and finite", FD_ERR_INVALID_ARG;
+    }
+    if (!(g->dt > 0.0) || !std::isfinite(g->dt)) return msg = "dt must be positive", FD_ERR_INVALID_ARG;
+    return FD_OK;
+}
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+Layout make_layout(const fd_grid* g) {
+    Layout L;
+    const int64_t nb = g->nbl;
+    L.nx = (int32_t)(g->shape[0] + 2 * nb);
+    L.ny = g->ndim == 3 ? (int32_t)(g->shape[1] + 2 * nb) : 1;
+    L.nz = (int32_t)(g->shape[2] + 2 * nb);
+    // x: 32 zero columns before the interior (rows start on a 128-byte line),
+    // the interior rounded up to whole 64-wide tiles, 32 zero columns after.
+    L.pitch = (int32_t)(fd::kGhostX + round_up(L.nx, fd::kTileX) + 32);
+    // y: kGhostYZ zero rows each side of the interior rounded to 64 rows (so
+    // any tile height dividing 64 stays inside); 2D has a single row.
+    L.rows = g->ndim == 3 ? (int32_t)(fd::kGhostYZ + round_up(L.ny, 64) + fd::kGhostYZ) : 1;
+    L.planes = L.nz + 2 * fd::kGhostYZ;
+    L.plane = (int64_t)L.pitch * L.rows;
+    L.origin = (int64_t)fd::kGhostYZ * L.plane + (g->ndim == 3 ? (int64_t)fd::kGhostYZ * L.pitch : 0) +
+               fd::kGhostX;
+    L.volume = round_up(L.plane * L.planes, 64);
+    return L;
+}
+
+struct Carve {
+    uint64_t off = 0;
+    uint64_t take(uint64_t bytes) {
+        const uint64_t o = off;
+        off = (uint64_t)round_up((int64_t)(off + bytes), 256);
+        return o;
+    }
+};
+
+int min_tile_y() { return 8; }
+
+// Workspace plan; when base is non-null the pointers are filled in.
+uint64_t plan_workspace(const fd_grid* g, const Layout& L, int32_t max_points, fd_ctx* ctx,
+                        char* base) {
+    Carve cv;
+    const uint64_t vol = (uint64_t)L.volume * sizeof(float);
+    const bool tti = g->physics == FD_TTI;
+    const uint64_t o_red = cv.take(256);
+    const uint64_t o_A = cv.take(vol);
+    const uint64_t o_sig = cv.take(vol);
+    uint64_t o_e = 0, o_d = 0, o_c[6] = {0, 0, 0, 0, 0, 0}, o_r[2] = {0, 0};
+    if (tti) {
+        o_e = cv.take(vol);
+        o_d = cv.take(vol);
+        for (int k = 0; k < 6; ++k) o_c[k] = cv.take(vol);
+    }
+    const uint64_t o_u0 = cv.take(vol);
+    const uint64_t o_u1 = cv.take(vol);
+    if (tti) {
+        o_r[0] = cv.take(vol);
+        o_r[1] = cv.take(vol);
+    }
+    const int64_t ntx = (L.nx + fd::kTileX - 1) / fd::kTileX;
+    const int64_t nty = (L.ny + min_tile_y() - 1) / min_tile_y();
+    const uint64_t o_flag = cv.take((uint64_t)(ntx * nty * L.nz));
+    const uint64_t o_pts = cv.take((uint64_t)(max_points > 0 ? max_points : 1) * sizeof(SparsePoint));
+    if (ctx && base) {
+        ctx->reduce = reinterpret_cast<uint32_t*>(base + o_red);
+        ctx->A = reinterpret_cast<float*>(base + o_A);
+        ctx->sig = reinterpret_cast<float*>(base + o_sig);
+        ctx->e = tti ? reinterpret_cast<float*>(base + o_e) : nullptr;
+        ctx->d = tti ? reinterpret_cast<float*>(base + o_d) : nullptr;
+        for (int k = 0; k < 6; ++k) ctx->c[k] = tti ? reinterpret_cast<float*>(base + o_c[k]) : nullptr;
+        ctx->u[0] = reinterpret_cast<float*>(base + o_u0);
+        ctx->u[1] = reinterpret_cast<float*>(base + o_u1);
+        ctx->r[0] = tti ? reinterpret_cast<float*>(base + o_r[0]) : nullptr;
+        ctx->r[1] = tti ? reinterpret_cast<float*>(base + o_r[1]) : nullptr;
+        ctx->dflag = reinterpret_cast<uint8_t*>(base + o_flag);
+        ctx->pts = reinterpret_cast<SparsePoint*>(base + o_pts);
+    }
+    return cv.off;
+}
+
+// S = |w0| + 2 sum |w_j| of the second-derivative stencil (unit spacing).
+double abs_weight_sum(int so) {
+    double w[fd::kMaxRadius + 1];
+    central_weights(so, 2, w);
+    double s = std::fabs(w[0]);
+    for (int j = 1; j <= so / 2; ++j) s += 2.0 * std::fabs(w[j]);
+    return s;
+}
+
+double cfl_dt(const fd_grid* g, double vmax) {
+    const double S = abs_weight_sum(g->space_order);
+    double den = S / (g->spacing[0] * g->spacing[0]) + S / (g->spacing[2] * g->spacing[2]);
+    if (g->ndim == 3) den += S / (g->spacing[1] * g->spacing[1]);
+    return std::sqrt(4.0 / den) / vmax;
+}
+
+// Host preprocessing of one sparse point (see fd.h, Conventions).
+bool locate(const fd_ctx* ctx, const double* c, SparsePoint* P) {
+    const fd_grid& g = ctx->g;
+    const Layout& L = ctx->L;
+    int64_t idx[3] = {0, 0, 0};
+    double frac[3] = {0.0, 0.0, 0.0};
+    const int32_t n[3] = {L.nx, L.ny, L.nz};
+    for (int a = 0; a < 3; ++a) {
+        if (g.ndim == 2 && a == 1) continue;
+        const double coord = g.ndim == 2 ? c[a == 0 ? 0 : 1] : c[a];
+        if (!std::isfinite(coord)) return false;
+        const double gi = coord / g.spacing[a] + (double)g.nbl;
+        if (!(gi >= 0.0) || gi > (double)(n[a] - 1) || n[a] < 2) return false;
+        int64_t i = (int64_t)std::floor(gi);
+        if (i > n[a] - 2) i = n[a] - 2;
+        idx[a] = i;
+        frac[a] = gi - (double)i;
+    }
+    P->base = L.origin + idx[2] * L.plane + idx[1] * L.pitch + idx[0];
+    P->fx = (float)frac[0];
+    P->fy = (float)frac[1];
+    P->fz = (float)frac[2];
+    P->pad = 0;
+    return true;
+}
+
+int default_vy(int radius) { return radius <= 4 ? 4 : 2; }
+
+void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, fd::AcousticStep* a,
+               fd::TTIStep* t) {
+    const Layout& L = ctx->L;
+    const int ntx = (L.nx + fd::kTileX - 1) / fd::kTileX;
+    const int nty = (L.ny + tile_y - 1) / tile_y;
+    int zc = zchunk_opt;
+    if (zc <= 0) {
+        const int64_t xy = (int64_t)ntx * nty;
+        const int64_t target = (2048 + xy - 1) / xy;
+        zc = (int)((L.nz + target - 1) / target);
+        if (zc < 4 * radius) zc = 4 * radius;
+    }
+    if (zc > L.nz) zc = L.nz;
+    const int nzc = (L.nz + zc - 1) / zc;
+    const int ntiles = ntx * nty * nzc;
+    const int nblocks = (int)round_up(ntiles, 8);
+    if (a) {
+        a->ntx = ntx; a->nty = nty; a->nzc = nzc; a->zchunk = zc;
+        a->ntiles = ntiles; a->nblocks = nblocks;
+    }
+    if (t) {
+        t->ntx = ntx; t->nty = nty; t->nzc = nzc; t->zchunk = zc;
+        t->ntiles = ntiles; t->nblocks = nblocks;
+    }
+}
+
+hipError_t refresh_flags(fd_ctx* ctx, hipStream_t s) {
+    if (!ctx->damping || ctx->g.ndim != 3) return hipSuccess;
+    const Layout& L = ctx->L;
+    const int ntx = (L.nx + fd::kTileX - 1) / fd::kTileX;
+    const int nty = (L.ny + ctx->tile_y - 1) / ctx->tile_y;
+    return fd::launch_damping_flags(ctx->sig, ctx->dflag, L, ctx->tile_y, ntx, nty, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fd_stencil_weights(int32_t space_order, int32_t deriv, double* w) {
+    if (!w) return FD_ERR_INVALID_ARG;
+    if (space_order > FD_MAX_SPACE_ORDER && space_order % 2 == 0) return FD_ERR_UNSUPPORTED;
+    return central_weights(space_order, deriv, w) ? FD_OK : FD_ERR_INVALID_ARG;
+}
+
+int32_t fd_cfl_dt(const fd_grid* grid, double vmax, double* dt_max) {
+    std::string msg;
+    if (!dt_max || !(vmax > 0.0)) return FD_ERR_INVALID_ARG;
+    fd_grid g = *grid;
+    g.dt = 1.0;  // dt itself is not validated here
+    const int32_t rc = validate_grid(&g, msg);
+    if (rc != FD_OK) return rc;
+    *dt_max = cfl_dt(grid, vmax);
+    return FD_OK;
+}
+
+int32_t fd_workspace_bytes(const fd_grid* grid, int32_t max_points, uint64_t* bytes) {
+    std::string msg;
+    if (!bytes || max_points < 0) return FD_ERR_INVALID_ARG;
+    const int32_t rc = validate_grid(grid, msg);
+    if (rc != FD_OK) return rc;
+    const Layout L = make_layout(grid);
+    *bytes = plan_workspace(grid, L, max_points, nullptr, nullptr);
+    return FD_OK;
+}
+
+int32_t fd_setup(const fd_grid* grid, const fd_model* model, void* workspace,
+                 uint64_t workspace_bytes, int32_t max_points, void* stream, fd_ctx** out) {
+    std::string msg;
+    if (!out) return FD_ERR_INVALID_ARG;
+    *out = nullptr;
+    int32_t rc = validate_grid(grid, msg);
+    if (rc != FD_OK) return rc;
+    if (!model || !model->vel || max_points < 0 || !workspace) return FD_ERR_INVALID_ARG;
+    const bool tti = grid->physics == FD_TTI;
+    if (tti && (!model->epsilon || !model->delta || !model->theta || !model->phi))
+        return FD_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return FD_ERR_WORKSPACE;
+    const Layout L = make_layout(grid);
+    const uint64_t need = plan_workspace(grid, L, max_points, nullptr, nullptr);
+    if (workspace_bytes < need) return FD_ERR_WORKSPACE;
+
+    fd_ctx* ctx = new (std::nothrow) fd_ctx();
+    if (!ctx) return FD_ERR_INVALID_ARG;
+    ctx->g = *grid;
+    ctx->radius = grid->space_order / 2;
+    ctx->L = L;
+    ctx->tti = tti;
+    ctx->damping = model->eta != nullptr;
+    ctx->max_points = max_points;
+    ctx->cur = 1;
+    ctx->variant = 0;
+    ctx->vy = default_vy(ctx->radius);
+    ctx->zchunk_opt = 0;
+    ctx->tile_y = tti ? fd::tti_tile_y(ctx->radius) : fd::acoustic_tile_y(ctx->radius, ctx->vy);
+    ctx->nsrc_dev = ctx->nrec_dev = -1;
+    ctx->flags_stale = false;
+    plan_workspace(grid, L, max_points, ctx, static_cast<char*>(workspace));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    // zero everything (ghost rings must be zero), then derive coefficients
+    hipError_t he = fd::launch_fill_zero(static_cast<float*>(workspace),
+                                         (int64_t)(need / sizeof(float)), s);
+    if (he != hipSuccess) {
+        hip_fail(ctx, he, "fill");
+        delete ctx;
+        return FD_ERR_DEVICE;
+    }
+    fd::SetupArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.vel = model->vel;
+    sa.eta = model->eta;
+    sa.eps = model->epsilon;
+    sa.delta = model->delta;
+    sa.theta = model->theta;
+    sa.phi = model->phi;
+    sa.dt = (float)grid->dt;
+    sa.A = ctx->A;
+    sa.sig = ctx->damping ? ctx->sig : nullptr;
+    sa.e = ctx->e;
+    sa.d = ctx->d;
+    for (int k = 0; k < 6; ++k) sa.c[k] = ctx->c[k];
+    sa.reduce = ctx->reduce;
+    sa.L = L;
+    he = fd::launch_setup(sa, s);
+    if (he == hipSuccess) he = refresh_flags(ctx, s);
+    uint32_t red[4] = {0, 0, 0, 0};
+    if (he == hipSuccess) he = hipMemcpyAsync(red, ctx->reduce, sizeof(red), hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) {
+        hip_fail(ctx, he, "setup");
+        delete ctx;
+        return FD_ERR_DEVICE;
+    }
+    if (red[1]) {
+        delete ctx;
+        return FD_ERR_NONFINITE;
+    }
+    if (red[2]) {
+        delete ctx;
+        return FD_ERR_INVALID_ARG;  // delta > epsilon: unstable pseudo-acoustic mode
+    }
+    float vmax;
+    std::memcpy(&vmax, &red[0], sizeof(float));
+    if (!(vmax > 0.f)) {
+        delete ctx;
+        return FD_ERR_NONFINITE;
+    }
+    if (grid->dt > cfl_dt(grid, (double)vmax) * (1.0 + 1e-12)) {
+        delete ctx;
+        return FD_ERR_UNSTABLE_DT;
+    }
+    // stencil weights / h or h^2, rounded once to float
+    double w2[fd::kMaxRadius + 1], w1[fd::kMaxRadius + 1];
+    central_weights(grid->space_order, 2, w2);
+    central_weights(grid->space_order, 1, w1);
+    for (int a = 0; a < 3; ++a) {
+        const bool used = !(grid->ndim == 2 && a == 1);
+        const double h = grid->spacing[a];
+        for (int j = 0; j <= fd::kMaxRadius; ++j) {
+            ctx->w2[a][j] = (used && j <= ctx->radius) ? (float)(w2[j] / (h * h)) : 0.f;
+            ctx->w1[a][j] = (used && j <= ctx->radius) ? (float)(w1[j] / h) : 0.f;
+        }
+    }
+    *out = ctx;
+    return FD_OK;
+}
+
+int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value) {
+    if (!ctx) return FD_ERR_INVALID_ARG;
+    switch (option) {
+        case FD_OPT_KERNEL:
+            if (value != 0 && value != 1) return fail(ctx, FD_ERR_INVALID_ARG, "kernel variant 0 or 1");
+            ctx->variant = (int)value;
+            return FD_OK;
+        case FD_OPT_ZCHUNK:
+            if (value < 0 || value > (1 << 20)) return fail(ctx, FD_ERR_INVALID_ARG, "zchunk range");
+            ctx->zchunk_opt = (int)value;
+            return FD_OK;
+        case FD_OPT_VY: {
+            if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "VY applies to the acoustic kernel");
+            const int v = value == 0 ? default_vy(ctx->radius) : (int)value;
+            if (v != 2 && v != 4 && v != 8) return fail(ctx, FD_ERR_INVALID_ARG, "VY must be 2, 4 or 8");
+            ctx->vy = v;
+            ctx->tile_y = fd::acoustic_tile_y(ctx->radius, v);
+            ctx->flags_stale = true;  // rebuilt on the caller's stream by fd_forward
+            return FD_OK;
+        }
+        default: return fail(ctx, FD_ERR_INVALID_ARG, "unknown option");
+    }
+}
+
+int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_points* rec,
+                   int32_t flags, void* stream) {
+    if (!ctx) return FD_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
+    const int nsrc = src ? src->n : 0, nrec = rec ? rec->n : 0;
+    if (nsrc < 0 || nrec < 0) return fail(ctx, FD_ERR_INVALID_ARG, "negative point count");
+    if ((int64_t)nsrc + nrec > ctx->max_points)
+        return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
+    if (nsrc > 0 && (!src->coords || (!src->data && nt > 0)))
+        return fail(ctx, FD_ERR_INVALID_ARG, "source coords/data missing");
+    if (nrec > 0 && (!rec->coords || (!rec->data && nt > 0)))
+        return fail(ctx, FD_ERR_INVALID_ARG, "receiver coords/data missing");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nd = ctx->g.ndim;
+
+    // sparse tables: rebuild and upload only when the coordinates change
+    std::vector<double> sc(src && nsrc ? src->coords : nullptr,
+                           src && nsrc ? src->coords + (size_t)nsrc * nd : nullptr);
+    std::vector<double> rcv(rec && nrec ? rec->coords : nullptr,
+                            rec && nrec ? rec->coords + (size_t)nrec * nd : nullptr);
+    if (nsrc != ctx->nsrc_dev || nrec != ctx->nrec_dev || sc != ctx->src_coords ||
+        rcv != ctx->rec_coords) {
+        std::vector<SparsePoint> host((size_t)nsrc + nrec);
+        for (int i = 0; i < nsrc; ++i)
+            if (!locate(ctx, &sc[(size_t)i * nd], &host[i]))
+                return fail(ctx, FD_ERR_INVALID_ARG, "source " + std::to_string(i) + " outside the grid");
+        for (int i = 0; i < nrec; ++i)
+            if (!locate(ctx, &rcv[(size_t)i * nd], &host[(size_t)nsrc + i]))
+                return fail(ctx, FD_ERR_INVALID_ARG, "receiver " + std::to_string(i) + " outside the grid");
+        if (!host.empty()) {
+            hipError_t he = hipMemcpyAsync(ctx->pts, host.data(), host.size() * sizeof(SparsePoint),
+                                           hipMemcpyHostToDevice, s);
+            if (he == hipSuccess) he = hipStreamSynchronize(s);  // host table goes out of scope
+            if (he != hipSuccess) return hip_fail(ctx, he, "point upload");
+        }
+        ctx->src_coords.swap(sc);
+        ctx->rec_coords.swap(rcv);
+        ctx->nsrc_dev = nsrc;
+        ctx->nrec_dev = nrec;
+    }
+
+    hipError_t he = hipSuccess;
+    if (ctx->flags_stale) {
+        he = refresh_flags(ctx, s);
+        if (he != hipSuccess) return hip_fail(ctx, he, "damping flags");
+        ctx->flags_stale = false;
+    }
+    if (flags & FD_ZERO_STATE) {
+        for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume, s);
+        if (ctx->tti)
+            for (int k = 0; k < 2 && he == hipSuccess; ++k)
+                he = fd::launch_fill_zero(ctx->r[k], ctx->L.volume, s);
+        if (he != hipSuccess) return hip_fail(ctx, he, "zero state");
+    }
+    const double hp = nd == 3 ? ctx->g.spacing[0] * ctx->g.spacing[1] * ctx->g.spacing[2]
+                              : ctx->g.spacing[0] * ctx->g.spacing[2];
+    const float scale = (float)(1.0 / hp);
+    const SparsePoint* spts = ctx->pts;
+    const SparsePoint* rpts = ctx->pts + nsrc;
+    const float* sig = ctx->damping ? ctx->sig : nullptr;
+    const uint8_t* dflag = (ctx->damping && nd == 3) ? ctx->dflag : nullptr;
+
+    if (!ctx->tti) {
+        fd::AcousticStep p;
+        std::memset(&p, 0, sizeof(p));
+        p.A = ctx->A;
+        p.sig = sig;
+        p.dflag = dflag;
+        p.L = ctx->L;
+        double c0 = 0.0;
+        for (int a = 0; a < 3; ++a) c0 += ctx->w2[a][0];
+        p.c0 = (float)c0;
+        for (int j = 0; j <= fd::kMaxRadius; ++j) {
+            p.cx[j] = ctx->w2[0][j];
+            p.cy[j] = ctx->w2[1][j];
+            p.cz[j] = ctx->w2[2][j];
+        }
+        tile_grid(ctx, ctx->tile_y, ctx->zchunk_opt, ctx->radius, &p, nullptr);
+        for (int n = 0; n < nt; ++n) {
+            float* un = ctx->u[1 - ctx->cur];  // holds u^{n-1}, receives u^{n+1}
+            p.uc = ctx->u[ctx->cur];
+            p.up = un;
+            he = fd::launch_acoustic(p, nd, ctx->radius, ctx->variant, ctx->vy, s);
+            if (he == hipSuccess && nsrc)
+                he = fd::launch_inject(un, ctx->A, sig, spts, nsrc, src->data + (size_t)n * nsrc,
+                                       scale, ctx->L, nd, s);
+            if (he == hipSuccess && nrec)
+                he = fd::launch_record(un, rpts, nrec, rec->data + (size_t)n * nrec, ctx->L, nd, s);
+            if (he != hipSuccess) return hip_fail(ctx, he, "step");
+            ctx->cur = 1 - ctx->cur;
+        }
+    } else {
+        fd::TTIStep p;
+        std::memset(&p, 0, sizeof(p));
+        p.A = ctx->A;
+        p.sig = sig;
+        p.dflag = dflag;
+        p.e = ctx->e;
+        p.d = ctx->d;
+        for (int k = 0; k < 6; ++k) p.c[k] = ctx->c[k];
+        p.L = ctx->L;
+        for (int j = 0; j <= fd::kMaxRadius; ++j) {
+            p.w2x[j] = ctx->w2[0][j];
+            p.w2y[j] = ctx->w2[1][j];
+            p.w2z[j] = ctx->w2[2][j];
+            p.w1x[j] = ctx->w1[0][j];
+            p.w1y[j] = ctx->w1[1][j];
+            p.w1z[j] = ctx->w1[2][j];
+        }
+        tile_grid(ctx, ctx->tile_y, ctx->zchunk_opt, ctx->radius, nullptr, &p);
+        for (int n = 0; n < nt; ++n) {
+            float* pn = ctx->u[1 - ctx->cur];
+            float* rn = ctx->r[1 - ctx->cur];
+            p.pc = ctx->u[ctx->cur];
+            p.rc = ctx->r[ctx->cur];
+            p.pp = pn;
+            p.rp = rn;
+            he = fd::launch_tti(p, ctx->radius, ctx->variant, s);
+            if (he == hipSuccess && nsrc) {
+                const float* q = src->data + (size_t)n * nsrc;
+                he = fd::launch_inject(pn, ctx->A, sig, spts, nsrc, q, scale, ctx->L, 3, s);
+                if (he == hipSuccess)
+                    he = fd::launch_inject(rn, ctx->A, sig, spts, nsrc, q, scale, ctx->L, 3, s);
+            }
+            if (he == hipSuccess && nrec)
+                he = fd::launch_record(pn, rpts, nrec, rec->data + (size_t)n * nrec, ctx->L, 3, s);
+            if (he != hipSuccess) return hip_fail(ctx, he, "step");
+            ctx->cur = 1 - ctx->cur;
+        }
+    }
+    return FD_OK;
+}
+
+static float* field_ptr(fd_ctx* ctx, int32_t which) {
+    switch (which) {
+        case FD_FIELD_PREV: return ctx->u[1 - ctx->cur];
+        case FD_FIELD_CUR: return ctx->u[ctx->cur];
+        case FD_FIELD_R_PREV: return ctx->tti ? ctx->r[1 - ctx->cur] : nullptr;
+        case FD_FIELD_R_CUR: return ctx->tti ? ctx->r[ctx->cur] : nullptr;
+        default: return nullptr;
+    }
+}
+
+int32_t fd_get_field(fd_ctx* ctx, int32_t which, float* dst, void* stream) {
+    if (!ctx) return FD_ERR_INVALID_ARG;
+    float* f = field_ptr(ctx, which);
+    if (!f || !dst) return fail(ctx, FD_ERR_INVALID_ARG, "bad field selector or pointer");
+    const hipError_t he = fd::launch_pack(f, dst, ctx->L, static_cast<hipStream_t>(stream));
+    return he == hipSuccess ? FD_OK : hip_fail(ctx, he, "get_field");
+}
+
+int32_t fd_set_field(fd_ctx* ctx, int32_t which, const float* src, void* stream) {
+    if (!ctx) return FD_ERR_INVALID_ARG;
+    float* f = field_ptr(ctx, which);
+    if (!f || !src) return fail(ctx, FD_ERR_INVALID_ARG, "bad field selector or pointer");
+    const hipError_t he = fd::launch_unpack(src, f, ctx->L, static_cast<hipStream_t>(stream));
+    return he == hipSuccess ? FD_OK : hip_fail(ctx, he, "set_field");
+}
+
+int32_t fd_destroy(fd_ctx* ctx) {
+    delete ctx;
+    return FD_OK;
+}
+
+const char* fd_strerror(int32_t status) {
+    switch (status) {
+        case FD_OK: return "success";
+        case FD_ERR_INVALID_ARG: return "invalid argument";
+        case FD_ERR_UNSTABLE_DT: return "dt exceeds the CFL bound";
+        case FD_ERR_UNSUPPORTED: return "unsupported space order or physics";
+        case FD_ERR_WORKSPACE: return "workspace too small or misaligned";
+        case FD_ERR_DEVICE: return "HIP runtime error";
+        case FD_ERR_NONFINITE: return "non-finite or non-positive model values";
+        default: return "unknown status";
+    }
+}
+
+const char* fd_last_error(const fd_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+}  // extern "C"

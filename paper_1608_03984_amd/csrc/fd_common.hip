@@ -1,0 +1,232 @@
+// fd_common.hip -- layout, setup and sparse-point kernels of libfd (gfx950).
+#include "fd_internal.h"
+
+namespace fd {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ inline int64_t vol_index(const Layout& L, int x, int y, int z) {
+    return L.origin + (int64_t)z * L.plane + (int64_t)y * L.pitch + x;
+}
+
+__global__ __launch_bounds__(kBlock) void fill_zero_kernel(float4* p, int64_t n4) {
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n4;
+         i += (int64_t)gridDim.x * kBlock)
+        p[i] = z;
+}
+
+// dense [nz][ny][nx] <-> padded volume
+__global__ __launch_bounds__(kBlock) void pack_kernel(const float* __restrict__ vol,
+                                                      float* __restrict__ dense, Layout L) {
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int x = (int)(i % L.nx);
+        const int64_t r = i / L.nx;
+        const int y = (int)(r % L.ny);
+        const int z = (int)(r / L.ny);
+        dense[i] = vol[vol_index(L, x, y, z)];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void unpack_kernel(const float* __restrict__ dense,
+                                                        float* __restrict__ vol, Layout L) {
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int x = (int)(i % L.nx);
+        const int64_t r = i / L.nx;
+        const int y = (int)(r % L.ny);
+        const int z = (int)(r / L.ny);
+        vol[vol_index(L, x, y, z)] = dense[i];
+    }
+}
+
+// Derive the per-point coefficients the time loop reads, in FP32:
+//   A = (dt v)^2, s = eta dt / 2, and for TTI e = 1 + 2 eps, d = sqrt(1 + 2 delta),
+//   c1 = sin^2(th) cos^2(ph), c2 = sin^2(th) sin^2(ph), c3 = cos^2(th),
+//   c4 = sin(2ph) sin^2(th), c5 = sin(ph) sin(2th), c6 = cos(ph) sin(2th)
+// (the weights of Dxx, Dyy, Dzz, Dxy, Dyz, Dxz in G_zbar_zbar, Eq. (DiffOp)).
+// Also reduces the fastest speed (v, or v sqrt(1 + 2 eps) for TTI) and flags
+// invalid values and delta > eps.
+__global__ __launch_bounds__(kBlock) void setup_kernel(SetupArgs a) {
+    __shared__ float smax[kBlock / 64];
+    const Layout& L = a.L;
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    float vmax = 0.f;
+    uint32_t bad = 0, dgt = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int x = (int)(i % L.nx);
+        const int64_t r = i / L.nx;
+        const int y = (int)(r % L.ny);
+        const int z = (int)(r / L.ny);
+        const int64_t k = vol_index(L, x, y, z);
+        const float v = a.vel[i];
+        if (!(v > 0.f) || !isfinite(v)) bad = 1;
+        const float dv = a.dt * v;
+        a.A[k] = dv * dv;
+        float speed = v;
+        if (a.sig) {
+            const float et = a.eta[i];
+            if (!(et >= 0.f) || !isfinite(et)) bad = 1;
+            a.sig[k] = 0.5f * a.dt * et;
+        }
+        if (a.e) {
+            const float ep = a.eps[i], de = a.delta[i], th = a.theta[i], ph = a.phi[i];
+            if (!isfinite(ep) || !isfinite(de) || !isfinite(th) || !isfinite(ph)) bad = 1;
+            const float e = 1.f + 2.f * ep;
+            const float d2 = 1.f + 2.f * de;
+            if (!(e > 0.f) || !(d2 > 0.f)) bad = 1;
+            if (de > ep) dgt = 1;
+            a.e[k] = e;
+            a.d[k] = sqrtf(fmaxf(d2, 0.f));
+            float st, ct, sp, cp;
+            sincosf(th, &st, &ct);
+            sincosf(ph, &sp, &cp);
+            const float st2 = st * st;
+            a.c[0][k] = st2 * cp * cp;
+            a.c[1][k] = st2 * sp * sp;
+            a.c[2][k] = ct * ct;
+            a.c[3][k] = 2.f * sp * cp * st2;
+            a.c[4][k] = sp * 2.f * st * ct;
+            a.c[5][k] = cp * 2.f * st * ct;
+            speed = v * sqrtf(fmaxf(e, 0.f));
+        }
+        if (isfinite(speed)) vmax = fmaxf(vmax, speed);
+    }
+    // block reduction of the maximum speed
+    for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off));
+    if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = vmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = smax[0];
+        for (int i = 1; i < kBlock / 64; ++i) m = fmaxf(m, smax[i]);
+        atomicMax(&a.reduce[0], __float_as_uint(m));  // non-negative: int order = float order
+    }
+    if (bad) atomicOr(&a.reduce[1], 1u);
+    if (dgt) atomicOr(&a.reduce[2], 1u);
+}
+
+// flags[(z * nty + ty) * ntx + tx] = 1 when any damping coefficient in the
+// 64 x tile_y tile (tx, ty) of plane z is non-zero.
+__global__ __launch_bounds__(kBlock) void damping_flags_kernel(const float* __restrict__ sig,
+                                                               uint8_t* flags, Layout L,
+                                                               int tile_y, int ntx, int nty) {
+    const int tile = blockIdx.x;
+    const int z = blockIdx.y;
+    const int tx = tile % ntx, ty = tile / ntx;
+    int any = 0;
+    for (int e = threadIdx.x; e < kTileX * tile_y; e += kBlock) {
+        const int x = tx * kTileX + (e & (kTileX - 1));
+        const int y = ty * tile_y + e / kTileX;
+        if (x < L.nx && y < L.ny && sig[vol_index(L, x, y, z)] != 0.f) any = 1;
+    }
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) flags[((int64_t)z * nty + ty) * ntx + tx] = any ? 1 : 0;
+}
+
+// One thread per (point, corner): u[corner] += w A q scale / (1 + s).
+__global__ __launch_bounds__(kBlock) void inject_kernel(float* u, const float* __restrict__ A,
+                                                        const float* __restrict__ sig,
+                                                        const SparsePoint* __restrict__ pts,
+                                                        int n, const float* __restrict__ q,
+                                                        float scale, Layout L, int ndim) {
+    const int ncorner = ndim == 3 ? 8 : 4;
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n * ncorner) return;
+    const int s = k / ncorner, c = k % ncorner;
+    const SparsePoint P = pts[s];
+    const int dx = c & 1;
+    const int dy = ndim == 3 ? (c >> 1) & 1 : 0;
+    const int dz = ndim == 3 ? c >> 2 : c >> 1;
+    const float w = (dx ? P.fx : 1.f - P.fx) * (dy ? P.fy : 1.f - P.fy) * (dz ? P.fz : 1.f - P.fz);
+    if (w == 0.f) return;
+    const int64_t i = P.base + dx + (int64_t)dy * L.pitch + (int64_t)dz * L.plane;
+    const float sg = sig ? sig[i] : 0.f;
+    atomicAdd(&u[i], w * A[i] * q[s] * scale / (1.f + sg));
+}
+
+// One thread per receiver: multilinear interpolation of u.
+__global__ __launch_bounds__(kBlock) void record_kernel(const float* __restrict__ u,
+                                                        const SparsePoint* __restrict__ pts,
+                                                        int n, float* __restrict__ out, Layout L,
+                                                        int ndim) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const SparsePoint P = pts[j];
+    const int ncorner = ndim == 3 ? 8 : 4;
+    float acc = 0.f;
+    for (int c = 0; c < ncorner; ++c) {
+        const int dx = c & 1;
+        const int dy = ndim == 3 ? (c >> 1) & 1 : 0;
+        const int dz = ndim == 3 ? c >> 2 : c >> 1;
+        const float w =
+            (dx ? P.fx : 1.f - P.fx) * (dy ? P.fy : 1.f - P.fy) * (dz ? P.fz : 1.f - P.fz);
+        if (w != 0.f) acc += w * u[P.base + dx + (int64_t)dy * L.pitch + (int64_t)dz * L.plane];
+    }
+    out[j] = acc;
+}
+
+int grid_for(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 65536) g = 65536;
+    return (int)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s) {
+    const int64_t n4 = n / 4;  // volumes and regions are multiples of 64 floats
+    hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(n4)), dim3(kBlock), 0, s,
+                       reinterpret_cast<float4*>(p), n4);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const float* vol, float* dense, const Layout& L, hipStream_t s) {
+    hipLaunchKernelGGL(pack_kernel, dim3(grid_for((int64_t)L.nx * L.ny * L.nz)), dim3(kBlock), 0,
+                       s, vol, dense, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const float* dense, float* vol, const Layout& L, hipStream_t s) {
+    hipLaunchKernelGGL(unpack_kernel, dim3(grid_for((int64_t)L.nx * L.ny * L.nz)), dim3(kBlock),
+                       0, s, dense, vol, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(setup_kernel, dim3(grid_for((int64_t)a.L.nx * a.L.ny * a.L.nz)),
+                       dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_damping_flags(const float* sig, uint8_t* flags, const Layout& L, int tile_y,
+                                int ntx, int nty, hipStream_t s) {
+    hipLaunchKernelGGL(damping_flags_kernel, dim3(ntx * nty, L.nz), dim3(kBlock), 0, s, sig,
+                       flags, L, tile_y, ntx, nty);
+    return hipGetLastError();
+}
+
+hipError_t launch_inject(float* u, const float* A, const float* sig, const SparsePoint* pts,
+                         int n, const float* q, float scale, const Layout& L, int ndim,
+                         hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int total = n * (ndim == 3 ? 8 : 4);
+    hipLaunchKernelGGL(inject_kernel, dim3((total + kBlock - 1) / kBlock), dim3(kBlock), 0, s, u,
+                       A, sig, pts, n, q, scale, L, ndim);
+    return hipGetLastError();
+}
+
+hipError_t launch_record(const float* u, const SparsePoint* pts, int n, float* out,
+                         const Layout& L, int ndim, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(record_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, u, pts,
+                       n, out, L, ndim);
+    return hipGetLastError();
+}
+
+}  // namespace fd

@@ -1,0 +1,121 @@
+// fd_internal.h -- layout and launch parameters shared by the host runtime and
+// the gfx950 kernels of libfd.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fd {
+
+constexpr int kMaxRadius = 8;   // space order 16
+constexpr int kGhostX = 32;     // zero columns left of x = 0 (128 B: rows start line-aligned)
+constexpr int kGhostYZ = 8;     // zero rows / planes beyond each y and z edge (>= kMaxRadius)
+constexpr int kTileX = 64;      // one wave64 spans the x extent of a tile
+
+// One padded volume in HBM.  Interior point (x, y, z) of the caller's
+// [Nz][Ny][Nx] array sits at  origin + z * plane + y * pitch + x.  The ring of
+// ghost cells around the interior is zero and never written, so stencil
+// reads need no bounds checks (homogeneous Dirichlet boundary).  The pitch
+// and the row count are rounded up so that the last, ragged tile of any
+// kernel reads only ghost cells past the interior.
+struct Layout {
+    int32_t nx, ny, nz;   // interior sizes (padded problem shape)
+    int32_t pitch;        // floats per row
+    int32_t rows;         // rows per plane
+    int32_t planes;       // planes per volume
+    int64_t plane;        // pitch * rows
+    int64_t origin;       // offset of interior (0,0,0)
+    int64_t volume;       // floats per volume (multiple of 64)
+};
+
+// A sparse point after host-side preprocessing: flat offset of its lowest
+// interpolation corner and the fractional position in that cell per axis.
+struct SparsePoint {
+    int64_t base;
+    float fx, fy, fz;
+    int32_t pad;
+};
+
+// Acoustic step: u^{n+1} = [2u^n - (1-s)u^{n-1} + A L u^n]/(1+s), written
+// over u^{n-1}.  L u = c0 u + sum_j cx[j](u[x+j]+u[x-j]) + (y) + (z).
+struct AcousticStep {
+    const float* __restrict__ uc;  // u^n
+    float* up;                     // u^{n-1} in, u^{n+1} out
+    const float* __restrict__ A;   // dt^2 v^2
+    const float* __restrict__ sig; // eta dt / 2, or nullptr
+    const uint8_t* __restrict__ dflag; // per (z, tile) "layer has damping" or nullptr
+    float c0;
+    float cx[kMaxRadius + 1], cy[kMaxRadius + 1], cz[kMaxRadius + 1];
+    Layout L;
+    int32_t ntx, nty, nzc, zchunk;  // tile grid (tiled kernels)
+    int32_t ntiles, nblocks;        // ntx*nty*nzc and the launched (multiple of 8) count
+};
+
+// TTI step (3D).  Per point the coefficient fields are
+//   A = dt^2 v^2, e = 1 + 2 eps, d = sqrt(1 + 2 delta),
+//   c1..c6 the G_zbar_zbar weights of Dxx, Dyy, Dzz, Dxy, Dyz, Dxz;
+// H = Laplacian - G_zbar_zbar.
+struct TTIStep {
+    const float* __restrict__ pc;
+    const float* __restrict__ rc;
+    float* pp;  // p^{n-1} in, p^{n+1} out
+    float* rp;  // r^{n-1} in, r^{n+1} out
+    const float* __restrict__ A;
+    const float* __restrict__ sig;
+    const uint8_t* __restrict__ dflag;
+    const float* __restrict__ e;
+    const float* __restrict__ d;
+    const float* __restrict__ c[6];
+    float w2x[kMaxRadius + 1], w2y[kMaxRadius + 1], w2z[kMaxRadius + 1];  // 2nd-derivative / h^2
+    float w1x[kMaxRadius + 1], w1y[kMaxRadius + 1], w1z[kMaxRadius + 1];  // 1st-derivative / h
+    Layout L;
+    int32_t ntx, nty, nzc, zchunk;
+    int32_t ntiles, nblocks;
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (defined in the .hip files), all asynchronous on `s`.
+// ---------------------------------------------------------------------------
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
+hipError_t launch_pack(const float* vol, float* dense, const Layout& L, hipStream_t s);
+hipError_t launch_unpack(const float* dense, float* vol, const Layout& L, hipStream_t s);
+
+// setup: derive coefficient volumes from the caller's dense model arrays and
+// reduce the model to {max speed, bad-value flag, delta>eps flag}.
+struct SetupArgs {
+    const float* vel;
+    const float* eta;
+    const float* eps;
+    const float* delta;
+    const float* theta;
+    const float* phi;
+    float dt;
+    float* A;
+    float* sig;     // nullptr when eta is nullptr
+    float* e;       // TTI only
+    float* d;
+    float* c[6];
+    uint32_t* reduce;  // [0] max speed bits, [1] bad flag, [2] delta>eps flag
+    Layout L;
+};
+hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
+hipError_t launch_damping_flags(const float* sig, uint8_t* flags, const Layout& L, int tile_y,
+                                int ntx, int nty, hipStream_t s);
+
+// sparse points
+hipError_t launch_inject(float* u, const float* A, const float* sig, const SparsePoint* pts,
+                         int n, const float* q, float scale, const Layout& L, int ndim,
+                         hipStream_t s);
+hipError_t launch_record(const float* u, const SparsePoint* pts, int n, float* out,
+                         const Layout& L, int ndim, hipStream_t s);
+
+// stencils
+hipError_t launch_acoustic(const AcousticStep& p, int ndim, int radius, int variant, int vy,
+                           hipStream_t s);
+hipError_t launch_tti(const TTIStep& p, int radius, int variant, hipStream_t s);
+
+// Tile height (rows) of the tiled acoustic kernel for a given radius / VY.
+int acoustic_tile_y(int radius, int vy);
+int tti_tile_y(int radius);
+
+}  // namespace fd

@@ -1,0 +1,206 @@
+"""GPU parity of the acoustic path (libfd through its C ABI) against the
+FP64 CPU oracle.
+
+Tolerances: one step from a common FP32 state must agree to relative L2
+1e-5; a full run must agree to 1e-4 on the receiver traces and on the final
+field relative to the field's peak norm over the run.  The GPU computes in
+FP32, the oracle in FP64 from the same FP32 inputs.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_1608_03984_amd as P  # noqa: E402
+from paper_1608_03984_amd.solver import Solver, from_problem  # noqa: E402
+from tests._gpu_util import (THREADS, acoustic_problem, oracle_run_with_peak, rel,  # noqa: E402
+                             sample_points, say)
+from workloads import acoustic_2d, acoustic_3d, noise_state  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+ORDERS = [2, 4, 6, 8, 10, 12, 14, 16]
+
+
+def gpu_run(p, variant=0, vy=0, zchunk=0):
+    s = from_problem(p)
+    if variant:
+        s.set_option(P.FD_OPT_KERNEL, variant)
+    if vy:
+        s.set_option(P.FD_OPT_VY, vy)
+    if zchunk:
+        s.set_option(P.FD_OPT_ZCHUNK, zchunk)
+    tr = s.forward(p.nt, p.src, p.wavelet, p.rec)
+    u = s.get_field(P.FD_FIELD_CUR)
+    torch.cuda.synchronize()
+    out = tr.cpu().numpy(), u.cpu().numpy()
+    s.close()
+    return out
+
+
+def test_acoustic_2d_workload_full_run():
+    """The 2D workload (201 x 201, so 4, 500 steps) end to end."""
+    p = acoustic_2d()
+    say("case: acoustic_2d so4 500 steps")
+    tr, u = gpu_run(p)
+    tref, st, peak = oracle_run_with_peak(p, chunk=25)
+    et, eu = rel(tr, tref), float(np.linalg.norm(u - st[1]) / peak)
+    say(f"  traces {et:.2e}  field/peak {eu:.2e}  field/inst {rel(u, st[1]):.2e}")
+    assert et < 1e-4 and eu < 1e-4
+
+
+@pytest.mark.parametrize("so", ORDERS)
+@pytest.mark.parametrize("variant", [0, 1])
+def test_acoustic_3d_multi_tile_full_run(so, variant):
+    """3D, several 64-wide tiles in x with a ragged tail, ragged in y and z,
+    damping layer, off-grid source, on- and off-grid receivers."""
+    p = acoustic_problem(3, (150, 37, 41), 8, so, 120, seed=100 + so)
+    say(f"case: acoustic 3d {p.padded} so{so} variant{variant}")
+    tr, u = gpu_run(p, variant=variant)
+    tref, st, peak = oracle_run_with_peak(p, chunk=20)
+    et, eu = rel(tr, tref), float(np.linalg.norm(u - st[1]) / peak)
+    say(f"  traces {et:.2e}  field/peak {eu:.2e}")
+    assert et < 1e-4 and eu < 1e-4
+
+
+@pytest.mark.parametrize("vy", [2, 4, 8])
+@pytest.mark.parametrize("so", [4, 16])
+def test_acoustic_3d_tile_shapes(so, vy):
+    """Every built row-blocking of the tiled kernel, short z chunks."""
+    p = acoustic_problem(3, (70, 50, 30), 6, so, 40, seed=7 + vy)
+    say(f"case: tile shapes so{so} vy{vy}")
+    tr, u = gpu_run(p, vy=vy, zchunk=2 * so + 3)
+    tref, st, peak = oracle_run_with_peak(p, chunk=40)
+    assert rel(tr, tref) < 1e-4
+    assert np.linalg.norm(u - st[1]) / peak < 1e-4
+
+
+@pytest.mark.parametrize("so", ORDERS)
+def test_acoustic_one_step_from_common_state(so):
+    """One source-free step from an FP32 white-noise state, every point."""
+    p = acoustic_problem(3, (90, 20, 30), 5, so, 1, seed=so)
+    shape = p.padded
+    up, uc = noise_state(shape, 1), noise_state(shape, 2)
+    say(f"case: one step so{so} {shape}")
+    s = from_problem(p)
+    s.set_field(P.FD_FIELD_PREV, up)
+    s.set_field(P.FD_FIELD_CUR, uc)
+    s.forward(1, zero_state=False)
+    got = s.get_field(P.FD_FIELD_CUR).cpu().numpy()
+    prev_after = s.get_field(P.FD_FIELD_PREV).cpu().numpy()
+    torch.cuda.synchronize()
+    s.close()
+    pts = np.arange(got.size)
+    oracle.set_threads(THREADS)
+    ref = oracle.acoustic_step_points(3, p.spacing, p.dt, so, p.vel, p.eta, up, uc, pts)
+    oracle.set_threads(1)
+    e = rel(got.ravel(), ref)
+    say(f"  one-step rel L2 {e:.2e}")
+    assert e < 1e-5
+    assert np.array_equal(prev_after, uc)  # the level swap hands u^n back as u^{n-1}
+
+
+@pytest.fixture(scope="module")
+def full_size_inputs():
+    say("generating the 512^3 (+40 layer) workload model")
+    p = acoustic_3d(so=8, phys=512, nbl=40, nt=1, receivers="none")
+    shape = p.padded
+    return p, noise_state(shape, 11), noise_state(shape, 12)
+
+
+@pytest.mark.parametrize("so", [4, 8, 12, 16])
+def test_acoustic_full_size_one_step_sampled(full_size_inputs, so):
+    """592^3 (512^3 + 40-point layer), the launch configuration the benchmark
+    times: one step from a common state, checked at sampled points (edges,
+    corners, tile boundaries and random points)."""
+    p0, up, uc = full_size_inputs
+    from workloads import DT
+    dt = DT[("acoustic_3d", so)]
+    say(f"case: full-size one step so{so} {p0.padded}")
+    s = Solver(3, p0.shape, p0.spacing, p0.nbl, so, dt, p0.vel, p0.eta, max_points=16)
+    s.set_field(P.FD_FIELD_PREV, up)
+    s.set_field(P.FD_FIELD_CUR, uc)
+    s.forward(1, zero_state=False)
+    got = s.get_field(P.FD_FIELD_CUR).cpu().numpy().ravel()
+    torch.cuda.synchronize()
+    s.close()
+    pts = sample_points(p0.padded, 6000, seed=so, radius=so // 2)
+    oracle.set_threads(THREADS)
+    ref = oracle.acoustic_step_points(3, p0.spacing, dt, so, p0.vel, p0.eta, up, uc, pts)
+    oracle.set_threads(1)
+    e = rel(got[pts], ref)
+    say(f"  sampled ({pts.size} pts) one-step rel L2 {e:.2e}")
+    assert e < 1e-5
+    assert np.all(np.isfinite(got[pts]))
+
+
+def test_acoustic_deterministic():
+    p = acoustic_problem(3, (100, 30, 30), 6, 8, 50, seed=3)
+    say("case: determinism")
+    a = gpu_run(p)
+    b = gpu_run(p)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_acoustic_continue_equals_single_run():
+    """Two calls of n1 and n2 steps equal one call of n1 + n2 steps."""
+    p = acoustic_problem(3, (80, 20, 20), 4, 4, 30, seed=4)
+    say("case: continue")
+    s = from_problem(p)
+    t_all = s.forward(30, p.src, p.wavelet, p.rec).cpu().numpy()
+    u_all = s.get_field().cpu().numpy()
+    t1 = s.forward(12, p.src, p.wavelet[:12], p.rec).cpu().numpy()
+    t2 = s.forward(18, p.src, p.wavelet[12:], p.rec, zero_state=False).cpu().numpy()
+    u2 = s.get_field().cpu().numpy()
+    torch.cuda.synchronize()
+    s.close()
+    assert np.array_equal(np.concatenate([t1, t2]), t_all)
+    assert np.array_equal(u2, u_all)
+
+
+def test_acoustic_edge_cases():
+    say("case: edge cases")
+    # a grid smaller than the stencil, no layer, no points, nt = 0
+    p = acoustic_problem(3, (3, 2, 5), 0, 16, 6, seed=5, damping=False, nrec=2)
+    tr, u = gpu_run(p)
+    tref, st, _ = oracle_run_with_peak(p, chunk=6)
+    assert rel(tr, tref) < 1e-4 and rel(u, st[1]) < 1e-4
+    s = from_problem(p)
+    s.forward(0, p.src, p.wavelet[:0], p.rec)
+    s.forward(5)
+    assert float(s.get_field().abs().max()) == 0.0
+    s.close()
+    # 2D with odd sizes and every order
+    for so in (2, 8, 16):
+        q = acoustic_problem(2, (67, 1, 33), 5, so, 40, seed=so)
+        tr, u = gpu_run(q)
+        tref, st, peak = oracle_run_with_peak(q, chunk=40)
+        assert rel(tr, tref) < 1e-4 and np.linalg.norm(u - st[1]) / peak < 1e-4
+
+
+def test_acoustic_error_paths():
+    say("case: error paths")
+    p = acoustic_problem(3, (20, 20, 20), 4, 8, 2, seed=6)
+    g = P.make_grid(3, p.shape, p.spacing, p.nbl, 8, p.dt * 2.6)   # 0.4 * 2.6 > CFL
+    with pytest.raises(P.FdError) as e:
+        Solver(3, p.shape, p.spacing, p.nbl, 8, p.dt * 2.6, p.vel, p.eta)
+    assert e.value.code == P.FD_ERR_UNSTABLE_DT
+    bad = p.vel.copy()
+    bad[3, 4, 5] = np.nan
+    with pytest.raises(P.FdError) as e:
+        Solver(3, p.shape, p.spacing, p.nbl, 8, p.dt, bad, p.eta)
+    assert e.value.code == P.FD_ERR_NONFINITE
+    bad = p.vel.copy()
+    bad[0, 0, 0] = -1.0
+    with pytest.raises(P.FdError) as e:
+        Solver(3, p.shape, p.spacing, p.nbl, 8, p.dt, bad, p.eta)
+    assert e.value.code == P.FD_ERR_NONFINITE
+    s = from_problem(p)
+    with pytest.raises(P.FdError) as e:
+        s.forward(2, np.array([[1e6, 0.0, 0.0]]), p.wavelet, p.rec)
+    assert e.value.code == P.FD_ERR_INVALID_ARG and "outside" in str(e.value)
+    with pytest.raises(P.FdError):
+        s.set_option(P.FD_OPT_VY, 3)
+    s.close()
+    del g

@@ -1,0 +1,103 @@
+"""GPU parity of the TTI path (libfd through its C ABI) against the FP64
+CPU oracle (same tolerances as the acoustic path)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_1608_03984_amd as P  # noqa: E402
+from paper_1608_03984_amd.solver import Solver, from_problem  # noqa: E402
+from tests._gpu_util import (THREADS, oracle_run_with_peak, rel, sample_points, say,  # noqa: E402
+                             tti_problem)
+from workloads import noise_state, tti_3d  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_run(p, variant=0):
+    s = from_problem(p)
+    if variant:
+        s.set_option(P.FD_OPT_KERNEL, variant)
+    tr = s.forward(p.nt, p.src, p.wavelet, p.rec)
+    u = s.get_field(P.FD_FIELD_CUR)
+    r = s.get_field(P.FD_FIELD_R_CUR)
+    torch.cuda.synchronize()
+    out = tr.cpu().numpy(), u.cpu().numpy(), r.cpu().numpy()
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("so", [2, 4, 8])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_tti_multi_tile_full_run(so, variant):
+    p = tti_problem((80, 26, 22), 6, so, 60, seed=200 + so)
+    say(f"case: tti {p.padded} so{so} variant{variant}")
+    tr, u, r = gpu_run(p, variant)
+    tref, st, peak = oracle_run_with_peak(p, chunk=20)
+    et = rel(tr, tref)
+    eu = float(np.linalg.norm(u - st[1]) / peak)
+    er = float(np.linalg.norm(r - st[3]) / max(np.linalg.norm(st[3]), 1e-30))
+    say(f"  traces {et:.2e}  p/peak {eu:.2e}  r {er:.2e}")
+    assert et < 1e-4 and eu < 1e-4 and er < 1e-4
+
+
+@pytest.mark.parametrize("so", [2, 4, 8, 12, 16])
+def test_tti_one_step_from_common_state(so):
+    p = tti_problem((70, 18, 20), 4, so, 1, seed=so)
+    shape = p.padded
+    st = [noise_state(shape, 20 + k) for k in range(4)]
+    say(f"case: tti one step so{so} {shape}")
+    s = from_problem(p)
+    for which, f in zip((P.FD_FIELD_PREV, P.FD_FIELD_CUR, P.FD_FIELD_R_PREV, P.FD_FIELD_R_CUR), st):
+        s.set_field(which, f)
+    s.forward(1, zero_state=False)
+    gp = s.get_field(P.FD_FIELD_CUR).cpu().numpy().ravel()
+    gr = s.get_field(P.FD_FIELD_R_CUR).cpu().numpy().ravel()
+    torch.cuda.synchronize()
+    s.close()
+    pts = np.arange(gp.size)
+    oracle.set_threads(THREADS)
+    rp, rr = oracle.tti_step_points(p.spacing, p.dt, so, p.vel, p.eta, p.eps, p.delta, p.theta,
+                                    p.phi, st, pts)
+    oracle.set_threads(1)
+    ep, er = rel(gp, rp), rel(gr, rr)
+    say(f"  one-step rel L2 p {ep:.2e} r {er:.2e}")
+    assert ep < 1e-5 and er < 1e-5
+
+
+def test_tti_full_size_one_step_sampled():
+    """464^3 (384^3 + 40-point layer), so 8: one step from a common state at
+    sampled points, in the launch configuration the benchmark times."""
+    say("generating the 384^3 (+40 layer) TTI workload model")
+    p = tti_3d(so=8, phys=384, nbl=40, nt=1, receivers="none")
+    shape = p.padded
+    st = [noise_state(shape, 30 + k) for k in range(4)]
+    say(f"case: tti full-size one step {shape}")
+    s = Solver(3, p.shape, p.spacing, p.nbl, 8, p.dt, p.vel, p.eta, physics="tti",
+               epsilon=p.eps, delta=p.delta, theta=p.theta, phi=p.phi, max_points=16)
+    for which, f in zip((P.FD_FIELD_PREV, P.FD_FIELD_CUR, P.FD_FIELD_R_PREV, P.FD_FIELD_R_CUR), st):
+        s.set_field(which, f)
+    s.forward(1, zero_state=False)
+    gp = s.get_field(P.FD_FIELD_CUR).cpu().numpy().ravel()
+    gr = s.get_field(P.FD_FIELD_R_CUR).cpu().numpy().ravel()
+    torch.cuda.synchronize()
+    s.close()
+    pts = sample_points(shape, 4000, seed=8, radius=4)
+    oracle.set_threads(THREADS)
+    rp, rr = oracle.tti_step_points(p.spacing, p.dt, 8, p.vel, p.eta, p.eps, p.delta, p.theta,
+                                    p.phi, st, pts)
+    oracle.set_threads(1)
+    ep, er = rel(gp[pts], rp), rel(gr[pts], rr)
+    say(f"  sampled one-step rel L2 p {ep:.2e} r {er:.2e}")
+    assert ep < 1e-5 and er < 1e-5
+
+
+def test_tti_rejects_delta_above_epsilon():
+    p = tti_problem((20, 20, 20), 2, 4, 1, seed=1)
+    bad = p.delta.copy()
+    bad[5, 5, 5] = p.eps[5, 5, 5] + 0.05
+    with pytest.raises(P.FdError) as e:
+        Solver(3, p.shape, p.spacing, p.nbl, 4, p.dt, p.vel, p.eta, physics="tti",
+               epsilon=p.eps, delta=bad, theta=p.theta, phi=p.phi)
+    assert e.value.code == P.FD_ERR_INVALID_ARG

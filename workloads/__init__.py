@@ -191,6 +191,12 @@ def _pad_edge(a: np.ndarray, nbl: int) -> np.ndarray:
     return np.pad(a, nbl, mode="edge") if nbl > 0 else a
 
 
+def noise_state(padded_shape, seed: int) -> np.ndarray:
+    """White-noise state N(0, 1), float32 (the harshest input for a stencil)."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(padded_shape, dtype=np.float32)
+
+
 def smooth_state(padded_shape, seed: int, corr_pts: float = 6.0) -> np.ndarray:
     """Synthetic wavefield-like state: a smooth random field plus 1 % white
     noise, float32, max|.| about 1.  Used as a common starting state for
