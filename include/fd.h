@@ -151,13 +151,22 @@ int32_t fd_set_field(fd_ctx* ctx, int32_t which, const float* src, void* stream)
 int32_t fd_stencil_weights(int32_t space_order, int32_t deriv, double* w);
 int32_t fd_cfl_dt(const fd_grid* grid, double vmax, double* dt_max);
 
+/* STREAM-style triad a[i] = b[i] + s c[i] over n floats (device pointers,
+ * 16-byte aligned): the measured bandwidth ceiling of section 3.1 (STREAM
+ * TRIAD as the practical memory limit), and a kernel of exactly known
+ * traffic (8 bytes read, 4 written per element) for calibrating hardware
+ * byte counters.  Asynchronous on `stream`. */
+int32_t fd_triad(float* a, const float* b, const float* c, float s, int64_t n, void* stream);
+
 /* Tuning options (kernel variant / launch shape), mainly for benchmarking.
  * FD_OPT_KERNEL: 0 = tiled (default), 1 = direct global-memory kernel.
  * FD_OPT_ZCHUNK: z-planes per thread block of the tiled 3D kernels (0 = auto).
- * FD_OPT_VY: rows per thread of the tiled acoustic kernel (0 = auto). */
+ * FD_OPT_TILE: (x, y) tile of the tiled 3D acoustic kernel: 0 = 64x8 with 256
+ *   threads, 1 = 64x16 with 256, 2 = 64x8 with 512, 3 = 64x16 with 512,
+ *   -1 = the default for the space order. */
 #define FD_OPT_KERNEL 1
 #define FD_OPT_ZCHUNK 2
-#define FD_OPT_VY 3
+#define FD_OPT_TILE 3
 int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value);
 
 /* Frees the host context (not the workspace). NULL is accepted. */

@@ -32,12 +32,12 @@ FD_MAX_SPACE_ORDER = 16
 
 FD_OPT_KERNEL = 1
 FD_OPT_ZCHUNK = 2
-FD_OPT_VY = 3
+FD_OPT_TILE = 3
 
 EXPORTS = (
     "fd_workspace_bytes", "fd_setup", "fd_forward", "fd_get_field", "fd_set_field",
     "fd_stencil_weights", "fd_cfl_dt", "fd_set_option", "fd_destroy", "fd_strerror",
-    "fd_last_error",
+    "fd_last_error", "fd_triad",
 )
 
 
@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
             "fd_destroy": (i32, [vp]),
             "fd_strerror": (ctypes.c_char_p, [i32]),
             "fd_last_error": (ctypes.c_char_p, [vp]),
+            "fd_triad": (i32, [vp, vp, vp, ctypes.c_float, ctypes.c_int64, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -190,6 +191,11 @@ def fd_set_option(ctx, option: int, value: int):
 def fd_destroy(ctx):
     if ctx:
         lib().fd_destroy(ctx)
+
+
+def fd_triad(a_ptr: int, b_ptr: int, c_ptr: int, s: float, n: int, stream: int):
+    _check(lib().fd_triad(ctypes.c_void_p(a_ptr), ctypes.c_void_p(b_ptr), ctypes.c_void_p(c_ptr),
+                          float(s), int(n), ctypes.c_void_p(stream)), "fd_triad")
 
 
 def fd_stencil_weights(space_order: int, deriv: int) -> np.ndarray:

@@ -36,7 +36,7 @@ struct fd_ctx {
     float* c[6];
     float* u[2];  // acoustic u / TTI p: two levels
     float* r[2];  // TTI r: two levels
-    uint8_t* dflag;
+    int32_t* dflag;
     SparsePoint* pts;
     int cur;  // index of the level holding u^n in u[]/r[]
     // derived stencil coefficients (float, already divided by h or h^2)
@@ -44,7 +44,7 @@ struct fd_ctx {
     float w1[3][fd::kMaxRadius + 1];
     // launch configuration
     int variant;
-    int vy;
+    int tile_cfg;
     int zchunk_opt;
     int tile_y;
     bool flags_stale;
@@ -156,7 +156,7 @@ Layout make_layout(const fd_grid* g) {
     // y: kGhostYZ zero rows each side of the interior rounded to 64 rows (so
     // any tile height dividing 64 stays inside); 2D has a single row.
     L.rows = g->ndim == 3 ? (int32_t)(fd::kGhostYZ + round_up(L.ny, 64) + fd::kGhostYZ) : 1;
-    L.planes = L.nz + 2 * fd::kGhostYZ;
+    L.planes = L.nz + fd::kGhostYZ + fd::kGhostZTop;
     L.plane = (int64_t)L.pitch * L.rows;
     L.origin = (int64_t)fd::kGhostYZ * L.plane + (g->ndim == 3 ? (int64_t)fd::kGhostYZ * L.pitch : 0) +
                fd::kGhostX;
@@ -198,7 +198,7 @@ uint64_t plan_workspace(const fd_grid* g, const Layout& L, int32_t max_points, f
     }
     const int64_t ntx = (L.nx + fd::kTileX - 1) / fd::kTileX;
     const int64_t nty = (L.ny + min_tile_y() - 1) / min_tile_y();
-    const uint64_t o_flag = cv.take((uint64_t)(ntx * nty * L.nz));
+    const uint64_t o_flag = cv.take((uint64_t)(ntx * nty * L.nz) * sizeof(int32_t));
     const uint64_t o_pts = cv.take((uint64_t)(max_points > 0 ? max_points : 1) * sizeof(SparsePoint));
     if (ctx && base) {
         ctx->reduce = reinterpret_cast<uint32_t*>(base + o_red);
@@ -211,7 +211,7 @@ uint64_t plan_workspace(const fd_grid* g, const Layout& L, int32_t max_points, f
         ctx->u[1] = reinterpret_cast<float*>(base + o_u1);
         ctx->r[0] = tti ? reinterpret_cast<float*>(base + o_r[0]) : nullptr;
         ctx->r[1] = tti ? reinterpret_cast<float*>(base + o_r[1]) : nullptr;
-        ctx->dflag = reinterpret_cast<uint8_t*>(base + o_flag);
+        ctx->dflag = reinterpret_cast<int32_t*>(base + o_flag);
         ctx->pts = reinterpret_cast<SparsePoint*>(base + o_pts);
     }
     return cv.off;
@@ -259,7 +259,10 @@ bool locate(const fd_ctx* ctx, const double* c, SparsePoint* P) {
     return true;
 }
 
-int default_vy(int radius) { return radius <= 4 ? 4 : 2; }
+// Tile shape of the tiled acoustic kernel (measured on the 592^3 workload):
+// 64 x 16 with 512 threads up to radius 4, 64 x 8 with 256 threads above,
+// where the wider register queue leaves room for fewer rows per block.
+int default_tile(int radius) { return radius <= 4 ? 3 : 0; }
 
 void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, fd::AcousticStep* a,
                fd::TTIStep* t) {
@@ -268,9 +271,13 @@ void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, fd::Ac
     const int nty = (L.ny + tile_y - 1) / tile_y;
     int zc = zchunk_opt;
     if (zc <= 0) {
+        // Split z so the grid holds about 768 blocks (three 256-thread blocks
+        // per CU): every z chunk re-reads 2R planes and runs R pipeline-fill
+        // steps, so high orders round the chunk count down.
         const int64_t xy = (int64_t)ntx * nty;
-        const int64_t target = (2048 + xy - 1) / xy;
-        zc = (int)((L.nz + target - 1) / target);
+        int64_t nzc = radius <= 4 ? (768 + xy / 2) / xy : 768 / xy;
+        if (nzc < 1) nzc = 1;
+        zc = (int)((L.nz + nzc - 1) / nzc);
         if (zc < 4 * radius) zc = 4 * radius;
     }
     if (zc > L.nz) zc = L.nz;
@@ -352,9 +359,9 @@ int32_t fd_setup(const fd_grid* grid, const fd_model* model, void* workspace,
     ctx->max_points = max_points;
     ctx->cur = 1;
     ctx->variant = 0;
-    ctx->vy = default_vy(ctx->radius);
+    ctx->tile_cfg = default_tile(ctx->radius);
     ctx->zchunk_opt = 0;
-    ctx->tile_y = tti ? fd::tti_tile_y(ctx->radius) : fd::acoustic_tile_y(ctx->radius, ctx->vy);
+    ctx->tile_y = tti ? fd::tti_tile_y(ctx->radius) : fd::acoustic_tile_y(ctx->tile_cfg);
     ctx->nsrc_dev = ctx->nrec_dev = -1;
     ctx->flags_stale = false;
     plan_workspace(grid, L, max_points, ctx, static_cast<char*>(workspace));
@@ -439,12 +446,12 @@ int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value) {
             if (value < 0 || value > (1 << 20)) return fail(ctx, FD_ERR_INVALID_ARG, "zchunk range");
             ctx->zchunk_opt = (int)value;
             return FD_OK;
-        case FD_OPT_VY: {
-            if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "VY applies to the acoustic kernel");
-            const int v = value == 0 ? default_vy(ctx->radius) : (int)value;
-            if (v != 2 && v != 4 && v != 8) return fail(ctx, FD_ERR_INVALID_ARG, "VY must be 2, 4 or 8");
-            ctx->vy = v;
-            ctx->tile_y = fd::acoustic_tile_y(ctx->radius, v);
+        case FD_OPT_TILE: {
+            if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "the tile option applies to acoustic");
+            const int v = value < 0 ? default_tile(ctx->radius) : (int)value;
+            if (v < 0 || v > 3) return fail(ctx, FD_ERR_INVALID_ARG, "tile configuration is 0..3");
+            ctx->tile_cfg = v;
+            ctx->tile_y = fd::acoustic_tile_y(v);
             ctx->flags_stale = true;  // rebuilt on the caller's stream by fd_forward
             return FD_OK;
         }
@@ -513,7 +520,8 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
     const SparsePoint* spts = ctx->pts;
     const SparsePoint* rpts = ctx->pts + nsrc;
     const float* sig = ctx->damping ? ctx->sig : nullptr;
-    const uint8_t* dflag = (ctx->damping && nd == 3) ? ctx->dflag : nullptr;
+    // 3D kernels always get the flag array (all zero when there is no damping)
+    const int32_t* dflag = nd == 3 ? ctx->dflag : nullptr;
 
     if (!ctx->tti) {
         fd::AcousticStep p;
@@ -535,7 +543,7 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
             float* un = ctx->u[1 - ctx->cur];  // holds u^{n-1}, receives u^{n+1}
             p.uc = ctx->u[ctx->cur];
             p.up = un;
-            he = fd::launch_acoustic(p, nd, ctx->radius, ctx->variant, ctx->vy, s);
+            he = fd::launch_acoustic(p, nd, ctx->radius, ctx->variant, ctx->tile_cfg, s);
             if (he == hipSuccess && nsrc)
                 he = fd::launch_inject(un, ctx->A, sig, spts, nsrc, src->data + (size_t)n * nsrc,
                                        scale, ctx->L, nd, s);

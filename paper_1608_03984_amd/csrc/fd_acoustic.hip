@@ -10,6 +10,8 @@
 // hold damping.
 #include "fd_internal.h"
 
+#include <utility>
+
 namespace fd {
 
 namespace {
@@ -17,6 +19,21 @@ namespace {
 __device__ inline float update(float c, float prev, float a, float lap, float s) {
     if (s == 0.f) return fmaf(a, lap, 2.f * c - prev);
     return (2.f * c - (1.f - s) * prev + a * lap) / (1.f + s);
+}
+
+// Raw buffer access: a uniform base pointer (one per plane, held in SGPRs)
+// plus a per-lane 32-bit byte offset.  aux 2 marks streaming (non-temporal)
+// accesses.  The record limit only has to exceed the largest in-tile offset.
+constexpr int kBufNT = 2;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const float* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, 0x7fffffff, 0x00020000);
+}
+template <int AUX = 0>
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+}
+__device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, kBufNT);
 }
 
 // ---------------------------------------------------------------------------
@@ -52,168 +69,253 @@ __global__ __launch_bounds__(256) void acoustic_direct(AcousticStep p) {
 // Tiled 3D kernel (2.5D blocking).
 //
 // A block owns a 64 x TY column of (x, y) and marches over a chunk of z
-// planes.  Each lane holds one x position and VY consecutive rows; the 2R+1
-// planes around the current one live in a per-lane register queue (the z
-// derivative never touches LDS).  The current plane, with an R-wide halo in x
-// and y, is staged in a double-buffered LDS tile (one barrier per plane);
-// x and y neighbours are read from LDS.  The loads for plane z+1 (queue
-// head, halo, u^{n-1}, A and, in damped tiles, s) are issued before plane z
-// is computed, so their latency overlaps the arithmetic.
+// planes; each lane holds one x position and VY consecutive rows.
+//
+// Plane p enters the block once, as the "head" of the z pipeline, R planes
+// before it becomes the output plane.  On arrival its centre values and its
+// R-wide x/y halo are staged in LDS and the in-plane part of the Laplacian,
+// Lx + Ly, is computed for the lane's points; the centre values go into a
+// register queue (2R+1 planes, for the z derivative) and Lx + Ly into an LDS
+// ring (R+1 planes, each lane reading back only what it wrote) until the
+// plane is output.  Loading the halo of the
+// head plane -- rather than of the output plane -- means a tile reads its
+// neighbours' rows at the moment the neighbours stream the same plane in, so
+// the halo re-reads hit in L2 instead of going back to memory.
+//
+// The operands of a step (head centre and halo, and u^{n-1}, A, damping of
+// the output plane) are loaded two steps ahead into one of two register
+// slots.  Every step issues the same loads and the z loop is unrolled by the
+// queue period U = 2R+2, so queues and slots rotate by compile-time index and
+// the compiler waits for exactly the slot it needs.  Loads and stores are
+// raw buffer accesses: a uniform per-plane base in SGPRs plus a per-lane
+// 32-bit offset.  Offsets of points outside the interior are set past the
+// buffer's record limit, so ghost points read as zero without any memory
+// traffic and their stores are dropped.  Undamped tiles, and the steps that
+// produce no output, read their operands from an all-zero ghost plane that
+// stays cached; the per-plane damping flag is a scalar load issued one step
+// ahead.
 //
 // Blocks are numbered so that the 8 XCDs (which receive blocks round-robin)
 // each get a contiguous run of tiles: neighbours that share halo rows run on
 // the same XCD and find them in its L2.
 // ---------------------------------------------------------------------------
+typedef const __attribute__((address_space(4))) int32_t cflag_t;
+constexpr uint32_t kOOB = 0x80000000u;  // any offset at or past the record limit reads 0
+constexpr int kRecords = 0x7fffffff;
+
+
 template <int R, int NW, int VY>
-__global__ __launch_bounds__(64 * NW) void acoustic3d_tiled(AcousticStep p) {
-    constexpr int TY = NW * VY;
-    constexpr int LW = kTileX + 2 * R;
-    constexpr int LH = TY + 2 * R;
-    constexpr int NYH = (2 * R + NW - 1) / NW;               // y-halo rows per wave
-    constexpr int NXH = (2 * R * TY + 64 * NW - 1) / (64 * NW);  // x-halo values per thread
-    __shared__ float lds[2][LH][LW];
+struct TiledAcoustic {
+    static constexpr int TY = NW * VY;
+    static constexpr int LW = kTileX + 2 * R;
+    static constexpr int LH = TY + 2 * R + 1;  // last row: sink for idle halo lanes
+    static constexpr int U = 2 * R + 2;
+    static constexpr int NYH = (2 * R + NW - 1) / NW;
+    static constexpr int NXH = (2 * R * TY + 64 * NW - 1) / (64 * NW);
+    static constexpr int LDS_FLOATS = LH * LW;
+    static constexpr int LQ_FLOATS = (R + 1) * TY * kTileX;  // ring of Lx + Ly, R+1 planes
 
-    const int b = blockIdx.x;
-    const int t = (b & 7) * (p.nblocks >> 3) + (b >> 3);
-    if (t >= p.ntiles) return;
-    const int tx = t % p.ntx;
-    const int t2 = t / p.ntx;
-    const int ty = t2 % p.nty;
-    const int zc = t2 / p.nty;
-    const int x0 = tx * kTileX, y0 = ty * TY;
-    const int z0 = zc * p.zchunk;
-    const int z1 = min(z0 + p.zchunk, p.L.nz);
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int w = tid >> 6;
-    const int64_t pitch = p.L.pitch, plane = p.L.plane;
-    const int64_t col = p.L.origin + (int64_t)(y0 + w * VY) * pitch + x0 + lane;
-    const bool xin = x0 + lane < p.L.nx;
-    const float* __restrict__ u = p.uc;
+    const AcousticStep& p;
+    float* lds;
+    const float* ub;  // tile origin (x0 - R, y0 - R) of u^n, plane 0
+    float* pb;        // same for u^{n-1} / u^{n+1}
+    const float* ab;  // same for A
+    const float* sb;  // same for the damping coefficient
+    const float* zpl; // an all-zero plane (ghost plane of A) at the tile origin
+    cflag_t* flags;
+    int64_t plane;
+    int z0, z1, nz, ty, tx, nty, ntx;
+    int lane, w;
+    int flagbuf;      // damping flag of the next plane to fetch
+    uint32_t oc[VY], ohy[NYH], ohx[NXH];  // byte offsets inside the tile (kOOB outside)
+    int ly_[NYH], lx_[NXH];
+    float q[U][VY];   // centre values, planes z-R .. z+R
+    float* lq;        // LDS ring: Lx + Ly of planes z .. z+R, slot (plane - zs) mod (R+1)
+    float nxt[2][VY], prv[2][VY], aa[2][VY], sg[2][VY], hy[2][NYH], hx[2][NXH];
+    int damp[2];
 
-    // halo sources (offsets within a plane) and LDS destinations
-    int64_t hy_off[NYH];
-    int hy_row[NYH];
-#pragma unroll
-    for (int k = 0; k < NYH; ++k) {
-        const int hr = w + k * NW;
-        const int yy = hr < R ? y0 - R + hr : y0 + TY + (hr - R);
-        hy_row[k] = hr < R ? hr : TY + hr;
-        hy_off[k] = p.L.origin + (int64_t)yy * pitch + x0 + lane;
-    }
-    int64_t hx_off[NXH];
-    int hx_lds[NXH];
-#pragma unroll
-    for (int k = 0; k < NXH; ++k) {
-        const int e = tid + k * 64 * NW;
-        const int row = e / (2 * R), cc = e % (2 * R);
-        const int xx = cc < R ? x0 - R + cc : x0 + kTileX + (cc - R);
-        hx_lds[k] = (R + row) * LW + (cc < R ? cc : kTileX + cc);
-        hx_off[k] = p.L.origin + (int64_t)(y0 + row) * pitch + xx;
+    __device__ TiledAcoustic(const AcousticStep& ps, float* l, float* lqr)
+        : p(ps), lds(l), lq(lqr) {}
+
+    __device__ __forceinline__ int flag_of(int z) const {
+        if (z < 0 || z >= nz) return 0;
+        return flags[((int64_t)z * nty + ty) * ntx + tx];
     }
 
-    float q[2 * R + 1][VY];
-    float nxt[VY], prv[VY], aa[VY], sg[VY], hyv[NYH], hxv[NXH];
-    int damp;
-
-    auto load_plane_extras = [&](int z, float* prv_, float* aa_, float* sg_, int& damp_) {
-        const int64_t zo = (int64_t)z * plane;
+    // Operands of the step whose output plane is zc: the head plane zc + R
+    // (centre and halo) and u^{n-1}, A and damping of plane zc.  Head planes
+    // beyond the grid are zero ghost planes of the volume; the operands of a
+    // step without output come from the all-zero plane.
+    template <int S>
+    __device__ __forceinline__ void fetch(int zc) {
+        const auto rh = rsrc(ub + (int64_t)(zc + R) * plane);
 #pragma unroll
-        for (int k = 0; k < NYH; ++k)
-            if (w + k * NW < 2 * R) hyv[k] = u[hy_off[k] + zo];
+        for (int v = 0; v < VY; ++v) nxt[S][v] = bload(rh, oc[v]);
 #pragma unroll
-        for (int k = 0; k < NXH; ++k)
-            if (tid + k * 64 * NW < 2 * R * TY) hxv[k] = u[hx_off[k] + zo];
+        for (int k = 0; k < NYH; ++k) hy[S][k] = bload(rh, ohy[k]);
+#pragma unroll
+        for (int k = 0; k < NXH; ++k) hx[S][k] = bload(rh, ohx[k]);
+        const bool out = zc >= z0 && zc < z1;
+        const int64_t zo = (int64_t)zc * plane;
+        const auto rp = rsrc(out ? pb + zo : zpl);
+        const auto ra = rsrc(out ? ab + zo : zpl);
 #pragma unroll
         for (int v = 0; v < VY; ++v) {
-            prv_[v] = __builtin_nontemporal_load(p.up + col + v * pitch + zo);
-            aa_[v] = __builtin_nontemporal_load(p.A + col + v * pitch + zo);
+            prv[S][v] = bload<kBufNT>(rp, oc[v]);
+            aa[S][v] = bload<kBufNT>(ra, oc[v]);
         }
-        damp_ = 0;
-        if (p.dflag) damp_ = __builtin_amdgcn_readfirstlane(
-                         (int)p.dflag[((int64_t)z * p.nty + ty) * p.ntx + tx]);
-        if (damp_) {
+        const int d = (out && flagbuf != 0) ? 1 : 0;
+        flagbuf = flag_of(zc + 1);
+        damp[S] = d;
+        const auto rs = rsrc(d ? sb + zo : zpl);
 #pragma unroll
-            for (int v = 0; v < VY; ++v) sg_[v] = p.sig[col + v * pitch + zo];
-        } else {
-#pragma unroll
-            for (int v = 0; v < VY; ++v) sg_[v] = 0.f;
-        }
-    };
+        for (int v = 0; v < VY; ++v) sg[S][v] = bload(rs, oc[v]);
+    }
 
-    // prime the queue with planes z0-R .. z0+R-1 and fetch plane z0+R
+    template <int K>
+    __device__ __forceinline__ bool step(int z) {
+        if (z >= z1) return false;
+        constexpr int S = K & 1;
+        constexpr int H = (K + 2 * R) % U;  // head plane z + R
+        constexpr int C = (K + R) % U;      // output plane z
 #pragma unroll
-    for (int k = 0; k < 2 * R; ++k)
+        for (int v = 0; v < VY; ++v) q[H][v] = nxt[S][v];
+        float* tile = lds + S * LDS_FLOATS;
 #pragma unroll
-        for (int v = 0; v < VY; ++v) q[k + 1][v] = u[col + v * pitch + (int64_t)(z0 - R + k) * plane];
+        for (int v = 0; v < VY; ++v) tile[(R + w * VY + v) * LW + R + lane] = q[H][v];
 #pragma unroll
-    for (int v = 0; v < VY; ++v) nxt[v] = u[col + v * pitch + (int64_t)(z0 + R) * plane];
-    load_plane_extras(z0, prv, aa, sg, damp);
-
-    int buf = 0;
-    for (int z = z0; z < z1; ++z) {
+        for (int k = 0; k < NYH; ++k) tile[ly_[k]] = hy[S][k];
 #pragma unroll
-        for (int k = 0; k < 2 * R; ++k)
-#pragma unroll
-            for (int v = 0; v < VY; ++v) q[k][v] = q[k + 1][v];
-#pragma unroll
-        for (int v = 0; v < VY; ++v) q[2 * R][v] = nxt[v];
-
-        float* tile = &lds[buf][0][0];
-#pragma unroll
-        for (int v = 0; v < VY; ++v) tile[(R + w * VY + v) * LW + R + lane] = q[R][v];
-#pragma unroll
-        for (int k = 0; k < NYH; ++k)
-            if (w + k * NW < 2 * R) tile[hy_row[k] * LW + R + lane] = hyv[k];
-#pragma unroll
-        for (int k = 0; k < NXH; ++k)
-            if (tid + k * 64 * NW < 2 * R * TY) tile[hx_lds[k]] = hxv[k];
+        for (int k = 0; k < NXH; ++k) tile[lx_[k]] = hx[S][k];
         __syncthreads();
 
-        // keep this plane's operands, prefetch the next plane's
-        float prv_c[VY], aa_c[VY], sg_c[VY];
-#pragma unroll
-        for (int v = 0; v < VY; ++v) {
-            prv_c[v] = prv[v];
-            aa_c[v] = aa[v];
-            sg_c[v] = sg[v];
-        }
-        const int damp_c = damp;
-        if (z + 1 < z1) {
-#pragma unroll
-            for (int v = 0; v < VY; ++v)
-                nxt[v] = u[col + v * pitch + (int64_t)(z + R + 1) * plane];
-            load_plane_extras(z + 1, prv, aa, sg, damp);
-        }
-
-        // y window of this lane's column: rows w*VY - R .. w*VY + VY + R - 1
+        // in-plane Laplacian of the head plane
         float cw[VY + 2 * R];
 #pragma unroll
         for (int k = 0; k < VY + 2 * R; ++k) cw[k] = tile[(w * VY + k) * LW + R + lane];
-
-        const int64_t zo = (int64_t)z * plane;
 #pragma unroll
         for (int v = 0; v < VY; ++v) {
             const float* row = tile + (R + w * VY + v) * LW + R + lane;
-            const float c = q[R][v];
-            float lx = 0.f, ly = 0.f, lz = 0.f;
+            float lx = 0.f, ly = 0.f;
 #pragma unroll
             for (int j = 1; j <= R; ++j) lx = fmaf(p.cx[j], row[j] + row[-j], lx);
 #pragma unroll
             for (int j = 1; j <= R; ++j) ly = fmaf(p.cy[j], cw[v + R + j] + cw[v + R - j], ly);
-#pragma unroll
-            for (int j = 1; j <= R; ++j) lz = fmaf(p.cz[j], q[R + j][v] + q[R - j][v], lz);
-            const float lap = fmaf(p.c0, c, lx + ly + lz);
-            float nv;
-            if (damp_c)
-                nv = update(c, prv_c[v], aa_c[v], lap, sg_c[v]);
-            else
-                nv = fmaf(aa_c[v], lap, 2.f * c - prv_c[v]);
-            if (xin && y0 + w * VY + v < p.L.ny)
-                __builtin_nontemporal_store(nv, p.up + col + v * pitch + zo);
+            lq[((K + R) % (R + 1)) * TY * kTileX + (w * VY + v) * kTileX + lane] = lx + ly;
         }
-        buf ^= 1;
+
+        // output plane z; the R steps before the chunk store nothing (their
+        // store buffer has a zero record limit), so every step issues the
+        // same memory operations
+        const auto ro = __builtin_amdgcn_make_buffer_rsrc(pb + (int64_t)z * plane, 0,
+                                                          z >= z0 ? kRecords : 0, 0x00020000);
+        float nv[VY];
+#pragma unroll
+        for (int v = 0; v < VY; ++v) {
+            float lz = 0.f;
+#pragma unroll
+            for (int j = 1; j <= R; ++j)
+                lz = fmaf(p.cz[j], q[(C + j) % U][v] + q[(C + U - j) % U][v], lz);
+            const float lxy = lq[(K % (R + 1)) * TY * kTileX + (w * VY + v) * kTileX + lane];
+            const float lap = fmaf(p.c0, q[C][v], lxy + lz);
+            nv[v] = fmaf(aa[S][v], lap, 2.f * q[C][v] - prv[S][v]);
+            if (damp[S]) {
+                const float sv = sg[S][v];
+                nv[v] = (2.f * q[C][v] - (1.f - sv) * prv[S][v] + aa[S][v] * lap) / (1.f + sv);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < VY; ++v) bstore_nt(ro, oc[v], nv[v]);
+        fetch<S>(z + 2);
+        return true;
     }
+
+    template <int... Ks>
+    __device__ __forceinline__ bool period(int zb, std::integer_sequence<int, Ks...>) {
+        return (step<Ks>(zb + Ks) && ...);
+    }
+
+    __device__ void run() {
+        const int b = blockIdx.x;
+        const int t = (b & 7) * (p.nblocks >> 3) + (b >> 3);
+        if (t >= p.ntiles) return;
+        ntx = p.ntx;
+        nty = p.nty;
+        tx = t % ntx;
+        const int t2 = t / ntx;
+        ty = t2 % nty;
+        const int zc = t2 / nty;
+        const int x0 = tx * kTileX, y0 = ty * TY;
+        const int nx = p.L.nx, ny = p.L.ny;
+        nz = p.L.nz;
+        z0 = zc * p.zchunk;
+        z1 = min(z0 + p.zchunk, nz);
+        const int tid = threadIdx.x;
+        lane = tid & 63;
+        w = tid >> 6;
+        plane = p.L.plane;
+        const int pitch = p.L.pitch;
+        const int64_t org = p.L.origin + (int64_t)(y0 - R) * pitch + (x0 - R);
+        ub = p.uc + org;
+        pb = p.up + org;
+        ab = p.A + org;
+        sb = (p.sig ? p.sig : p.A) + org;
+        zpl = p.A + org - (int64_t)kGhostYZ * plane;
+        flags = (cflag_t*)p.dflag;
+        // offsets of tile point (row r, column c), r/c counted from (y0 - R, x0 - R)
+        auto off = [&](int r, int c) -> uint32_t {
+            const int y = y0 - R + r, x = x0 - R + c;
+            return (x >= 0 && x < nx && y >= 0 && y < ny) ? (uint32_t)((r * pitch + c) * 4)
+                                                           : kOOB;
+        };
+#pragma unroll
+        for (int v = 0; v < VY; ++v) oc[v] = off(R + w * VY + v, R + lane);
+        const int sink = (LH - 1) * LW + lane;
+#pragma unroll
+        for (int k = 0; k < NYH; ++k) {
+            const int hr = w + k * NW;
+            const int row = hr < R ? hr : TY + hr;
+            const bool on = hr < 2 * R;
+            ohy[k] = on ? off(row, R + lane) : kOOB;
+            ly_[k] = on ? row * LW + R + lane : sink;
+        }
+#pragma unroll
+        for (int k = 0; k < NXH; ++k) {
+            const int e = tid + k * 64 * NW;
+            const int row = e / (2 * R), cc = e % (2 * R);
+            const int col = cc < R ? cc : kTileX + cc;
+            const bool on = e < 2 * R * TY;
+            ohx[k] = on ? off(R + row, col) : kOOB;
+            lx_[k] = on ? (R + row) * LW + col : (LH - 1) * LW + (tid & 63);
+        }
+        // The loop starts R steps before the chunk so that planes z0 .. z0+R-1
+        // enter as heads; those steps produce no output.  Queue index i holds
+        // plane zs - R + i (mod U); planes z0-R .. z0-1 are primed here.
+        const int zs = z0 - R;
+#pragma unroll
+        for (int i = 0; i < U; ++i)
+#pragma unroll
+            for (int v = 0; v < VY; ++v) q[i][v] = 0.f;
+#pragma unroll
+        for (int i = R; i < 2 * R; ++i) {
+            const auto r = rsrc(ub + (int64_t)(zs - R + i) * plane);
+#pragma unroll
+            for (int v = 0; v < VY; ++v) q[i][v] = bload(r, oc[v]);
+        }
+        flagbuf = flag_of(zs);
+        fetch<0>(zs);
+        fetch<1>(zs + 1);
+        for (int zb_ = zs; period(zb_, std::make_integer_sequence<int, U>{}); zb_ += U) {
+        }
+    }
+};
+
+template <int R, int NW, int VY>
+__global__ __launch_bounds__(64 * NW) void acoustic3d_tiled(AcousticStep p) {
+    using T = TiledAcoustic<R, NW, VY>;
+    __shared__ float lds[2 * T::LDS_FLOATS + T::LQ_FLOATS];
+    TiledAcoustic<R, NW, VY> k(p, lds, lds + 2 * T::LDS_FLOATS);
+    k.run();
 }
 
 template <int R>
@@ -236,28 +338,29 @@ hipError_t launch_tiled(const AcousticStep& p, hipStream_t s) {
 }
 
 template <int R>
-hipError_t launch_tiled_vy(const AcousticStep& p, int vy, hipStream_t s) {
-    switch (vy) {
-        case 2: return launch_tiled<R, 4, 2>(p, s);
-        case 4: return launch_tiled<R, 4, 4>(p, s);
-        case 8: return launch_tiled<R, 4, 8>(p, s);
+hipError_t launch_tiled_cfg(const AcousticStep& p, int cfg, hipStream_t s) {
+    switch (cfg) {
+        case 0: return launch_tiled<R, 4, 2>(p, s);   // 64 x 8 tile
+        case 1: return launch_tiled<R, 4, 4>(p, s);   // 64 x 16
+        case 2: return launch_tiled<R, 8, 1>(p, s);   // 64 x 8, 512 threads
+        case 3: return launch_tiled<R, 8, 2>(p, s);   // 64 x 16, 512 threads
         default: return hipErrorInvalidValue;
     }
 }
 
 }  // namespace
 
-int acoustic_tile_y(int radius, int vy) {
-    (void)radius;
-    return 4 * vy;
+int acoustic_tile_y(int cfg) {
+    static const int ty[4] = {8, 16, 8, 16};
+    return cfg >= 0 && cfg < 4 ? ty[cfg] : 8;
 }
 
-hipError_t launch_acoustic(const AcousticStep& p, int ndim, int radius, int variant, int vy,
+hipError_t launch_acoustic(const AcousticStep& p, int ndim, int radius, int variant, int cfg,
                            hipStream_t s) {
     const bool tiled = ndim == 3 && variant == 0;
 #define FD_CASE(RR)                                                     \
     case RR:                                                            \
-        return tiled ? launch_tiled_vy<RR>(p, vy, s) : launch_direct<RR>(p, ndim, s);
+        return tiled ? launch_tiled_cfg<RR>(p, cfg, s) : launch_direct<RR>(p, ndim, s);
     switch (radius) {
         FD_CASE(1)
         FD_CASE(2)

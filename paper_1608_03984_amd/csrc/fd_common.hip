@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void setup_kernel(SetupArgs a) {
 // flags[(z * nty + ty) * ntx + tx] = 1 when any damping coefficient in the
 // 64 x tile_y tile (tx, ty) of plane z is non-zero.
 __global__ __launch_bounds__(kBlock) void damping_flags_kernel(const float* __restrict__ sig,
-                                                               uint8_t* flags, Layout L,
+                                                               int32_t* flags, Layout L,
                                                                int tile_y, int ntx, int nty) {
     const int tile = blockIdx.x;
     const int z = blockIdx.y;
@@ -204,7 +204,7 @@ hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_damping_flags(const float* sig, uint8_t* flags, const Layout& L, int tile_y,
+hipError_t launch_damping_flags(const float* sig, int32_t* flags, const Layout& L, int tile_y,
                                 int ntx, int nty, hipStream_t s) {
     hipLaunchKernelGGL(damping_flags_kernel, dim3(ntx * nty, L.nz), dim3(kBlock), 0, s, sig,
                        flags, L, tile_y, ntx, nty);

@@ -10,6 +10,8 @@ namespace fd {
 constexpr int kMaxRadius = 8;   // space order 16
 constexpr int kGhostX = 32;     // zero columns left of x = 0 (128 B: rows start line-aligned)
 constexpr int kGhostYZ = 8;     // zero rows / planes beyond each y and z edge (>= kMaxRadius)
+constexpr int kGhostZTop = 12;  // zero planes above the last z plane: kMaxRadius plus the
+                                // two planes a streaming kernel may prefetch past its end
 constexpr int kTileX = 64;      // one wave64 spans the x extent of a tile
 
 // One padded volume in HBM.  Interior point (x, y, z) of the caller's
@@ -17,7 +19,8 @@ constexpr int kTileX = 64;      // one wave64 spans the x extent of a tile
 // ghost cells around the interior is zero and never written, so stencil
 // reads need no bounds checks (homogeneous Dirichlet boundary).  The pitch
 // and the row count are rounded up so that the last, ragged tile of any
-// kernel reads only ghost cells past the interior.
+// kernel reads only ghost cells past the interior; the planes below z = 0
+// are also the all-zero source of the tiled kernels' undamped loads.
 struct Layout {
     int32_t nx, ny, nz;   // interior sizes (padded problem shape)
     int32_t pitch;        // floats per row
@@ -43,7 +46,7 @@ struct AcousticStep {
     float* up;                     // u^{n-1} in, u^{n+1} out
     const float* __restrict__ A;   // dt^2 v^2
     const float* __restrict__ sig; // eta dt / 2, or nullptr
-    const uint8_t* __restrict__ dflag; // per (z, tile) "layer has damping" or nullptr
+    const int32_t* __restrict__ dflag; // per (z, tile): 1 if the tile-plane holds damping
     float c0;
     float cx[kMaxRadius + 1], cy[kMaxRadius + 1], cz[kMaxRadius + 1];
     Layout L;
@@ -62,7 +65,7 @@ struct TTIStep {
     float* rp;  // r^{n-1} in, r^{n+1} out
     const float* __restrict__ A;
     const float* __restrict__ sig;
-    const uint8_t* __restrict__ dflag;
+    const int32_t* __restrict__ dflag;
     const float* __restrict__ e;
     const float* __restrict__ d;
     const float* __restrict__ c[6];
@@ -99,7 +102,7 @@ struct SetupArgs {
     Layout L;
 };
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
-hipError_t launch_damping_flags(const float* sig, uint8_t* flags, const Layout& L, int tile_y,
+hipError_t launch_damping_flags(const float* sig, int32_t* flags, const Layout& L, int tile_y,
                                 int ntx, int nty, hipStream_t s);
 
 // sparse points
@@ -110,12 +113,12 @@ hipError_t launch_record(const float* u, const SparsePoint* pts, int n, float* o
                          const Layout& L, int ndim, hipStream_t s);
 
 // stencils
-hipError_t launch_acoustic(const AcousticStep& p, int ndim, int radius, int variant, int vy,
+hipError_t launch_acoustic(const AcousticStep& p, int ndim, int radius, int variant, int tile_cfg,
                            hipStream_t s);
 hipError_t launch_tti(const TTIStep& p, int radius, int variant, hipStream_t s);
 
-// Tile height (rows) of the tiled acoustic kernel for a given radius / VY.
-int acoustic_tile_y(int radius, int vy);
+// Tile height (rows) of the tiled acoustic kernel for a tile configuration.
+int acoustic_tile_y(int tile_cfg);
 int tti_tile_y(int radius);
 
 }  // namespace fd

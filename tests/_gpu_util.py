@@ -45,7 +45,8 @@ def acoustic_problem(ndim, phys, nbl, so, nt, seed, h=(10.0, 10.0, 10.0), dampin
     else:
         src = np.array([[0.37 * nx * h[0] + 3.3, 0.52 * ny * h[1] - 2.1, 0.41 * nz * h[2] + 1.7]])
         xs = np.linspace(-nbl * h[0], (nx + nbl - 1) * h[0], nrec)
-        rec = np.stack([xs, np.full(nrec, 0.5 * ny * h[1] + 0.5 * h[1]), np.full(nrec, 2.0 * h[2])], 1)
+        yr = 0.5 * (ny - 1) * h[1] + 0.25 * h[1] if ny > 1 else 0.0
+        rec = np.stack([xs, np.full(nrec, yr), np.full(nrec, 2.0 * h[2])], 1)
         rec[::2, 0] = np.round(rec[::2, 0] / h[0]) * h[0]
     return Problem("test", ndim, "acoustic", (nx, ny if ndim == 3 else 1, nz), h, nbl, so, dt, nt,
                    f0, vel, eta, src, rec, q, seed=seed)
@@ -119,6 +120,6 @@ def tti_problem(phys, nbl, so, nt, seed, h=(12.5, 12.5, 12.5), nrec=20):
     src = np.array([[0.45 * nx * h[0] + 1.1, 0.5 * ny * h[1] - 2.3, 0.4 * nz * h[2] + 0.7]])
     xs = np.linspace(-nbl * h[0], (nx + nbl - 1) * h[0], nrec)
     rec = np.stack([xs, np.full(nrec, 0.5 * ny * h[1]), np.full(nrec, 2.0 * h[2])], 1)
-    rec[1::2, 0] += 0.3 * h[0]
+    rec[1::2, 0] -= 0.3 * h[0]   # odd receivers off grid, all inside the array
     return Problem("tti-test", 3, "tti", (nx, ny, nz), h, nbl, so, dt, nt, f0, vel, eta, src, rec,
                    q, eps=eps, delta=delta, theta=theta, phi=phi, seed=seed)

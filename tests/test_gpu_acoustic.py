@@ -23,12 +23,12 @@ pytestmark = pytest.mark.gpu
 ORDERS = [2, 4, 6, 8, 10, 12, 14, 16]
 
 
-def gpu_run(p, variant=0, vy=0, zchunk=0):
+def gpu_run(p, variant=0, tile=None, zchunk=0):
     s = from_problem(p)
     if variant:
         s.set_option(P.FD_OPT_KERNEL, variant)
-    if vy:
-        s.set_option(P.FD_OPT_VY, vy)
+    if tile is not None:
+        s.set_option(P.FD_OPT_TILE, tile)
     if zchunk:
         s.set_option(P.FD_OPT_ZCHUNK, zchunk)
     tr = s.forward(p.nt, p.src, p.wavelet, p.rec)
@@ -64,13 +64,15 @@ def test_acoustic_3d_multi_tile_full_run(so, variant):
     assert et < 1e-4 and eu < 1e-4
 
 
-@pytest.mark.parametrize("vy", [2, 4, 8])
-@pytest.mark.parametrize("so", [4, 16])
-def test_acoustic_3d_tile_shapes(so, vy):
-    """Every built row-blocking of the tiled kernel, short z chunks."""
-    p = acoustic_problem(3, (70, 50, 30), 6, so, 40, seed=7 + vy)
-    say(f"case: tile shapes so{so} vy{vy}")
-    tr, u = gpu_run(p, vy=vy, zchunk=2 * so + 3)
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+@pytest.mark.parametrize("so", [2, 4, 12, 16])
+@pytest.mark.parametrize("zchunk", [0, 5, 23])
+def test_acoustic_3d_tile_shapes(so, tile, zchunk):
+    """Every built tile shape of the tiled kernel, with z chunks shorter and
+    longer than the stencil radius and the unrolled queue period."""
+    p = acoustic_problem(3, (70, 50, 30), 6, so, 40, seed=7 + tile)
+    say(f"case: tile shapes so{so} tile{tile} zchunk{zchunk}")
+    tr, u = gpu_run(p, tile=tile, zchunk=zchunk)
     tref, st, peak = oracle_run_with_peak(p, chunk=40)
     assert rel(tr, tref) < 1e-4
     assert np.linalg.norm(u - st[1]) / peak < 1e-4
@@ -201,6 +203,6 @@ def test_acoustic_error_paths():
         s.forward(2, np.array([[1e6, 0.0, 0.0]]), p.wavelet, p.rec)
     assert e.value.code == P.FD_ERR_INVALID_ARG and "outside" in str(e.value)
     with pytest.raises(P.FdError):
-        s.set_option(P.FD_OPT_VY, 3)
+        s.set_option(P.FD_OPT_TILE, 4)
     s.close()
     del g
