@@ -13,14 +13,22 @@ in HBM, timed with events on the launch stream between two synchronisations).
 Printed (one JSON line): value = Gpt/s over the sweep (total point updates /
 total time), the per-order figures, the roofline of the stencil kernel
 (algorithmic 16 bytes per point update / the kernel's average launch time,
-measured in a second timed loop that launches only the stencil), and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+measured in a second timed loop that launches only the stencil), the STREAM
+triad bandwidth measured the same way (the practical ceiling of section 3.1),
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+`roofline.traffic` is the calibrated HBM traffic per launch from the committed
+rocprofv3 counter summary, reported only while the kernel source is unchanged.
+
+`--profile-pass` is the driver for counter collection: it launches 3 triads of
+2^26 floats and then 3 stencil-only steps per order, and prints nothing else.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 from pathlib import Path
@@ -31,6 +39,8 @@ ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+TRAFFIC_SUMMARY = ROOT / "profiles" / "acoustic3d_tiled_592cubed_traffic.md"
+KERNEL_SOURCE = ROOT / "paper_1608_03984_amd" / "csrc" / "fd_acoustic.hip"
 BYTES_PER_POINT = 16           # read u^n, u^{n-1}, dt^2 v^2; write u^{n+1}
 ORDERS = (4, 8, 12, 16)
 
@@ -50,7 +60,72 @@ def parse():
     ap.add_argument("--phys", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile-pass", action="store_true")
+    ap.add_argument("--workload", choices=("acoustic", "tti"), default="acoustic")
     return ap.parse_args()
+
+
+def committed_traffic(phys: int):
+    """Per-order HBM bytes per launch from the committed counter summary, or
+    None when the summary is missing, for another size, or older than the
+    kernel source."""
+    if phys != 512 or not TRAFFIC_SUMMARY.exists():
+        return None
+    m = re.search(r"<!-- machine-readable: (.*) -->", TRAFFIC_SUMMARY.read_text())
+    if not m:
+        return None
+    data = json.loads(m.group(1))
+    if data["source_sha256_16"] != hashlib.sha256(KERNEL_SOURCE.read_bytes()).hexdigest()[:16]:
+        return None
+    return {int(k): v["traffic_bytes"] for k, v in data["per_order"].items()}
+
+
+def triad_gbs(torch, P):
+    """STREAM-style triad bandwidth (2^28 floats per array), events on the
+    launch stream."""
+    n = 1 << 28
+    dev = torch.device("cuda:0")
+    a = torch.empty(n, device=dev)
+    b = torch.ones(n, device=dev)
+    c = torch.ones(n, device=dev)
+    st = torch.cuda.current_stream().cuda_stream
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    P.fd_triad(a.data_ptr(), b.data_ptr(), c.data_ptr(), 2.0, n, st)
+    t = timed(lambda: [P.fd_triad(a.data_ptr(), b.data_ptr(), c.data_ptr(), 2.0, n, st)
+                       for _ in range(10)], ev) / 10
+    ok = float(a[n - 1].item()) == 3.0
+    del a, b, c
+    torch.cuda.empty_cache()
+    return 12 * n / t / 1e9 if ok else None
+
+
+def profile_pass(args):
+    import torch
+
+    import paper_1608_03984_amd as P
+    from paper_1608_03984_amd.solver import Solver
+    from workloads import DT, acoustic_3d
+
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream().cuda_stream
+    n = 1 << 26
+    a = torch.empty(n, device=dev)
+    b = torch.ones(n, device=dev)
+    c = torch.ones(n, device=dev)
+    for _ in range(3):
+        P.fd_triad(a.data_ptr(), b.data_ptr(), c.data_ptr(), 2.0, n, st)
+    torch.cuda.synchronize()
+    del a, b, c
+    prob = acoustic_3d(so=8, phys=args.phys, nbl=40, nt=1, receivers="none")
+    for so in [int(x) for x in args.orders.split(",")]:
+        s = Solver(3, prob.shape, prob.spacing, prob.nbl, so, DT[("acoustic_3d", so)], prob.vel,
+                   prob.eta, max_points=4, device=dev)
+        s.forward(3, zero_state=False)
+        torch.cuda.synchronize()
+        print(f"# profile pass so{so} done", file=sys.stderr, flush=True)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
 
 
 def timed(fn, stream_events):
@@ -104,12 +179,64 @@ def cpu_baseline(problem, seconds: float):
     }
 
 
+def tti_bench(args):
+    """TTI pseudo-acoustic, 384^3 + 40-point layer (464^3), space order 8:
+    60 algorithmic bytes and 964 paper FLOPs per point update (Table 1)."""
+    import torch
+
+    from paper_1608_03984_amd.solver import Solver
+    from workloads import tti_3d
+
+    phys = 384 if args.phys == 512 else args.phys
+    p = tti_3d(so=8, phys=phys, nbl=40, nt=1, receivers="line")
+    npts = p.npoints
+    dev = torch.device("cuda:0")
+    nt = args.warmup + args.steps
+    from workloads import ricker
+    wav = torch.from_numpy(ricker(10.0, p.dt, nt)[:, None]).to(dev)
+    traces = torch.empty((nt, p.rec.shape[0]), dtype=torch.float32, device=dev)
+    s = Solver(3, p.shape, p.spacing, p.nbl, 8, p.dt, p.vel, p.eta, physics="tti",
+               epsilon=p.eps, delta=p.delta, theta=p.theta, phi=p.phi,
+               max_points=1 + p.rec.shape[0], device=dev)
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    s.forward(args.warmup, p.src, wav[:args.warmup], p.rec, traces=traces[:args.warmup])
+    tw = timed(lambda: s.forward(args.steps, p.src, wav[args.warmup:], p.rec, zero_state=False,
+                                 traces=traces[args.warmup:]), ev)
+    s.forward(args.warmup, zero_state=False)
+    tk = timed(lambda: s.forward(args.steps, zero_state=False), ev)
+    ok = bool(torch.isfinite(traces).all().item())
+    s.close()
+    kernel_s = tk / args.steps
+    ach = 60 * npts / kernel_s / 1e9
+    line = {
+        "metric": "Gpt/s (3D TTI so8)", "value": round(npts * args.steps / tw / 1e9, 3),
+        "unit": "Gpt/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(tw / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"3D TTI, {phys}^3 + 40-pt layer ({p.padded[0]}^3 points), "
+                               "h=12.5 m, layered v, smooth eps/delta/theta/phi, so 8",
+                   "points": npts},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "TTI stencil"},
+        "gflops_paper": round(964 * npts / kernel_s / 1e9, 1),
+        "stencil_ms": round(kernel_s * 1e3, 4), "finite": ok,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not "
                                    "supported (the solver has no multi-GPU path)"}))
         sys.exit(2)
+    if args.profile_pass:
+        profile_pass(args)
+        return
+    if args.workload == "tti":
+        tti_bench(args)
+        return
     import torch
 
     import paper_1608_03984_amd as P
@@ -117,6 +244,7 @@ def main():
     from workloads import DT, acoustic_3d
 
     orders = [int(s) for s in args.orders.split(",")]
+    traffic = committed_traffic(args.phys)
     t0 = time.perf_counter()
     prob = acoustic_3d(so=8, phys=args.phys, nbl=40, nt=1, receivers="surface")
     print(f"# model generated in {time.perf_counter() - t0:.1f} s, padded {prob.padded}",
@@ -154,6 +282,7 @@ def main():
         per.append({"so": so, "gpts": round(gpts, 2), "ms_per_step": round(tw / args.steps * 1e3, 4),
                     "stencil_ms": round(kernel_ms, 4), "stencil_gbs": round(achieved, 1),
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": traffic.get(so) if traffic else None,
                     "gflops_paper": round(paper_flops(so) * npts / (kernel_ms / 1e3) / 1e9, 1),
                     "finite": ok})
         print(f"# so{so}: {gpts:.1f} Gpt/s, stencil {kernel_ms:.3f} ms = {achieved:.0f} GB/s",
@@ -163,6 +292,9 @@ def main():
         tot_kernel += tk
     value = tot_pts / tot_time / 1e9
     ach = BYTES_PER_POINT * tot_pts / tot_kernel / 1e9
+    tgbs = triad_gbs(torch, P)
+    mean_traffic = (round(sum(traffic[so] for so in orders) / len(orders))
+                    if traffic and all(so in traffic for so in orders) else None)
     line = {
         "metric": "Gpt/s, % roofline (3D acoustic SO4-16)",
         "value": round(value, 3),
@@ -181,8 +313,12 @@ def main():
                                f"smooth perturbation, 1 Ricker source, {rec.shape[0]} receivers",
                    "space_orders": orders, "points": npts},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "acoustic3d_tiled (sweep aggregate)"},
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": mean_traffic,
+                     "kernel": "acoustic3d_tiled (sweep aggregate; traffic = mean bytes per "
+                               "launch over the orders)"},
+        "triad_gbs": round(tgbs, 1) if tgbs else None,
+        "frac_of_triad": round(ach / tgbs, 4) if tgbs else None,
         "per_order": per,
     }
     if not args.no_cpu_baseline:
