@@ -10,6 +10,8 @@
 // traffic: 15 fields x 4 bytes = 60 bytes per point (section 4.2).
 #include "fd_internal.h"
 
+#include <utility>
+
 namespace fd {
 
 namespace {
@@ -91,6 +93,331 @@ __global__ __launch_bounds__(256) void tti_direct(TTIStep p) {
     p.rp[i] = rn;
 }
 
+// ---------------------------------------------------------------------------
+// Tiled TTI kernel (2.5D blocking), one row per lane, 64 x NW tiles.
+//
+// Each plane of p and r enters the block once, as the head of the z pipeline,
+// R planes before it is output, staged in LDS with its full R-wide halo
+// (corners included: the mixed derivative needs them).  At head time the
+// lane computes, for f in {p, r}:
+//   Dxx f, Dyy f, gx = D1x f, gy = D1y f (gy also on the x-halo columns, into
+//   an LDS tile), then Dxy f = D1x(gy);
+//   the in-plane parts  Dxx p + Dyy p  and  c1 Dxx f + c2 Dyy f + c4 Dxy f
+//   (c1, c2, c4 of the head plane), parked in an LDS ring until output.
+// f, gx and gy go into per-lane register queues; at output time
+//   Dzz f = D2z(f queue),  Dxz f = D1z(gx queue),  Dyz f = D1z(gy queue),
+// which is the product-of-first-derivatives form of the mixed terms (the
+// same sum the zero-ghost stencil gives).  G_zbar_zbar f adds c3 Dzz + c5 Dyz
+// + c6 Dxz (c's of the output plane), H p = Laplacian p - G_zbar_zbar p, and
+// the update of Eq. (TTI) writes p^{n+1}, r^{n+1} over p^{n-1}, r^{n-1}.
+//
+// Operands are prefetched two steps ahead into register slots, the z loop is
+// unrolled by the queue period U = 2R+2, loads and stores are raw buffer
+// accesses with out-of-range offsets for ghost points, and the 2R steps
+// before a chunk only fill the pipeline (their stores have a zero record
+// limit).  Two barriers per step: one after staging p and r, one after
+// staging gy.
+// ---------------------------------------------------------------------------
+typedef const __attribute__((address_space(4))) int32_t tflag_t;
+constexpr uint32_t kOOBt = 0x80000000u;
+constexpr int kRecordsT = 0x7fffffff;
+constexpr int kNT = 2;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t trsrc(const float* base, int rec = kRecordsT) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, rec, 0x00020000);
+}
+template <int AUX = 0>
+__device__ __forceinline__ float tload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+}
+__device__ __forceinline__ void tstore(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, kNT);
+}
+
+template <int R, int NW>
+struct TiledTTI {
+    static constexpr int TY = NW;
+    static constexpr int LW = kTileX + 2 * R;
+    static constexpr int LH = TY + 2 * R;
+    static constexpr int FT = (LH + 1) * LW;  // staged field tile (+1 sink row)
+    static constexpr int GT = TY * LW;        // gy on the x-extended rows
+    static constexpr int U = 2 * R + 2;
+    static constexpr int NHALO = LH * LW - TY * kTileX;
+    static constexpr int NH = (NHALO + 64 * NW - 1) / (64 * NW);
+    static constexpr int NGX = 2 * R * TY;     // x-halo gy points
+    static constexpr int RING = (R + 1) * TY * kTileX;
+    static constexpr int LDS_FLOATS = 2 * FT + 2 * GT + 3 * RING;
+
+    const TTIStep& p;
+    float* fp_t;   // staged p tile
+    float* fr_t;   // staged r tile
+    float* gp_t;   // gy of p
+    float* gr_t;   // gy of r
+    float* ring;   // [3][R+1][TY][64]: Dxx p + Dyy p, c1 Dxx p + c2 Dyy p + c4 Dxy p, same for r
+    const float *pb, *rb, *ab, *eb, *db, *sb, *zpl;
+    const float* cb[6];
+    float *ppb, *rpb;
+    tflag_t* flags;
+    int64_t plane;
+    int z0, z1, nz, tx, ty, ntx, nty, lane, w, tid;
+    int flagbuf;
+    uint32_t oc;            // own point offset (kOOBt outside the interior)
+    uint32_t oh[NH];        // halo element offsets
+    int lh[NH];             // halo element LDS index
+    bool gx_on;             // this thread computes one x-halo gy point
+    int gxf, gxg;           // its f-tile index (row, col) and gy-tile index
+    float fqp[U], fqr[U], gxp[U], gxr[U], gyp[U], gyr[U];
+    // slots
+    float hp_c[2], hr_c[2], hp_h[2][NH], hr_h[2][NH], c1h[2], c2h[2], c4h[2];
+    float opp[2], orp[2], oa[2], oe[2], od[2], oc3[2], oc5[2], oc6[2], osg[2];
+    int damp[2];
+
+    __device__ TiledTTI(const TTIStep& ps, float* lds) : p(ps) {
+        fp_t = lds;
+        fr_t = lds + FT;
+        gp_t = lds + 2 * FT;
+        gr_t = lds + 2 * FT + GT;
+        ring = lds + 2 * FT + 2 * GT;
+    }
+
+    __device__ __forceinline__ int flag_of(int z) const {
+        if (z < 0 || z >= nz) return 0;
+        return flags[((int64_t)z * nty + ty) * ntx + tx];
+    }
+
+    template <int S>
+    __device__ __forceinline__ void fetch(int zc) {
+        const int64_t zh = (int64_t)(zc + R) * plane;
+        const auto rp = trsrc(pb + zh), rr = trsrc(rb + zh);
+        hp_c[S] = tload(rp, oc);
+        hr_c[S] = tload(rr, oc);
+#pragma unroll
+        for (int k = 0; k < NH; ++k) {
+            hp_h[S][k] = tload(rp, oh[k]);
+            hr_h[S][k] = tload(rr, oh[k]);
+        }
+        c1h[S] = tload<kNT>(trsrc(cb[0] + zh), oc);
+        c2h[S] = tload<kNT>(trsrc(cb[1] + zh), oc);
+        c4h[S] = tload<kNT>(trsrc(cb[3] + zh), oc);
+        const bool out = zc >= z0 && zc < z1;
+        const int64_t zo = (int64_t)zc * plane;
+        opp[S] = tload<kNT>(trsrc(out ? ppb + zo : zpl), oc);
+        orp[S] = tload<kNT>(trsrc(out ? rpb + zo : zpl), oc);
+        oa[S] = tload<kNT>(trsrc(out ? ab + zo : zpl), oc);
+        oe[S] = tload<kNT>(trsrc(out ? eb + zo : zpl), oc);
+        od[S] = tload<kNT>(trsrc(out ? db + zo : zpl), oc);
+        oc3[S] = tload<kNT>(trsrc(out ? cb[2] + zo : zpl), oc);
+        oc5[S] = tload<kNT>(trsrc(out ? cb[4] + zo : zpl), oc);
+        oc6[S] = tload<kNT>(trsrc(out ? cb[5] + zo : zpl), oc);
+        const int d = (out && flagbuf != 0) ? 1 : 0;
+        flagbuf = flag_of(zc + 1);
+        damp[S] = d;
+        osg[S] = tload(trsrc(d ? sb + zo : zpl), oc);
+    }
+
+    template <int K>
+    __device__ __forceinline__ bool step(int z) {
+        if (z >= z1) return false;
+        constexpr int S = K & 1;
+        constexpr int H = (K + 2 * R) % U;
+        constexpr int C = (K + R) % U;
+        constexpr int RH = (K + R) % (R + 1);  // ring slot of the head plane
+        constexpr int RC = K % (R + 1);        // ring slot of the output plane
+        const int fc = (R + w) * LW + R + lane;  // own point in the field tile
+        // stage the head planes of p and r
+        fqp[H] = hp_c[S];
+        fqr[H] = hr_c[S];
+        fp_t[fc] = hp_c[S];
+        fr_t[fc] = hr_c[S];
+#pragma unroll
+        for (int k = 0; k < NH; ++k) {
+            fp_t[lh[k]] = hp_h[S][k];
+            fr_t[lh[k]] = hr_h[S][k];
+        }
+        __syncthreads();
+
+        // first and second derivatives of the head plane at the own point
+        float dxx_p = p.w2x[0] * fp_t[fc], dxx_r = p.w2x[0] * fr_t[fc];
+        float dyy_p = p.w2y[0] * fp_t[fc], dyy_r = p.w2y[0] * fr_t[fc];
+        float gx_p = 0.f, gx_r = 0.f, gy_p = 0.f, gy_r = 0.f;
+#pragma unroll
+        for (int j = 1; j <= R; ++j) {
+            const float ap = fp_t[fc + j], bp = fp_t[fc - j];
+            const float ar = fr_t[fc + j], br = fr_t[fc - j];
+            dxx_p = fmaf(p.w2x[j], ap + bp, dxx_p);
+            dxx_r = fmaf(p.w2x[j], ar + br, dxx_r);
+            gx_p = fmaf(p.w1x[j], ap - bp, gx_p);
+            gx_r = fmaf(p.w1x[j], ar - br, gx_r);
+            const float cp = fp_t[fc + j * LW], dp = fp_t[fc - j * LW];
+            const float cr = fr_t[fc + j * LW], dr = fr_t[fc - j * LW];
+            dyy_p = fmaf(p.w2y[j], cp + dp, dyy_p);
+            dyy_r = fmaf(p.w2y[j], cr + dr, dyy_r);
+            gy_p = fmaf(p.w1y[j], cp - dp, gy_p);
+            gy_r = fmaf(p.w1y[j], cr - dr, gy_r);
+        }
+        gxp[H] = gx_p;
+        gxr[H] = gx_r;
+        gyp[H] = gy_p;
+        gyr[H] = gy_r;
+        const int gc = w * LW + R + lane;
+        gp_t[gc] = gy_p;
+        gr_t[gc] = gy_r;
+        if (gx_on) {
+            float a = 0.f, b = 0.f;
+#pragma unroll
+            for (int j = 1; j <= R; ++j) {
+                a = fmaf(p.w1y[j], fp_t[gxf + j * LW] - fp_t[gxf - j * LW], a);
+                b = fmaf(p.w1y[j], fr_t[gxf + j * LW] - fr_t[gxf - j * LW], b);
+            }
+            gp_t[gxg] = a;
+            gr_t[gxg] = b;
+        }
+        __syncthreads();
+        float dxy_p = 0.f, dxy_r = 0.f;
+#pragma unroll
+        for (int j = 1; j <= R; ++j) {
+            dxy_p = fmaf(p.w1x[j], gp_t[gc + j] - gp_t[gc - j], dxy_p);
+            dxy_r = fmaf(p.w1x[j], gr_t[gc + j] - gr_t[gc - j], dxy_r);
+        }
+        const int rw = w * kTileX + lane;
+        ring[(0 * (R + 1) + RH) * TY * kTileX + rw] = dxx_p + dyy_p;
+        ring[(1 * (R + 1) + RH) * TY * kTileX + rw] =
+            fmaf(c1h[S], dxx_p, fmaf(c2h[S], dyy_p, c4h[S] * dxy_p));
+        ring[(2 * (R + 1) + RH) * TY * kTileX + rw] =
+            fmaf(c1h[S], dxx_r, fmaf(c2h[S], dyy_r, c4h[S] * dxy_r));
+
+        // output plane z
+        const float lap_in = ring[(0 * (R + 1) + RC) * TY * kTileX + rw];
+        const float gzin_p = ring[(1 * (R + 1) + RC) * TY * kTileX + rw];
+        const float gzin_r = ring[(2 * (R + 1) + RC) * TY * kTileX + rw];
+        float dzz_p = p.w2z[0] * fqp[C], dzz_r = p.w2z[0] * fqr[C];
+        float dxz_p = 0.f, dxz_r = 0.f, dyz_p = 0.f, dyz_r = 0.f;
+#pragma unroll
+        for (int j = 1; j <= R; ++j) {
+            constexpr int dummy = 0;
+            (void)dummy;
+            dzz_p = fmaf(p.w2z[j], fqp[(C + j) % U] + fqp[(C + U - j) % U], dzz_p);
+            dzz_r = fmaf(p.w2z[j], fqr[(C + j) % U] + fqr[(C + U - j) % U], dzz_r);
+            dxz_p = fmaf(p.w1z[j], gxp[(C + j) % U] - gxp[(C + U - j) % U], dxz_p);
+            dxz_r = fmaf(p.w1z[j], gxr[(C + j) % U] - gxr[(C + U - j) % U], dxz_r);
+            dyz_p = fmaf(p.w1z[j], gyp[(C + j) % U] - gyp[(C + U - j) % U], dyz_p);
+            dyz_r = fmaf(p.w1z[j], gyr[(C + j) % U] - gyr[(C + U - j) % U], dyz_r);
+        }
+        const float gz_p = gzin_p + oc3[S] * dzz_p + oc5[S] * dyz_p + oc6[S] * dxz_p;
+        const float gz_r = gzin_r + oc3[S] * dzz_r + oc5[S] * dyz_r + oc6[S] * dxz_r;
+        const float h_p = (lap_in + dzz_p) - gz_p;
+        const float fpv = oa[S] * (oe[S] * h_p + od[S] * gz_r);
+        const float frv = oa[S] * (od[S] * h_p + gz_r);
+        const float pc = fqp[C], rc = fqr[C];
+        float pn = (2.f * pc - opp[S]) + fpv;
+        float rn = (2.f * rc - orp[S]) + frv;
+        if (damp[S]) {
+            const float sv = osg[S];
+            pn = (2.f * pc - (1.f - sv) * opp[S] + fpv) / (1.f + sv);
+            rn = (2.f * rc - (1.f - sv) * orp[S] + frv) / (1.f + sv);
+        }
+        const int64_t zo = (int64_t)z * plane;
+        const int rec = z >= z0 ? kRecordsT : 0;
+        tstore(trsrc(ppb + zo, rec), oc, pn);
+        tstore(trsrc(rpb + zo, rec), oc, rn);
+        fetch<S>(z + 2);
+        return true;
+    }
+
+    template <int... Ks>
+    __device__ __forceinline__ bool period(int zb, std::integer_sequence<int, Ks...>) {
+        return (step<Ks>(zb + Ks) && ...);
+    }
+
+    __device__ void run() {
+        const int b = blockIdx.x;
+        const int t = (b & 7) * (p.nblocks >> 3) + (b >> 3);
+        if (t >= p.ntiles) return;
+        ntx = p.ntx;
+        nty = p.nty;
+        tx = t % ntx;
+        const int t2 = t / ntx;
+        ty = t2 % nty;
+        const int zc = t2 / nty;
+        const int x0 = tx * kTileX, y0 = ty * TY;
+        const int nx = p.L.nx, ny = p.L.ny;
+        nz = p.L.nz;
+        z0 = zc * p.zchunk;
+        z1 = min(z0 + p.zchunk, nz);
+        tid = threadIdx.x;
+        lane = tid & 63;
+        w = tid >> 6;
+        plane = p.L.plane;
+        const int pitch = p.L.pitch;
+        const int64_t org = p.L.origin + (int64_t)(y0 - R) * pitch + (x0 - R);
+        pb = p.pc + org;
+        rb = p.rc + org;
+        ppb = p.pp + org;
+        rpb = p.rp + org;
+        ab = p.A + org;
+        eb = p.e + org;
+        db = p.d + org;
+        sb = (p.sig ? p.sig : p.A) + org;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) cb[k] = p.c[k] + org;
+        zpl = p.A + org - (int64_t)kGhostYZ * plane;
+        flags = (tflag_t*)p.dflag;
+        auto off = [&](int r, int c) -> uint32_t {
+            const int y = y0 - R + r, x = x0 - R + c;
+            return (x >= 0 && x < nx && y >= 0 && y < ny) ? (uint32_t)((r * pitch + c) * 4) : kOOBt;
+        };
+        oc = off(R + w, R + lane);
+#pragma unroll
+        for (int k = 0; k < NH; ++k) {
+            int e = tid + k * 64 * NW;
+            int row = LH, col = lane;  // sink row
+            if (e < R * LW) {
+                row = e / LW;
+                col = e % LW;
+            } else if ((e -= R * LW) < TY * 2 * R) {
+                row = R + e / (2 * R);
+                const int cc = e % (2 * R);
+                col = cc < R ? cc : kTileX + cc;
+            } else if ((e -= TY * 2 * R) < R * LW) {
+                row = R + TY + e / LW;
+                col = e % LW;
+            }
+            oh[k] = row < LH ? off(row, col) : kOOBt;
+            lh[k] = row * LW + col;
+        }
+        gx_on = tid < NGX;
+        {
+            const int g = tid < NGX ? tid : 0;
+            const int row = g / (2 * R), cc = g % (2 * R);
+            const int col = cc < R ? cc : kTileX + cc;
+            gxf = (R + row) * LW + col;
+            gxg = row * LW + col;
+        }
+#pragma unroll
+        for (int i = 0; i < U; ++i) fqp[i] = fqr[i] = gxp[i] = gxr[i] = gyp[i] = gyr[i] = 0.f;
+        // 2R pipeline-fill steps: planes z0-R .. z0+R-1 enter as heads
+        const int zs = z0 - 2 * R;
+        flagbuf = flag_of(zs);
+        fetch<0>(zs);
+        fetch<1>(zs + 1);
+        for (int zb_ = zs; period(zb_, std::make_integer_sequence<int, U>{}); zb_ += U) {
+        }
+    }
+};
+
+template <int R, int NW>
+__global__ __launch_bounds__(64 * NW) void tti3d_tiled(TTIStep p) {
+    __shared__ float lds[TiledTTI<R, NW>::LDS_FLOATS];
+    TiledTTI<R, NW> k(p, lds);
+    k.run();
+}
+
+template <int R>
+hipError_t launch_tiled(const TTIStep& p, hipStream_t s) {
+    hipLaunchKernelGGL((tti3d_tiled<R, 8>), dim3(p.nblocks), dim3(512), 0, s, p);
+    return hipGetLastError();
+}
+
 template <int R>
 hipError_t launch_direct(const TTIStep& p, hipStream_t s) {
     const dim3 grid((p.L.nx + kTileX - 1) / kTileX, (p.L.ny + 3) / 4, p.L.nz);
@@ -102,22 +429,24 @@ hipError_t launch_direct(const TTIStep& p, hipStream_t s) {
 
 int tti_tile_y(int radius) {
     (void)radius;
-    return 16;
+    return 8;  // the tiled kernel's 64 x 8 tiles
 }
 
 hipError_t launch_tti(const TTIStep& p, int radius, int variant, hipStream_t s) {
-    (void)variant;
+#define FD_TCASE(RR) \
+    case RR: return variant == 0 ? launch_tiled<RR>(p, s) : launch_direct<RR>(p, s);
     switch (radius) {
-        case 1: return launch_direct<1>(p, s);
-        case 2: return launch_direct<2>(p, s);
-        case 3: return launch_direct<3>(p, s);
-        case 4: return launch_direct<4>(p, s);
-        case 5: return launch_direct<5>(p, s);
-        case 6: return launch_direct<6>(p, s);
-        case 7: return launch_direct<7>(p, s);
-        case 8: return launch_direct<8>(p, s);
+        FD_TCASE(1)
+        FD_TCASE(2)
+        FD_TCASE(3)
+        FD_TCASE(4)
+        FD_TCASE(5)
+        FD_TCASE(6)
+        FD_TCASE(7)
+        FD_TCASE(8)
         default: return hipErrorInvalidValue;
     }
+#undef FD_TCASE
 }
 
 }  // namespace fd
