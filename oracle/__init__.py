@@ -74,6 +74,10 @@ def _lib():
                                    dp, I, dp, dp, dp, dp]),
             "or_tti_step_points": (I, [lp, dp, D, I, fp, fp, fp, fp, fp, fp, fp, fp, fp, fp,
                                        L, lp, dp, dp]),
+            "or_acoustic_adjoint": (I, [I, lp, I, dp, D, I, fp, fp, I, dp, dp, I, dp, dp, I]),
+            "or_acoustic_gradient": (I, [I, lp, I, dp, D, I, fp, fp, I, dp, fp, I, dp, dp, I,
+                                         dp, dp]),
+            "or_acoustic_misfit": (I, [I, lp, I, dp, D, I, fp, fp, I, dp, fp, I, dp, dp, I, dp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -268,3 +272,64 @@ def tti_step_points(spacing, dt, so, vel, eta, eps, delta, theta, phi, state, pt
     if rc != 0:
         raise ValueError("oracle rejected the TTI step")
     return op, orr
+
+
+# --------------------------------------------------------------------------
+# Adjoint and gradient (acoustic)
+# --------------------------------------------------------------------------
+
+def _pts(xyz, ndim):
+    return _as_f64(np.reshape(xyz, (-1, ndim)) if len(xyz) else np.zeros((0, ndim)))
+
+
+def acoustic_adjoint(ndim, nbl, spacing, dt, so, vel, eta, src_xyz, rec_xyz, d, nt):
+    """F^T d: the transpose of the (zero-initial-state) map wavelet -> traces,
+    applied to receiver data d[nt][nrec]; returns q'[nt][nsrc] (FP64)."""
+    vel = _as_f32(vel)
+    n = _dims(ndim, vel.shape)
+    h = _as_f64(spacing)
+    src, rec = _pts(src_xyz, ndim), _pts(rec_xyz, ndim)
+    d = _as_f64(np.reshape(d, (nt, rec.shape[0])))
+    q = np.zeros((nt, max(src.shape[0], 1)))
+    rc = _lib().or_acoustic_adjoint(int(ndim), _l(n), int(nbl), _d(h), float(dt), int(so), _f(vel),
+                                    _f(_as_f32(eta)), int(src.shape[0]), _d(src), _d(q),
+                                    int(rec.shape[0]), _d(rec), _d(d), int(nt))
+    if rc != 0:
+        raise ValueError("oracle rejected the adjoint problem")
+    return q[:, :src.shape[0]]
+
+
+def acoustic_gradient(ndim, nbl, spacing, dt, so, vel, eta, src_xyz, wavelet, rec_xyz, dobs, nt):
+    """(dJ/dm field, J) for J = 1/2 sum (d - dobs)^2, m = 1/v^2 (FP64, full
+    forward history in memory: small grids only)."""
+    vel = _as_f32(vel)
+    n = _dims(ndim, vel.shape)
+    h = _as_f64(spacing)
+    src, rec = _pts(src_xyz, ndim), _pts(rec_xyz, ndim)
+    q = _as_f32(np.reshape(wavelet, (nt, src.shape[0])))
+    dobs = _as_f64(np.reshape(dobs, (nt, rec.shape[0])))
+    g = np.zeros(vel.shape)
+    J = np.zeros(1)
+    rc = _lib().or_acoustic_gradient(int(ndim), _l(n), int(nbl), _d(h), float(dt), int(so),
+                                     _f(vel), _f(_as_f32(eta)), int(src.shape[0]), _d(src), _f(q),
+                                     int(rec.shape[0]), _d(rec), _d(dobs), int(nt), _d(g), _d(J))
+    if rc != 0:
+        raise ValueError("oracle rejected the gradient problem")
+    return g, float(J[0])
+
+
+def acoustic_misfit(ndim, nbl, spacing, dt, so, vel, eta, src_xyz, wavelet, rec_xyz, dobs, nt):
+    """J = 1/2 sum (d - dobs)^2 of an oracle forward run."""
+    vel = _as_f32(vel)
+    n = _dims(ndim, vel.shape)
+    h = _as_f64(spacing)
+    src, rec = _pts(src_xyz, ndim), _pts(rec_xyz, ndim)
+    q = _as_f32(np.reshape(wavelet, (nt, src.shape[0])))
+    dobs = _as_f64(np.reshape(dobs, (nt, rec.shape[0])))
+    J = np.zeros(1)
+    rc = _lib().or_acoustic_misfit(int(ndim), _l(n), int(nbl), _d(h), float(dt), int(so), _f(vel),
+                                   _f(_as_f32(eta)), int(src.shape[0]), _d(src), _f(q),
+                                   int(rec.shape[0]), _d(rec), _d(dobs), int(nt), _d(J))
+    if rc != 0:
+        raise ValueError("oracle rejected the misfit problem")
+    return float(J[0])

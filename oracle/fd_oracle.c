@@ -539,3 +539,181 @@ int or_tti_step_points(const long* nxyz, const double* h, double dt, int so,
     }
     return OR_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint and gradient of the acoustic forward map                         */
+/* ------------------------------------------------------------------------ */
+/*
+ * The forward run is the linear recurrence, for n = 0 .. nt-1,
+ *   F^{n+1} := D u^{n+1} - 2 u^n + E u^{n-1} - B (L u^n + S^T q^n / prod(h)) = 0,
+ * D = diag(1 + s), E = diag(1 - s), B = diag(dt^2 v^2), with traces
+ * d^n = R u^{n+1} (S, R the multilinear spreading of sources / receivers).
+ * Its transpose in terms of the multipliers lambda^{n+1} of F^{n+1}:
+ *   D lambda^k = 2 lambda^{k+1} + L(B lambda^{k+1}) - E lambda^{k+2} + R^T d^{k-1},
+ * for k = nt .. 1 with lambda^{nt+1} = lambda^{nt+2} = 0 (L is symmetric),
+ * and the wavelet-side output q'^n = S B lambda^{n+1} / prod(h).
+ */
+
+/* One level of the transposed recurrence:
+ *   lambda^k = [2 lambda^{k+1} + L(B lambda^{k+1}) - E lambda^{k+2} + R^T dk] / (1 + s),
+ * with L applied to the product B lambda^{k+1} (the transpose of B L is L B).
+ * bl is scratch of N doubles; dk is the receiver data of index k-1 (nrec). */
+static void adjoint_level(double* l0, const double* l1, const double* l2, double* bl,
+                          dims_t n, int ndim, int nbl, const double* w, int r, const double* h,
+                          double dt, const float* vel, const float* eta,
+                          int nrec, const double* rec_xyz, const double* dk) {
+    long N = n.nx * n.ny * n.nz;
+    for (long i = 0; i < N; ++i) {
+        double v = (double)vel[i];
+        bl[i] = dt * dt * v * v * l1[i];
+    }
+    fld_t fb = {bl, NULL};
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+    for (long iz = 0; iz < n.nz; ++iz)
+        for (long iy = 0; iy < n.ny; ++iy)
+            for (long ix = 0; ix < n.nx; ++ix) {
+                long i = (iz * n.ny + iy) * n.nx + ix;
+                double s = eta ? 0.5 * dt * (double)eta[i] : 0.0;
+                l0[i] = 2.0 * l1[i] + laplacian_at(fb, n, ndim, w, r, h, ix, iy, iz) -
+                        (1.0 - s) * l2[i];
+            }
+    for (int j = 0; j < nrec; ++j) {
+        long idx[8];
+        double wc[8];
+        int m = corners(ndim, n, nbl, h, rec_xyz + (long)j * ndim, idx, wc);
+        for (int c = 0; c < m; ++c) l0[idx[c]] += wc[c] * dk[j];
+    }
+    for (long i = 0; i < N; ++i) {
+        double s = eta ? 0.5 * dt * (double)eta[i] : 0.0;
+        l0[i] /= (1.0 + s);
+    }
+}
+
+/* F^T d: returns q'[nt][nsrc] for receiver data d[nt][nrec] (FP64), with
+ * q'^{k-1} = S B lambda^k / prod(h). */
+int or_acoustic_adjoint(int ndim, const long* nxyz, int nbl, const double* h, double dt, int so,
+                        const float* vel, const float* eta,
+                        int nsrc, const double* src_xyz, double* qout,
+                        int nrec, const double* rec_xyz, const double* d, int nt) {
+    dims_t n = {nxyz[0], nxyz[1], nxyz[2]};
+    int r = so / 2;
+    double w[64];
+    if ((ndim != 2 && ndim != 3) || so < 2 || so % 2 || r > 63 || nt < 0) return OR_BAD;
+    if (ndim == 2 && n.ny != 1) return OR_BAD;
+    if (!check_points(ndim, n, nbl, h, nsrc, src_xyz)) return OR_BAD;
+    if (!check_points(ndim, n, nbl, h, nrec, rec_xyz)) return OR_BAD;
+    or_weights_d2(r, w);
+    long N = n.nx * n.ny * n.nz;
+    double* l0 = (double*)calloc((size_t)N, sizeof(double));
+    double* l1 = (double*)calloc((size_t)N, sizeof(double));
+    double* l2 = (double*)calloc((size_t)N, sizeof(double));
+    double* bl = (double*)calloc((size_t)N, sizeof(double));
+    if (!l0 || !l1 || !l2 || !bl) { free(l0); free(l1); free(l2); free(bl); return OR_BAD; }
+    double hp = hprod(ndim, h);
+    for (int k = nt; k >= 1; --k) {
+        adjoint_level(l0, l1, l2, bl, n, ndim, nbl, w, r, h, dt, vel, eta, nrec, rec_xyz,
+                      d + (long)(k - 1) * nrec);
+        for (int s = 0; s < nsrc; ++s) {
+            long idx[8];
+            double wc[8];
+            int m = corners(ndim, n, nbl, h, src_xyz + (long)s * ndim, idx, wc);
+            double acc = 0.0;
+            for (int c = 0; c < m; ++c) {
+                double v = (double)vel[idx[c]];
+                acc += wc[c] * dt * dt * v * v * l0[idx[c]];
+            }
+            qout[(long)(k - 1) * nsrc + s] = acc / hp;
+        }
+        double* t = l2;
+        l2 = l1;
+        l1 = l0;
+        l0 = t;
+    }
+    free(l0); free(l1); free(l2); free(bl);
+    return OR_OK;
+}
+
+/* Gradient of J = 1/2 sum_n |d^n - dobs^n|^2 with respect to m = 1/v^2 by the
+ * adjoint state, keeping the whole forward history in memory (small grids).
+ * B = dt^2 / m, so dF^k/dm = (1/m) [D u^k - 2 u^{k-1} + E u^{k-2}] (the
+ * recurrence F^k = 0 turns B (L u + S^T q / prod h) into that difference) and
+ *   dJ/dm = - sum_k lambda^k dF^k/dm,
+ * lambda solving the transposed recurrence driven by the residual d - dobs.
+ * Writes grad[N] and *misfit. */
+int or_acoustic_gradient(int ndim, const long* nxyz, int nbl, const double* h, double dt, int so,
+                         const float* vel, const float* eta,
+                         int nsrc, const double* src_xyz, const float* wavelet,
+                         int nrec, const double* rec_xyz, const double* dobs, int nt,
+                         double* grad, double* misfit) {
+    dims_t n = {nxyz[0], nxyz[1], nxyz[2]};
+    int r = so / 2;
+    double w[64];
+    if ((ndim != 2 && ndim != 3) || so < 2 || so % 2 || r > 63 || nt < 1) return OR_BAD;
+    or_weights_d2(r, w);
+    long N = n.nx * n.ny * n.nz;
+    size_t nr = (size_t)(nrec > 0 ? nrec : 1);
+    /* history: slot t + 1 holds u^t for t = -1 .. nt */
+    double* hist = (double*)calloc((size_t)N * (size_t)(nt + 2), sizeof(double));
+    double* res = (double*)calloc((size_t)nt * nr, sizeof(double));
+    double* up = (double*)calloc((size_t)N, sizeof(double));
+    double* uc = (double*)calloc((size_t)N, sizeof(double));
+    double* l0 = (double*)calloc((size_t)N, sizeof(double));
+    double* l1 = (double*)calloc((size_t)N, sizeof(double));
+    double* l2 = (double*)calloc((size_t)N, sizeof(double));
+    double* bl = (double*)calloc((size_t)N, sizeof(double));
+    int rc = (!hist || !res || !up || !uc || !l0 || !l1 || !l2 || !bl) ? OR_BAD : OR_OK;
+    for (int t = 0; t < nt && rc == OR_OK; ++t) {
+        rc = or_acoustic_forward(ndim, nxyz, nbl, h, dt, so, vel, eta, nsrc, src_xyz,
+                                 wavelet + (long)t * nsrc, nrec, rec_xyz, res + (long)t * nrec, 1,
+                                 up, uc);
+        if (rc == OR_OK) memcpy(hist + (size_t)(t + 2) * (size_t)N, uc, sizeof(double) * (size_t)N);
+    }
+    if (rc == OR_OK) {
+        double J = 0.0;
+        for (long k = 0; k < (long)nt * nrec; ++k) {
+            res[k] -= dobs[k];
+            J += 0.5 * res[k] * res[k];
+        }
+        *misfit = J;
+        for (long i = 0; i < N; ++i) grad[i] = 0.0;
+        for (int k = nt; k >= 1; --k) {
+            adjoint_level(l0, l1, l2, bl, n, ndim, nbl, w, r, h, dt, vel, eta, nrec, rec_xyz,
+                          res + (long)(k - 1) * nrec);
+            const double* uk = hist + (size_t)(k + 1) * (size_t)N;  /* u^k     */
+            const double* uk1 = hist + (size_t)k * (size_t)N;      /* u^{k-1} */
+            const double* uk2 = hist + (size_t)(k - 1) * (size_t)N;  /* u^{k-2} */
+            for (long i = 0; i < N; ++i) {
+                double s = eta ? 0.5 * dt * (double)eta[i] : 0.0;
+                double v = (double)vel[i];
+                double dFdm = v * v * ((1.0 + s) * uk[i] - 2.0 * uk1[i] + (1.0 - s) * uk2[i]);
+                grad[i] -= l0[i] * dFdm;
+            }
+            double* t = l2;
+            l2 = l1;
+            l1 = l0;
+            l0 = t;
+        }
+    }
+    free(hist); free(res); free(up); free(uc); free(l0); free(l1); free(l2); free(bl);
+    return rc;
+}
+
+/* Misfit J = 1/2 sum (d - dobs)^2 of a forward run from the zero state. */
+int or_acoustic_misfit(int ndim, const long* nxyz, int nbl, const double* h, double dt, int so,
+                       const float* vel, const float* eta, int nsrc, const double* src_xyz,
+                       const float* wavelet, int nrec, const double* rec_xyz, const double* dobs,
+                       int nt, double* misfit) {
+    dims_t n = {nxyz[0], nxyz[1], nxyz[2]};
+    long N = n.nx * n.ny * n.nz;
+    double* tr = (double*)calloc((size_t)nt * (size_t)(nrec > 0 ? nrec : 1), sizeof(double));
+    double* up = (double*)calloc((size_t)N, sizeof(double));
+    double* uc = (double*)calloc((size_t)N, sizeof(double));
+    if (!tr || !up || !uc) { free(tr); free(up); free(uc); return OR_BAD; }
+    int rc = or_acoustic_forward(ndim, nxyz, nbl, h, dt, so, vel, eta, nsrc, src_xyz, wavelet,
+                                 nrec, rec_xyz, tr, nt, up, uc);
+    double J = 0.0;
+    for (long k = 0; k < (long)nt * nrec; ++k) J += 0.5 * (tr[k] - dobs[k]) * (tr[k] - dobs[k]);
+    *misfit = J;
+    free(tr); free(up); free(uc);
+    return rc;
+}

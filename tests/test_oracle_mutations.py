@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_acoustic as ta
+from tests import test_oracle_adjoint as tadj
 from tests import test_oracle_tti as tt
 from tests import test_oracle_weights as tw
 
@@ -21,11 +22,16 @@ SRC = Path(oracle.__file__).resolve().parent / "fd_oracle.c"
 
 @contextlib.contextmanager
 def mutant(tmp_path, old, new):
+    """Plant the substitution old -> new (first occurrence; a tuple of strings
+    plants several)."""
     text = SRC.read_text()
-    assert text.count(old) >= 1, old
+    olds, news = (old, new) if isinstance(old, tuple) else ((old,), (new,))
+    for o, n in zip(olds, news):
+        assert text.count(o) >= 1, o
+        text = text.replace(o, n, 1)
     so = tmp_path / "liboracle_mutant.so"
     c = tmp_path / "fd_oracle_mutant.c"
-    c.write_text(text.replace(old, new, 1))
+    c.write_text(text)
     subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                     "-o", str(so), str(c), "-lm"], check=True)
     saved = (oracle._LIB, oracle._lib_handle)
@@ -55,6 +61,14 @@ TTI = [
     lambda: tt.test_rotated_operators_dense_geometric(2),
     lambda: tt.test_tti_plane_wave_exact(4),
     tt.test_dense_bruteforce_tti_run,
+]
+ADJOINT = [
+    lambda: tadj.test_adjoint_equals_dense_transpose(4),
+    lambda: tadj.test_adjoint_dot_product(3, 8),
+]
+GRADIENT = [
+    lambda: tadj.test_gradient_pointwise_central_differences(2),
+    tadj.test_gradient_directional_3d,
 ]
 
 MUTANTS = [
@@ -95,6 +109,23 @@ MUTANTS = [
     ("tti coupling", "A * (e2 * hp + sd * gr.gzz)", "A * (e2 * hp + gr.gzz)", TTI),
     # TTI: Gzz coefficient of dzz uses sin instead of cos
     ("Gzz dzz", "+ ct * ct * d.dzz\n", "+ st * st * d.dzz\n", TTI),
+    # adjoint: wrong sign of the damping factor on lambda^{k+2}
+    ("adjoint damping", "(1.0 - s) * l2[i];", "(1.0 + s) * l2[i];", ADJOINT),
+    # adjoint: B L applied instead of its transpose L B
+    ("adjoint operand order",
+     ("bl[i] = dt * dt * v * v * l1[i];",
+      "l0[i] = 2.0 * l1[i] + laplacian_at(fb, n, ndim, w, r, h, ix, iy, iz) -"),
+     ("bl[i] = l1[i];",
+      "l0[i] = 2.0 * l1[i] + dt * dt * (double)vel[i] * (double)vel[i] *"
+      " laplacian_at(fb, n, ndim, w, r, h, ix, iy, iz) -"), ADJOINT),
+    # adjoint: receiver data spread without the interpolation weights
+    ("adjoint receiver weights", "l0[idx[c]] += wc[c] * dk[j];", "l0[idx[c]] += dk[j];",
+     ADJOINT),
+    # gradient: wrong history level in the imaging condition
+    ("gradient level", "const double* uk2 = hist + (size_t)(k - 1) * (size_t)N;",
+     "const double* uk2 = hist + (size_t)k * (size_t)N;", GRADIENT),
+    # gradient: damping factor of u^k with the wrong sign
+    ("gradient damping", "(1.0 + s) * uk[i]", "(1.0 - s) * uk[i]", GRADIENT),
 ]
 
 
