@@ -158,6 +158,73 @@ int32_t fd_cfl_dt(const fd_grid* grid, double vmax, double* dt_max);
  * byte counters.  Asynchronous on `stream`. */
 int32_t fd_triad(float* a, const float* b, const float* c, float s, int64_t n, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Adjoint and gradient (acoustic only)                                      */
+/* ------------------------------------------------------------------------ */
+/*
+ * The zero-state forward run is a linear map F from the source wavelets q
+ * (fd_points.data of the sources, [nt][nsrc]) to the traces d ([nt][nrec]) for
+ * a fixed model m = 1/v^2 of Eq. (Acou).  The velocity gradient used by
+ * full-waveform inversion (the application the paper's Introduction names)
+ * comes from the adjoint state: with lambda the solution of the transposed
+ * recurrence driven by the trace sensitivities d' = dJ/dd,
+ *   dJ/dm = -sum_k lambda^k (D u^k - 2 u^{k-1} + E u^{k-2}) / m,
+ * D = 1 + eta dt/2, E = 1 - eta dt/2, and dJ/dq = F^T d'.  The library runs the
+ * transposed recurrence in the variable mu = dt^2 v^2 lambda, in which it has
+ * exactly the form of the forward step (the same stencil kernels), with the
+ * receivers as sources, backwards in time.  The forward history is rebuilt
+ * from checkpoints: every `interval` steps the pair (u^{n-1}, u^n) is saved,
+ * and each segment of `interval` steps is recomputed before the adjoint
+ * sweeps through it, storing the acceleration A L u + source of every step
+ * of the segment for the imaging condition.  Memory: 2 ceil(nt/interval)
+ * dense fields plus interval + 2 padded volumes plus one dense FP64 field;
+ * compute: at most two forward runs and one adjoint run.
+ *
+ * TTI contexts return FD_ERR_UNSUPPORTED from these calls.
+ */
+
+/* fd_gradient wrt selectors. */
+#define FD_WRT_M 0   /* gradient with respect to m = 1/v^2 (squared slowness) */
+#define FD_WRT_VEL 1 /* gradient with respect to v */
+
+/* Bytes of the caller-owned checkpoint store for nt steps with a checkpoint
+ * every `interval` steps (interval <= 0: the memory-minimising choice, about
+ * sqrt(2 nt) scaled by the padded/dense volume ratio; *interval_out receives
+ * the value used and may be NULL).  Host computation only. */
+int32_t fd_checkpoint_bytes(const fd_ctx* ctx, int32_t nt, int32_t interval, uint64_t* bytes,
+                            int32_t* interval_out);
+
+/* Zero-state forward run of nt steps, exactly as fd_forward with
+ * FD_ZERO_STATE (same traces), that also fills `store` (device, 256-byte
+ * aligned, at least fd_checkpoint_bytes) with the checkpoints and the last
+ * segment's accelerations for fd_gradient.  The context remembers the store,
+ * nt and interval; fd_gradient must then be given the same store, nt,
+ * interval and source wavelets.  Asynchronous on `stream`. */
+int32_t fd_forward_checkpointed(fd_ctx* ctx, int32_t nt, const fd_points* src,
+                                const fd_points* rec, int32_t interval, void* store,
+                                uint64_t store_bytes, void* stream);
+
+/* Gradient of J with respect to the model (wrt = FD_WRT_M or FD_WRT_VEL)
+ * and the source wavelets, for the trace sensitivities adj->data ([nt][n],
+ * device, read; adj->coords are the receiver positions of the forward run).
+ * grad: device dense [Nz][Ny][Nx] float32 over the padded array, overwritten.
+ * wavelet_grad: device [nt][nsrc] float32 (dJ/dq), overwritten; NULL skips it.
+ * Requires a preceding fd_forward_checkpointed with the same store, nt,
+ * interval and sources (FD_ERR_INVALID_ARG otherwise); may be called again on
+ * the same store with other sensitivities.  Leaves the held wavefields
+ * undefined.  Asynchronous on `stream`, except for a point-table upload. */
+int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_points* adj,
+                    int32_t interval, void* store, uint64_t store_bytes, int32_t wrt,
+                    float* grad, float* wavelet_grad, void* stream);
+
+/* The transpose of the zero-state map q -> d: reads adj->data ([nt][nrec],
+ * receiver positions adj->coords) and writes out->data ([nt][nsrc], source
+ * positions out->coords) = F^T d'.  Uses the context's wavefield levels as the
+ * adjoint state (the held forward state is lost).  Asynchronous on `stream`,
+ * except for a point-table upload. */
+int32_t fd_adjoint(fd_ctx* ctx, int32_t nt, const fd_points* adj, const fd_points* out,
+                   void* stream);
+
 /* Tuning options (kernel variant / launch shape), mainly for benchmarking.
  * FD_OPT_KERNEL: 0 = tiled (default), 1 = direct global-memory kernel.
  * FD_OPT_ZCHUNK: z-planes per thread block of the tiled 3D kernels (0 = auto).

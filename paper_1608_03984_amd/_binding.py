@@ -34,10 +34,14 @@ FD_OPT_KERNEL = 1
 FD_OPT_ZCHUNK = 2
 FD_OPT_TILE = 3
 
+FD_WRT_M = 0
+FD_WRT_VEL = 1
+
 EXPORTS = (
     "fd_workspace_bytes", "fd_setup", "fd_forward", "fd_get_field", "fd_set_field",
     "fd_stencil_weights", "fd_cfl_dt", "fd_set_option", "fd_destroy", "fd_strerror",
-    "fd_last_error", "fd_triad",
+    "fd_last_error", "fd_triad", "fd_checkpoint_bytes", "fd_forward_checkpointed", "fd_gradient",
+    "fd_adjoint",
 )
 
 
@@ -100,6 +104,10 @@ def lib() -> ctypes.CDLL:
             "fd_strerror": (ctypes.c_char_p, [i32]),
             "fd_last_error": (ctypes.c_char_p, [vp]),
             "fd_triad": (i32, [vp, vp, vp, ctypes.c_float, ctypes.c_int64, vp]),
+            "fd_checkpoint_bytes": (i32, [vp, i32, i32, u64p, ctypes.POINTER(i32)]),
+            "fd_forward_checkpointed": (i32, [vp, i32, pp, pp, i32, vp, ctypes.c_uint64, vp]),
+            "fd_gradient": (i32, [vp, i32, pp, pp, i32, vp, ctypes.c_uint64, i32, vp, vp, vp]),
+            "fd_adjoint": (i32, [vp, i32, pp, pp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -210,3 +218,47 @@ def fd_cfl_dt(grid: FdGrid, vmax: float) -> float:
     out = ctypes.c_double(0.0)
     _check(lib().fd_cfl_dt(ctypes.byref(grid), float(vmax), ctypes.byref(out)), "fd_cfl_dt")
     return float(out.value)
+
+
+def fd_checkpoint_bytes(ctx, nt: int, interval: int):
+    """(bytes, interval used)."""
+    out = ctypes.c_uint64(0)
+    used = ctypes.c_int32(0)
+    _check(lib().fd_checkpoint_bytes(ctx, int(nt), int(interval), ctypes.byref(out),
+                                     ctypes.byref(used)), "fd_checkpoint_bytes", ctx)
+    return int(out.value), int(used.value)
+
+
+def fd_forward_checkpointed(ctx, nt: int, src_coords, src_data_ptr, rec_coords, rec_data_ptr,
+                            interval: int, store_ptr: int, store_bytes: int, stream: int):
+    sp, keep_s = _points(src_coords, src_data_ptr)
+    rp, keep_r = _points(rec_coords, rec_data_ptr)
+    code = lib().fd_forward_checkpointed(ctx, int(nt), ctypes.byref(sp) if sp else None,
+                                         ctypes.byref(rp) if rp else None, int(interval),
+                                         ctypes.c_void_p(store_ptr), int(store_bytes),
+                                         ctypes.c_void_p(stream))
+    del keep_s, keep_r
+    _check(code, "fd_forward_checkpointed", ctx)
+
+
+def fd_gradient(ctx, nt: int, src_coords, src_data_ptr, adj_coords, adj_data_ptr, interval: int,
+                store_ptr: int, store_bytes: int, wrt: int, grad_ptr: int, wavelet_grad_ptr: int,
+                stream: int):
+    sp, keep_s = _points(src_coords, src_data_ptr)
+    ap, keep_a = _points(adj_coords, adj_data_ptr)
+    code = lib().fd_gradient(ctx, int(nt), ctypes.byref(sp) if sp else None,
+                             ctypes.byref(ap) if ap else None, int(interval),
+                             ctypes.c_void_p(store_ptr), int(store_bytes), int(wrt),
+                             ctypes.c_void_p(grad_ptr), ctypes.c_void_p(wavelet_grad_ptr or 0),
+                             ctypes.c_void_p(stream))
+    del keep_s, keep_a
+    _check(code, "fd_gradient", ctx)
+
+
+def fd_adjoint(ctx, nt: int, adj_coords, adj_data_ptr, out_coords, out_data_ptr, stream: int):
+    ap, keep_a = _points(adj_coords, adj_data_ptr)
+    op, keep_o = _points(out_coords, out_data_ptr)
+    code = lib().fd_adjoint(ctx, int(nt), ctypes.byref(ap) if ap else None,
+                            ctypes.byref(op) if op else None, ctypes.c_void_p(stream))
+    del keep_a, keep_o
+    _check(code, "fd_adjoint", ctx)

@@ -51,6 +51,10 @@ struct fd_ctx {
     // cached sparse-point coordinates of the last upload
     std::vector<double> src_coords, rec_coords;
     int nsrc_dev, nrec_dev;
+    // checkpoint store filled by the last fd_forward_checkpointed
+    const void* ck_store;
+    int32_t ck_nt, ck_interval;
+    bool ck_last_acc;  // the last segment's accelerations are still in the store
     std::string err;
 };
 
@@ -294,6 +298,130 @@ void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, fd::Ac
     }
 }
 
+// Upload the sparse-point table [first..., second...] when the coordinates
+// differ from the last upload.
+int32_t sync_points(fd_ctx* ctx, int n1, const double* c1, int n2, const double* c2,
+                    const char* what1, const char* what2, hipStream_t s) {
+    const int nd = ctx->g.ndim;
+    std::vector<double> a(n1 ? c1 : nullptr, n1 ? c1 + (size_t)n1 * nd : nullptr);
+    std::vector<double> b(n2 ? c2 : nullptr, n2 ? c2 + (size_t)n2 * nd : nullptr);
+    if (n1 == ctx->nsrc_dev && n2 == ctx->nrec_dev && a == ctx->src_coords && b == ctx->rec_coords)
+        return FD_OK;
+    std::vector<SparsePoint> host((size_t)n1 + n2);
+    for (int i = 0; i < n1; ++i)
+        if (!locate(ctx, &a[(size_t)i * nd], &host[i]))
+            return fail(ctx, FD_ERR_INVALID_ARG,
+                        std::string(what1) + " " + std::to_string(i) + " outside the grid");
+    for (int i = 0; i < n2; ++i)
+        if (!locate(ctx, &b[(size_t)i * nd], &host[(size_t)n1 + i]))
+            return fail(ctx, FD_ERR_INVALID_ARG,
+                        std::string(what2) + " " + std::to_string(i) + " outside the grid");
+    if (!host.empty()) {
+        hipError_t he = hipMemcpyAsync(ctx->pts, host.data(), host.size() * sizeof(SparsePoint),
+                                       hipMemcpyHostToDevice, s);
+        if (he == hipSuccess) he = hipStreamSynchronize(s);  // host table goes out of scope
+        if (he != hipSuccess) return hip_fail(ctx, he, "point upload");
+    }
+    ctx->src_coords.swap(a);
+    ctx->rec_coords.swap(b);
+    ctx->nsrc_dev = n1;
+    ctx->nrec_dev = n2;
+    return FD_OK;
+}
+
+// Argument checks shared by the stepping entry points.
+int32_t check_points_arg(fd_ctx* ctx, int nt, const fd_points* p, const char* what) {
+    if (!p) return FD_OK;
+    if (p->n < 0) return fail(ctx, FD_ERR_INVALID_ARG, std::string("negative ") + what + " count");
+    if (p->n > 0 && (!p->coords || (!p->data && nt > 0)))
+        return fail(ctx, FD_ERR_INVALID_ARG, std::string(what) + " coords/data missing");
+    return FD_OK;
+}
+
+double cell_volume(const fd_ctx* ctx) {
+    const double* h = ctx->g.spacing;
+    return ctx->g.ndim == 3 ? h[0] * h[1] * h[2] : h[0] * h[2];
+}
+
+// Coefficient part of an acoustic launch (fields set per step).
+fd::AcousticStep acoustic_params(const fd_ctx* ctx) {
+    fd::AcousticStep p;
+    std::memset(&p, 0, sizeof(p));
+    p.A = ctx->A;
+    p.sig = ctx->damping ? ctx->sig : nullptr;
+    p.dflag = ctx->g.ndim == 3 ? ctx->dflag : nullptr;  // all zero without damping
+    p.L = ctx->L;
+    double c0 = 0.0;
+    for (int a = 0; a < 3; ++a) c0 += ctx->w2[a][0];
+    p.c0 = (float)c0;
+    for (int j = 0; j <= fd::kMaxRadius; ++j) {
+        p.cx[j] = ctx->w2[0][j];
+        p.cy[j] = ctx->w2[1][j];
+        p.cz[j] = ctx->w2[2][j];
+    }
+    tile_grid(ctx, ctx->tile_y, ctx->zchunk_opt, ctx->radius, &p, nullptr);
+    return p;
+}
+
+// One acoustic stencil launch: up <- step(uc, up), optionally storing A L uc.
+hipError_t acoustic_stencil(const fd_ctx* ctx, fd::AcousticStep& p, const float* uc, float* up,
+                            float* acc, hipStream_t s) {
+    p.uc = uc;
+    p.up = up;
+    p.acc = acc;
+    return fd::launch_acoustic(p, ctx->g.ndim, ctx->radius, ctx->variant, ctx->tile_cfg, s);
+}
+
+// Checkpoint store layout (all regions 256-byte aligned):
+//   ck[2 * nck]  dense fields (u^{n-1}, u^n) at n = 0, I, 2I, ...
+//   acc[I]       padded volumes: accelerations of one segment
+//   mu[2]        padded volumes: adjoint levels
+//   g            dense FP64 gradient accumulator
+struct Store {
+    int nck = 0;
+    int64_t dense = 0;       // floats per dense field (rounded to 64)
+    float* ck = nullptr;
+    float* acc = nullptr;
+    float* mu[2] = {nullptr, nullptr};
+    double* g = nullptr;
+    uint64_t bytes = 0;
+    float* ckf(int k) const { return ck + (int64_t)k * dense; }
+    float* slot(const fd_ctx* ctx, int i) const { return acc + (int64_t)i * ctx->L.volume; }
+};
+
+Store plan_store(const fd_ctx* ctx, int nt, int interval, char* base) {
+    Store st;
+    const Layout& L = ctx->L;
+    st.nck = nt > 0 ? (nt + interval - 1) / interval : 0;
+    st.dense = round_up((int64_t)L.nx * L.ny * L.nz, 64);
+    Carve cv;
+    const uint64_t o_ck = cv.take((uint64_t)(2 * st.nck) * st.dense * sizeof(float));
+    const uint64_t o_acc = cv.take((uint64_t)interval * L.volume * sizeof(float));
+    const uint64_t o_mu0 = cv.take((uint64_t)L.volume * sizeof(float));
+    const uint64_t o_mu1 = cv.take((uint64_t)L.volume * sizeof(float));
+    const uint64_t o_g = cv.take((uint64_t)st.dense * sizeof(double));
+    st.bytes = cv.off;
+    if (base) {
+        st.ck = reinterpret_cast<float*>(base + o_ck);
+        st.acc = reinterpret_cast<float*>(base + o_acc);
+        st.mu[0] = reinterpret_cast<float*>(base + o_mu0);
+        st.mu[1] = reinterpret_cast<float*>(base + o_mu1);
+        st.g = reinterpret_cast<double*>(base + o_g);
+    }
+    return st;
+}
+
+// interval <= 0: minimise 2 (nt / I) dense + I volume floats.
+int resolve_interval(const fd_ctx* ctx, int nt, int interval) {
+    if (interval > 0) return interval < nt ? interval : (nt > 0 ? nt : 1);
+    const double dense = (double)ctx->L.nx * ctx->L.ny * ctx->L.nz;
+    const double best = std::sqrt(2.0 * nt * dense / (double)ctx->L.volume);
+    int I = (int)std::lround(best);
+    if (I < 1) I = 1;
+    if (I > nt) I = nt > 0 ? nt : 1;
+    return I;
+}
+
 hipError_t refresh_flags(fd_ctx* ctx, hipStream_t s) {
     if (!ctx->damping || ctx->g.ndim != 3) return hipSuccess;
     const Layout& L = ctx->L;
@@ -364,6 +492,9 @@ int32_t fd_setup(const fd_grid* grid, const fd_model* model, void* workspace,
     ctx->tile_y = tti ? fd::tti_tile_y(ctx->radius) : fd::acoustic_tile_y(ctx->tile_cfg);
     ctx->nsrc_dev = ctx->nrec_dev = -1;
     ctx->flags_stale = false;
+    ctx->ck_store = nullptr;
+    ctx->ck_nt = ctx->ck_interval = 0;
+    ctx->ck_last_acc = false;
     plan_workspace(grid, L, max_points, ctx, static_cast<char*>(workspace));
     hipStream_t s = static_cast<hipStream_t>(stream);
 
@@ -464,42 +595,17 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
     if (!ctx) return FD_ERR_INVALID_ARG;
     ctx->err.clear();
     if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
+    int32_t rc = check_points_arg(ctx, nt, src, "source");
+    if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver");
+    if (rc != FD_OK) return rc;
     const int nsrc = src ? src->n : 0, nrec = rec ? rec->n : 0;
-    if (nsrc < 0 || nrec < 0) return fail(ctx, FD_ERR_INVALID_ARG, "negative point count");
     if ((int64_t)nsrc + nrec > ctx->max_points)
         return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
-    if (nsrc > 0 && (!src->coords || (!src->data && nt > 0)))
-        return fail(ctx, FD_ERR_INVALID_ARG, "source coords/data missing");
-    if (nrec > 0 && (!rec->coords || (!rec->data && nt > 0)))
-        return fail(ctx, FD_ERR_INVALID_ARG, "receiver coords/data missing");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int nd = ctx->g.ndim;
-
-    // sparse tables: rebuild and upload only when the coordinates change
-    std::vector<double> sc(src && nsrc ? src->coords : nullptr,
-                           src && nsrc ? src->coords + (size_t)nsrc * nd : nullptr);
-    std::vector<double> rcv(rec && nrec ? rec->coords : nullptr,
-                            rec && nrec ? rec->coords + (size_t)nrec * nd : nullptr);
-    if (nsrc != ctx->nsrc_dev || nrec != ctx->nrec_dev || sc != ctx->src_coords ||
-        rcv != ctx->rec_coords) {
-        std::vector<SparsePoint> host((size_t)nsrc + nrec);
-        for (int i = 0; i < nsrc; ++i)
-            if (!locate(ctx, &sc[(size_t)i * nd], &host[i]))
-                return fail(ctx, FD_ERR_INVALID_ARG, "source " + std::to_string(i) + " outside the grid");
-        for (int i = 0; i < nrec; ++i)
-            if (!locate(ctx, &rcv[(size_t)i * nd], &host[(size_t)nsrc + i]))
-                return fail(ctx, FD_ERR_INVALID_ARG, "receiver " + std::to_string(i) + " outside the grid");
-        if (!host.empty()) {
-            hipError_t he = hipMemcpyAsync(ctx->pts, host.data(), host.size() * sizeof(SparsePoint),
-                                           hipMemcpyHostToDevice, s);
-            if (he == hipSuccess) he = hipStreamSynchronize(s);  // host table goes out of scope
-            if (he != hipSuccess) return hip_fail(ctx, he, "point upload");
-        }
-        ctx->src_coords.swap(sc);
-        ctx->rec_coords.swap(rcv);
-        ctx->nsrc_dev = nsrc;
-        ctx->nrec_dev = nrec;
-    }
+    rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nrec, rec ? rec->coords : nullptr,
+                     "source", "receiver", s);
+    if (rc != FD_OK) return rc;
 
     hipError_t he = hipSuccess;
     if (ctx->flags_stale) {
@@ -514,41 +620,22 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
                 he = fd::launch_fill_zero(ctx->r[k], ctx->L.volume, s);
         if (he != hipSuccess) return hip_fail(ctx, he, "zero state");
     }
-    const double hp = nd == 3 ? ctx->g.spacing[0] * ctx->g.spacing[1] * ctx->g.spacing[2]
-                              : ctx->g.spacing[0] * ctx->g.spacing[2];
-    const float scale = (float)(1.0 / hp);
+    const float scale = (float)(1.0 / cell_volume(ctx));
     const SparsePoint* spts = ctx->pts;
     const SparsePoint* rpts = ctx->pts + nsrc;
     const float* sig = ctx->damping ? ctx->sig : nullptr;
-    // 3D kernels always get the flag array (all zero when there is no damping)
-    const int32_t* dflag = nd == 3 ? ctx->dflag : nullptr;
 
     if (!ctx->tti) {
-        fd::AcousticStep p;
-        std::memset(&p, 0, sizeof(p));
-        p.A = ctx->A;
-        p.sig = sig;
-        p.dflag = dflag;
-        p.L = ctx->L;
-        double c0 = 0.0;
-        for (int a = 0; a < 3; ++a) c0 += ctx->w2[a][0];
-        p.c0 = (float)c0;
-        for (int j = 0; j <= fd::kMaxRadius; ++j) {
-            p.cx[j] = ctx->w2[0][j];
-            p.cy[j] = ctx->w2[1][j];
-            p.cz[j] = ctx->w2[2][j];
-        }
-        tile_grid(ctx, ctx->tile_y, ctx->zchunk_opt, ctx->radius, &p, nullptr);
+        fd::AcousticStep p = acoustic_params(ctx);
         for (int n = 0; n < nt; ++n) {
             float* un = ctx->u[1 - ctx->cur];  // holds u^{n-1}, receives u^{n+1}
-            p.uc = ctx->u[ctx->cur];
-            p.up = un;
-            he = fd::launch_acoustic(p, nd, ctx->radius, ctx->variant, ctx->tile_cfg, s);
+            he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, s);
             if (he == hipSuccess && nsrc)
                 he = fd::launch_inject(un, ctx->A, sig, spts, nsrc, src->data + (size_t)n * nsrc,
                                        scale, ctx->L, nd, s);
             if (he == hipSuccess && nrec)
-                he = fd::launch_record(un, rpts, nrec, rec->data + (size_t)n * nrec, ctx->L, nd, s);
+                he = fd::launch_record(un, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
+                                       nd, s);
             if (he != hipSuccess) return hip_fail(ctx, he, "step");
             ctx->cur = 1 - ctx->cur;
         }
@@ -557,7 +644,7 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
         std::memset(&p, 0, sizeof(p));
         p.A = ctx->A;
         p.sig = sig;
-        p.dflag = dflag;
+        p.dflag = ctx->dflag;
         p.e = ctx->e;
         p.d = ctx->d;
         for (int k = 0; k < 6; ++k) p.c[k] = ctx->c[k];
@@ -586,11 +673,212 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
                     he = fd::launch_inject(rn, ctx->A, sig, spts, nsrc, q, scale, ctx->L, 3, s);
             }
             if (he == hipSuccess && nrec)
-                he = fd::launch_record(pn, rpts, nrec, rec->data + (size_t)n * nrec, ctx->L, 3, s);
+                he = fd::launch_record(pn, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
+                                       3, s);
             if (he != hipSuccess) return hip_fail(ctx, he, "step");
             ctx->cur = 1 - ctx->cur;
         }
     }
+    return FD_OK;
+}
+
+int32_t fd_checkpoint_bytes(const fd_ctx* ctx, int32_t nt, int32_t interval, uint64_t* bytes,
+                            int32_t* interval_out) {
+    if (!ctx || !bytes || nt < 0) return FD_ERR_INVALID_ARG;
+    if (ctx->tti) return FD_ERR_UNSUPPORTED;
+    const int I = resolve_interval(ctx, nt, interval);
+    *bytes = plan_store(ctx, nt, I, nullptr).bytes;
+    if (interval_out) *interval_out = I;
+    return FD_OK;
+}
+
+namespace {
+
+int32_t check_store(fd_ctx* ctx, int nt, int I, void* store, uint64_t store_bytes) {
+    if (!store || reinterpret_cast<uintptr_t>(store) % 256)
+        return fail(ctx, FD_ERR_WORKSPACE, "checkpoint store missing or not 256-byte aligned");
+    if (store_bytes < plan_store(ctx, nt, I, nullptr).bytes)
+        return fail(ctx, FD_ERR_WORKSPACE, "checkpoint store smaller than fd_checkpoint_bytes");
+    return FD_OK;
+}
+
+// Forward steps n0 .. n1-1 from the held state, storing the acceleration of
+// step n into slot n - n0 when `slots` is set and sampling receivers when
+// `rec` is set.
+hipError_t forward_segment(fd_ctx* ctx, fd::AcousticStep& p, const Store* slots, int n0, int n1,
+                           const fd_points* src, int nsrc, const fd_points* rec, int nrec,
+                           hipStream_t s) {
+    const int nd = ctx->g.ndim;
+    const float scale = (float)(1.0 / cell_volume(ctx));
+    const float* sig = ctx->damping ? ctx->sig : nullptr;
+    hipError_t he = hipSuccess;
+    for (int n = n0; n < n1 && he == hipSuccess; ++n) {
+        float* un = ctx->u[1 - ctx->cur];
+        float* acc = slots ? slots->slot(ctx, n - n0) : nullptr;
+        he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, acc, s);
+        if (he == hipSuccess && nsrc) {
+            const float* q = src->data + (size_t)n * nsrc;
+            he = fd::launch_inject(un, ctx->A, sig, ctx->pts, nsrc, q, scale, ctx->L, nd, s);
+            // the acceleration carries the source term without the damping divisor
+            if (he == hipSuccess && acc)
+                he = fd::launch_inject(acc, ctx->A, nullptr, ctx->pts, nsrc, q, scale, ctx->L, nd,
+                                       s);
+        }
+        if (he == hipSuccess && nrec)
+            he = fd::launch_record(un, ctx->pts + nsrc, nrec, rec->data + (size_t)n * nrec, 1.f,
+                                   ctx->L, nd, s);
+        ctx->cur = 1 - ctx->cur;
+    }
+    return he;
+}
+
+// One adjoint step in mu = dt^2 v^2 lambda: mu^k from (mu^{k+1}, mu^{k+2}) by
+// the forward stencil, then B R^T d'^{k-1} / (1 + s) injected at the
+// receivers (the forward injection without the 1 / prod(h) source scaling),
+// and dJ/dq^{k-1} = S mu^k / prod(h) sampled at the sources.
+hipError_t adjoint_step(fd_ctx* ctx, fd::AcousticStep& p, const float* mu1, float* mu2, int k,
+                        int nsrc, float* qgrad, const fd_points* adj, int nadj, hipStream_t s) {
+    const int nd = ctx->g.ndim;
+    const float* sig = ctx->damping ? ctx->sig : nullptr;
+    hipError_t he = acoustic_stencil(ctx, p, mu1, mu2, nullptr, s);
+    if (he == hipSuccess && nadj)
+        he = fd::launch_inject(mu2, ctx->A, sig, ctx->pts + nsrc, nadj,
+                               adj->data + (size_t)(k - 1) * nadj, 1.f, ctx->L, nd, s);
+    if (he == hipSuccess && nsrc && qgrad)
+        he = fd::launch_record(mu2, ctx->pts, nsrc, qgrad + (size_t)(k - 1) * nsrc,
+                               (float)(1.0 / cell_volume(ctx)), ctx->L, nd, s);
+    return he;
+}
+
+}  // namespace
+
+int32_t fd_forward_checkpointed(fd_ctx* ctx, int32_t nt, const fd_points* src,
+                                const fd_points* rec, int32_t interval, void* store,
+                                uint64_t store_bytes, void* stream) {
+    if (!ctx) return FD_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "gradients are built for acoustic only");
+    if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
+    int32_t rc = check_points_arg(ctx, nt, src, "source");
+    if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver");
+    if (rc != FD_OK) return rc;
+    const int nsrc = src ? src->n : 0, nrec = rec ? rec->n : 0;
+    if ((int64_t)nsrc + nrec > ctx->max_points)
+        return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
+    const int I = resolve_interval(ctx, nt, interval);
+    rc = check_store(ctx, nt, I, store, store_bytes);
+    if (rc != FD_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nrec, rec ? rec->coords : nullptr,
+                     "source", "receiver", s);
+    if (rc != FD_OK) return rc;
+    ctx->ck_store = nullptr;
+    hipError_t he = hipSuccess;
+    if (ctx->flags_stale) {
+        he = refresh_flags(ctx, s);
+        if (he != hipSuccess) return hip_fail(ctx, he, "damping flags");
+        ctx->flags_stale = false;
+    }
+    for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume, s);
+    const Store st = plan_store(ctx, nt, I, static_cast<char*>(store));
+    fd::AcousticStep p = acoustic_params(ctx);
+    for (int j = 0; j < st.nck && he == hipSuccess; ++j) {
+        const int n0 = j * I, n1 = n0 + I < nt ? n0 + I : nt;
+        he = fd::launch_pack(ctx->u[1 - ctx->cur], st.ckf(2 * j), ctx->L, s);
+        if (he == hipSuccess) he = fd::launch_pack(ctx->u[ctx->cur], st.ckf(2 * j + 1), ctx->L, s);
+        if (he == hipSuccess)
+            he = forward_segment(ctx, p, j == st.nck - 1 ? &st : nullptr, n0, n1, src, nsrc, rec,
+                                 nrec, s);
+    }
+    if (he != hipSuccess) return hip_fail(ctx, he, "checkpointed forward");
+    ctx->ck_store = store;
+    ctx->ck_nt = nt;
+    ctx->ck_interval = I;
+    ctx->ck_last_acc = true;
+    return FD_OK;
+}
+
+int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_points* adj,
+                    int32_t interval, void* store, uint64_t store_bytes, int32_t wrt,
+                    float* grad, float* wavelet_grad, void* stream) {
+    if (!ctx) return FD_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "gradients are built for acoustic only");
+    if (wrt != FD_WRT_M && wrt != FD_WRT_VEL) return fail(ctx, FD_ERR_INVALID_ARG, "wrt");
+    if (!grad) return fail(ctx, FD_ERR_INVALID_ARG, "grad is NULL");
+    const int I = resolve_interval(ctx, nt, interval);
+    if (!ctx->ck_store || store != ctx->ck_store || nt != ctx->ck_nt || I != ctx->ck_interval)
+        return fail(ctx, FD_ERR_INVALID_ARG,
+                    "store, nt and interval must match the last fd_forward_checkpointed");
+    int32_t rc = check_points_arg(ctx, nt, src, "source");
+    if (rc == FD_OK) rc = check_points_arg(ctx, nt, adj, "adjoint source");
+    if (rc != FD_OK) return rc;
+    const int nsrc = src ? src->n : 0, nadj = adj ? adj->n : 0;
+    if ((int64_t)nsrc + nadj > ctx->max_points)
+        return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
+    rc = check_store(ctx, nt, I, store, store_bytes);
+    if (rc != FD_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nadj, adj ? adj->coords : nullptr,
+                     "source", "adjoint source", s);
+    if (rc != FD_OK) return rc;
+    const Store st = plan_store(ctx, nt, I, static_cast<char*>(store));
+    hipError_t he = hipSuccess;
+    for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(st.mu[k], ctx->L.volume, s);
+    if (he == hipSuccess) he = fd::launch_fill_zero(reinterpret_cast<float*>(st.g), 2 * st.dense, s);
+    fd::AcousticStep p = acoustic_params(ctx);
+    int m = 0;  // st.mu[m] holds mu^{k+1}, st.mu[1-m] mu^{k+2}
+    for (int j = st.nck - 1; j >= 0 && he == hipSuccess; --j) {
+        const int n0 = j * I, n1 = n0 + I < nt ? n0 + I : nt;
+        if (!(j == st.nck - 1 && ctx->ck_last_acc)) {
+            he = fd::launch_unpack(st.ckf(2 * j), ctx->u[1 - ctx->cur], ctx->L, s);
+            if (he == hipSuccess) he = fd::launch_unpack(st.ckf(2 * j + 1), ctx->u[ctx->cur], ctx->L, s);
+            if (he == hipSuccess)
+                he = forward_segment(ctx, p, &st, n0, n1, src, nsrc, nullptr, 0, s);
+        }
+        for (int k = n1; k > n0 && he == hipSuccess; --k) {
+            he = adjoint_step(ctx, p, st.mu[m], st.mu[1 - m], k, nsrc, wavelet_grad, adj, nadj, s);
+            if (he == hipSuccess) he = fd::launch_image(st.mu[1 - m], st.slot(ctx, k - 1 - n0), st.g, ctx->L, s);
+            m = 1 - m;
+        }
+    }
+    ctx->ck_last_acc = false;  // the segment slots now hold the first segment
+    if (he == hipSuccess)
+        he = fd::launch_finish_gradient(st.g, ctx->A, grad, ctx->L, ctx->g.dt, wrt == FD_WRT_VEL, s);
+    if (he != hipSuccess) return hip_fail(ctx, he, "gradient");
+    return FD_OK;
+}
+
+int32_t fd_adjoint(fd_ctx* ctx, int32_t nt, const fd_points* adj, const fd_points* out,
+                   void* stream) {
+    if (!ctx) return FD_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "the adjoint is built for acoustic only");
+    if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
+    int32_t rc = check_points_arg(ctx, nt, adj, "adjoint source");
+    if (rc == FD_OK) rc = check_points_arg(ctx, nt, out, "source");
+    if (rc != FD_OK) return rc;
+    const int nadj = adj ? adj->n : 0, nsrc = out ? out->n : 0;
+    if ((int64_t)nsrc + nadj > ctx->max_points)
+        return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = sync_points(ctx, nsrc, out ? out->coords : nullptr, nadj, adj ? adj->coords : nullptr,
+                     "source", "adjoint source", s);
+    if (rc != FD_OK) return rc;
+    hipError_t he = hipSuccess;
+    if (ctx->flags_stale) {
+        he = refresh_flags(ctx, s);
+        if (he != hipSuccess) return hip_fail(ctx, he, "damping flags");
+        ctx->flags_stale = false;
+    }
+    for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume, s);
+    fd::AcousticStep p = acoustic_params(ctx);
+    for (int k = nt; k >= 1 && he == hipSuccess; --k) {
+        he = adjoint_step(ctx, p, ctx->u[ctx->cur], ctx->u[1 - ctx->cur], k, nsrc,
+                          out ? out->data : nullptr, adj, nadj, s);
+        ctx->cur = 1 - ctx->cur;
+    }
+    if (he != hipSuccess) return hip_fail(ctx, he, "adjoint");
     return FD_OK;
 }
 

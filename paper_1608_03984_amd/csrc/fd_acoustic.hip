@@ -7,7 +7,9 @@
 // per-axis weights arrive pre-divided by h^2; symmetric neighbours are summed
 // before they are weighted.  Algorithmic traffic per point: read u^n, u^{n-1}
 // and A, write u^{n+1} = 16 bytes (section 4.2); s is read only in tiles that
-// hold damping.
+// hold damping.  For gradients a launch can also store the acceleration term
+// A L u^n of every point (4 more bytes written), which the imaging condition
+// correlates with the adjoint field.
 #include "fd_internal.h"
 
 #include <utility>
@@ -62,7 +64,9 @@ __global__ __launch_bounds__(256) void acoustic_direct(AcousticStep p) {
     for (int j = 1; j <= R; ++j) lz = fmaf(p.cz[j], u[i + j * plane] + u[i - j * plane], lz);
     const float lap = fmaf(p.c0, c, lx + ly + lz);
     const float s = p.sig ? p.sig[i] : 0.f;
-    p.up[i] = update(c, p.up[i], p.A[i], lap, s);
+    const float a = p.A[i];
+    p.up[i] = update(c, p.up[i], a, lap, s);
+    if (p.acc) p.acc[i] = a * lap;
 }
 
 // ---------------------------------------------------------------------------
@@ -104,7 +108,7 @@ constexpr uint32_t kOOB = 0x80000000u;  // any offset at or past the record limi
 constexpr int kRecords = 0x7fffffff;
 
 
-template <int R, int NW, int VY>
+template <int R, int NW, int VY, bool ACC>
 struct TiledAcoustic {
     static constexpr int TY = NW * VY;
     static constexpr int LW = kTileX + 2 * R;
@@ -119,6 +123,7 @@ struct TiledAcoustic {
     float* lds;
     const float* ub;  // tile origin (x0 - R, y0 - R) of u^n, plane 0
     float* pb;        // same for u^{n-1} / u^{n+1}
+    float* cb;        // same for the acceleration output (ACC)
     const float* ab;  // same for A
     const float* sb;  // same for the damping coefficient
     const float* zpl; // an all-zero plane (ghost plane of A) at the tile origin
@@ -209,7 +214,7 @@ struct TiledAcoustic {
         // same memory operations
         const auto ro = __builtin_amdgcn_make_buffer_rsrc(pb + (int64_t)z * plane, 0,
                                                           z >= z0 ? kRecords : 0, 0x00020000);
-        float nv[VY];
+        float nv[VY], av[VY];
 #pragma unroll
         for (int v = 0; v < VY; ++v) {
             float lz = 0.f;
@@ -218,6 +223,7 @@ struct TiledAcoustic {
                 lz = fmaf(p.cz[j], q[(C + j) % U][v] + q[(C + U - j) % U][v], lz);
             const float lxy = lq[(K % (R + 1)) * TY * kTileX + (w * VY + v) * kTileX + lane];
             const float lap = fmaf(p.c0, q[C][v], lxy + lz);
+            av[v] = aa[S][v] * lap;
             nv[v] = fmaf(aa[S][v], lap, 2.f * q[C][v] - prv[S][v]);
             if (damp[S]) {
                 const float sv = sg[S][v];
@@ -226,6 +232,12 @@ struct TiledAcoustic {
         }
 #pragma unroll
         for (int v = 0; v < VY; ++v) bstore_nt(ro, oc[v], nv[v]);
+        if constexpr (ACC) {
+            const auto rc = __builtin_amdgcn_make_buffer_rsrc(cb + (int64_t)z * plane, 0,
+                                                              z >= z0 ? kRecords : 0, 0x00020000);
+#pragma unroll
+            for (int v = 0; v < VY; ++v) bstore_nt(rc, oc[v], av[v]);
+        }
         fetch<S>(z + 2);
         return true;
     }
@@ -258,6 +270,7 @@ struct TiledAcoustic {
         const int64_t org = p.L.origin + (int64_t)(y0 - R) * pitch + (x0 - R);
         ub = p.uc + org;
         pb = p.up + org;
+        cb = ACC ? p.acc + org : pb;
         ab = p.A + org;
         sb = (p.sig ? p.sig : p.A) + org;
         zpl = p.A + org - (int64_t)kGhostYZ * plane;
@@ -310,11 +323,11 @@ struct TiledAcoustic {
     }
 };
 
-template <int R, int NW, int VY>
+template <int R, int NW, int VY, bool ACC>
 __global__ __launch_bounds__(64 * NW) void acoustic3d_tiled(AcousticStep p) {
-    using T = TiledAcoustic<R, NW, VY>;
+    using T = TiledAcoustic<R, NW, VY, ACC>;
     __shared__ float lds[2 * T::LDS_FLOATS + T::LQ_FLOATS];
-    TiledAcoustic<R, NW, VY> k(p, lds, lds + 2 * T::LDS_FLOATS);
+    T k(p, lds, lds + 2 * T::LDS_FLOATS);
     k.run();
 }
 
@@ -333,7 +346,12 @@ hipError_t launch_direct(const AcousticStep& p, int ndim, hipStream_t s) {
 
 template <int R, int NW, int VY>
 hipError_t launch_tiled(const AcousticStep& p, hipStream_t s) {
-    hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY>), dim3(p.nblocks), dim3(64 * NW), 0, s, p);
+    if (p.acc)
+        hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, true>), dim3(p.nblocks), dim3(64 * NW), 0,
+                           s, p);
+    else
+        hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, false>), dim3(p.nblocks), dim3(64 * NW),
+                           0, s, p);
     return hipGetLastError();
 }
 

@@ -150,11 +150,11 @@ __global__ __launch_bounds__(kBlock) void inject_kernel(float* u, const float* _
     atomicAdd(&u[i], w * A[i] * q[s] * scale / (1.f + sg));
 }
 
-// One thread per receiver: multilinear interpolation of u.
+// One thread per receiver: multilinear interpolation of u, times scale.
 __global__ __launch_bounds__(kBlock) void record_kernel(const float* __restrict__ u,
                                                         const SparsePoint* __restrict__ pts,
-                                                        int n, float* __restrict__ out, Layout L,
-                                                        int ndim) {
+                                                        int n, float* __restrict__ out,
+                                                        float scale, Layout L, int ndim) {
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
     const SparsePoint P = pts[j];
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void record_kernel(const float* __restrict_
             (dx ? P.fx : 1.f - P.fx) * (dy ? P.fy : 1.f - P.fy) * (dz ? P.fz : 1.f - P.fz);
         if (w != 0.f) acc += w * u[P.base + dx + (int64_t)dy * L.pitch + (int64_t)dz * L.plane];
     }
-    out[j] = acc;
+    out[j] = acc * scale;
 }
 
 int grid_for(int64_t n) {
@@ -221,11 +221,11 @@ hipError_t launch_inject(float* u, const float* A, const float* sig, const Spars
     return hipGetLastError();
 }
 
-hipError_t launch_record(const float* u, const SparsePoint* pts, int n, float* out,
+hipError_t launch_record(const float* u, const SparsePoint* pts, int n, float* out, float scale,
                          const Layout& L, int ndim, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(record_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, u, pts,
-                       n, out, L, ndim);
+                       n, out, scale, L, ndim);
     return hipGetLastError();
 }
 

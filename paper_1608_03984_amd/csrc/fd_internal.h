@@ -44,6 +44,7 @@ struct SparsePoint {
 struct AcousticStep {
     const float* __restrict__ uc;  // u^n
     float* up;                     // u^{n-1} in, u^{n+1} out
+    float* acc;                    // if set, receives A L u^n (the step's acceleration term)
     const float* __restrict__ A;   // dt^2 v^2
     const float* __restrict__ sig; // eta dt / 2, or nullptr
     const int32_t* __restrict__ dflag; // per (z, tile): 1 if the tile-plane holds damping
@@ -109,8 +110,16 @@ hipError_t launch_damping_flags(const float* sig, int32_t* flags, const Layout& 
 hipError_t launch_inject(float* u, const float* A, const float* sig, const SparsePoint* pts,
                          int n, const float* q, float scale, const Layout& L, int ndim,
                          hipStream_t s);
-hipError_t launch_record(const float* u, const SparsePoint* pts, int n, float* out,
+hipError_t launch_record(const float* u, const SparsePoint* pts, int n, float* out, float scale,
                          const Layout& L, int ndim, hipStream_t s);
+
+// adjoint / gradient
+// g[dense] += mu[vol] * acc[vol] over the interior (FP64 accumulation).
+hipError_t launch_image(const float* mu, const float* acc, double* g, const Layout& L,
+                        hipStream_t s);
+// out[dense] = g * -1/dt^2 (wrt m = 1/v^2) or g * 2 dt / A^{3/2} (wrt v).
+hipError_t launch_finish_gradient(const double* g, const float* A, float* out, const Layout& L,
+                                  double dt, int wrt_vel, hipStream_t s);
 
 // stencils
 hipError_t launch_acoustic(const AcousticStep& p, int ndim, int radius, int variant, int tile_cfg,

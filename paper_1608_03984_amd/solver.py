@@ -79,6 +79,60 @@ class Solver:
         self._keep_q = q  # the wavelet must outlive the asynchronous launches
         return traces
 
+    def _coords(self, c):
+        return None if c is None else np.asarray(c, np.float64).reshape(-1, self.ndim)
+
+    def forward_checkpointed(self, nt, src_coords, wavelet, rec_coords, interval=0):
+        """Zero-state forward run (same traces as ``forward``) that keeps the
+        checkpoints ``gradient`` needs; the store is allocated here."""
+        src, rec = self._coords(src_coords), self._coords(rec_coords)
+        nbytes, used = B.fd_checkpoint_bytes(self.ctx, nt, interval)
+        store = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (store.data_ptr() + 255) // 256 * 256
+        q = _dev(wavelet, self.device).reshape(nt, src.shape[0]) if src is not None and len(src) else None
+        nrec = 0 if rec is None else rec.shape[0]
+        traces = torch.empty((nt, nrec), dtype=torch.float32, device=self.device)
+        B.fd_forward_checkpointed(self.ctx, nt, src, q.data_ptr() if q is not None else 0, rec,
+                                  traces.data_ptr() if nrec else 0, used, ptr, nbytes,
+                                  self.stream)
+        self._ck = dict(store=store, ptr=ptr, bytes=nbytes, interval=used, nt=nt, src=src, q=q,
+                        rec=rec)
+        return traces
+
+    @property
+    def checkpoint_interval(self):
+        return self._ck["interval"] if getattr(self, "_ck", None) else None
+
+    def gradient(self, adj_data, wrt="vel", wavelet_grad=True):
+        """(dJ/dmodel [padded field shape], dJ/dwavelet [nt][nsrc] or None) for
+        the trace sensitivities ``adj_data`` [nt][nrec] of the last
+        ``forward_checkpointed`` run."""
+        ck = self._ck
+        nt, src, rec = ck["nt"], ck["src"], ck["rec"]
+        d = _dev(adj_data, self.device).reshape(nt, 0 if rec is None else rec.shape[0])
+        grad = torch.empty(self.field_shape, dtype=torch.float32, device=self.device)
+        nsrc = 0 if src is None else src.shape[0]
+        qg = torch.empty((nt, nsrc), dtype=torch.float32, device=self.device) \
+            if wavelet_grad and nsrc else None
+        B.fd_gradient(self.ctx, nt, src, ck["q"].data_ptr() if ck["q"] is not None else 0, rec,
+                      d.data_ptr(), ck["interval"], ck["ptr"], ck["bytes"],
+                      B.FD_WRT_VEL if wrt == "vel" else B.FD_WRT_M, grad.data_ptr(),
+                      qg.data_ptr() if qg is not None else 0, self.stream)
+        self._keep_adj = d
+        return grad, qg
+
+    def adjoint(self, nt, adj_coords, adj_data, out_coords):
+        """F^T d: the transpose of the zero-state map wavelet -> traces, for
+        data ``adj_data`` [nt][nadj] at ``adj_coords``; returns [nt][nout]
+        at ``out_coords``.  The held wavefields are overwritten."""
+        a, o = self._coords(adj_coords), self._coords(out_coords)
+        d = _dev(adj_data, self.device).reshape(nt, 0 if a is None else a.shape[0])
+        nout = 0 if o is None else o.shape[0]
+        out = torch.empty((nt, nout), dtype=torch.float32, device=self.device)
+        B.fd_adjoint(self.ctx, nt, a, d.data_ptr(), o, out.data_ptr() if nout else 0, self.stream)
+        self._keep_adj = d
+        return out
+
     def get_field(self, which=B.FD_FIELD_CUR):
         out = torch.empty(self.field_shape, dtype=torch.float32, device=self.device)
         B.fd_get_field(self.ctx, which, out.data_ptr(), self.stream)
@@ -112,3 +166,37 @@ def from_problem(p, device="cuda", max_points=None) -> Solver:
     return Solver(p.ndim, p.shape, p.spacing, p.nbl, p.so, p.dt, p.vel, p.eta, physics=p.physics,
                   epsilon=p.eps, delta=p.delta, theta=p.theta, phi=p.phi, max_points=mp,
                   device=device)
+
+
+class AcousticModeling(torch.autograd.Function):
+    """Traces of the zero-state acoustic run as a differentiable function of
+    the velocity model and the source wavelets.  The forward pass keeps
+    checkpoints; the backward pass runs libfd's adjoint and imaging
+    condition (fd_gradient) on the incoming trace sensitivities."""
+
+    @staticmethod
+    def forward(ctx, vel, wavelet, geometry):
+        g = geometry
+        s = Solver(g["ndim"], g["shape"], g["spacing"], g["nbl"], g["so"], g["dt"], vel.detach(),
+                   g.get("eta"), max_points=len(g["src"]) + len(g["rec"]) + 1, device=vel.device)
+        tr = s.forward_checkpointed(wavelet.shape[0], g["src"], wavelet.detach(), g["rec"],
+                                    g.get("interval", 0))
+        ctx.solver = s
+        return tr
+
+    @staticmethod
+    def backward(ctx, gtr):
+        s = ctx.solver
+        need_v, need_q = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        gv, gq = s.gradient(gtr.contiguous(), wrt="vel", wavelet_grad=need_q)
+        ctx.solver = None
+        s.close()
+        return (gv if need_v else None), (gq if need_q else None), None
+
+
+def acoustic_modeling(vel, wavelet, geometry):
+    """Differentiable traces [nt][nrec] for ``vel`` (padded shape, float32 on
+    the GPU) and ``wavelet`` [nt][nsrc].  ``geometry`` is a dict with ndim,
+    shape (x, y, z physical), spacing, nbl, so, dt, src and rec coordinates and
+    optionally eta (damping, padded shape) and interval (checkpoint spacing)."""
+    return AcousticModeling.apply(vel, wavelet, geometry)

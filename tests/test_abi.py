@@ -119,3 +119,13 @@ def test_null_context_and_strings():
     for c in range(7):
         assert len(P.fd_strerror(c)) > 3
     assert P.fd_strerror(99) == "unknown status"
+
+
+def test_gradient_entry_points_reject_null_context():
+    lib = P.lib()
+    u64 = ctypes.c_uint64(0)
+    assert lib.fd_checkpoint_bytes(None, 10, 0, ctypes.byref(u64), None) == P.FD_ERR_INVALID_ARG
+    assert lib.fd_forward_checkpointed(None, 10, None, None, 0, None, 0, None) == P.FD_ERR_INVALID_ARG
+    assert lib.fd_gradient(None, 10, None, None, 0, None, 0, P.FD_WRT_M, None, None,
+                           None) == P.FD_ERR_INVALID_ARG
+    assert lib.fd_adjoint(None, 10, None, None, None) == P.FD_ERR_INVALID_ARG

@@ -1,0 +1,234 @@
+"""GPU parity of the adjoint and the velocity gradient (libfd's fd_adjoint,
+fd_forward_checkpointed and fd_gradient through the C ABI) against the FP64
+oracle.
+
+Tolerances.  The adjoint run is a forward-type run of the same FP32 kernels,
+so its output is held to the full-run bar of the forward path, relative L2
+1e-4.  The gradient is a sum over time of products of two such FP32 fields
+(adjoint state times the forward acceleration), each within 1e-4 of the
+oracle's, accumulated in FP64: relative L2 2e-4 (the sum of the two factors'
+bounds).  The dot-product identity between the GPU forward and adjoint holds
+to FP32 rounding of the two runs, 1e-5 relative to |Fq| |d|.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_1608_03984_amd as P  # noqa: E402
+from paper_1608_03984_amd.solver import Solver, acoustic_modeling, from_problem  # noqa: E402
+from tests._gpu_util import THREADS, acoustic_problem, rel, say  # noqa: E402
+from workloads import smooth_random  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def observed(p, seed=99):
+    """Oracle traces of the model with a smooth 4 % velocity perturbation
+    (the 'observed' data of the misfit)."""
+    rng = np.random.default_rng(seed)
+    v = (p.vel.astype(np.float64) * (1 + 0.04 * smooth_random(p.vel.shape, 5.0, rng)))
+    oracle.set_threads(THREADS)
+    try:
+        d, _, _ = oracle.acoustic_forward(p.ndim, p.nbl, p.spacing, p.dt, p.so,
+                                          v.astype(np.float32), p.eta, p.src, p.wavelet, p.rec,
+                                          p.nt)
+    finally:
+        oracle.set_threads(1)
+    return d
+
+
+def oracle_gradient(p, dobs):
+    oracle.set_threads(THREADS)
+    try:
+        g, J = oracle.acoustic_gradient(p.ndim, p.nbl, p.spacing, p.dt, p.so, p.vel, p.eta, p.src,
+                                        p.wavelet, p.rec, dobs, p.nt)
+        tr, _, _ = oracle.acoustic_forward(p.ndim, p.nbl, p.spacing, p.dt, p.so, p.vel, p.eta,
+                                           p.src, p.wavelet, p.rec, p.nt)
+        qg = oracle.acoustic_adjoint(p.ndim, p.nbl, p.spacing, p.dt, p.so, p.vel, p.eta, p.src,
+                                     p.rec, tr - dobs, p.nt)
+    finally:
+        oracle.set_threads(1)
+    return g, J, qg
+
+
+def with_sources(p, nsrc=3, seed=5):
+    """The problem with several sources of distinct wavelets (so that the
+    wavelet gradient has several columns)."""
+    rng = np.random.default_rng(seed)
+    src = np.repeat(p.src, nsrc, axis=0)
+    span = np.array(p.shape, np.float64) * np.array(p.spacing)
+    dims = [0, 2] if p.ndim == 2 else [0, 1, 2]
+    src = src + (rng.random(src.shape) - 0.5) * 0.2 * span[dims]
+    q = np.concatenate([p.wavelet * (1 + k) for k in range(nsrc)], axis=1).astype(np.float32)
+    p.src, p.wavelet = src, q
+    return p
+
+
+@pytest.mark.parametrize("ndim,so", [(2, 4), (2, 16), (3, 2), (3, 8), (3, 16)])
+def test_adjoint_vs_oracle(ndim, so):
+    phys = (67, 1, 45) if ndim == 2 else (90, 37, 41)
+    p = with_sources(acoustic_problem(ndim, phys, 6, so, 90, seed=200 + so))
+    rng = np.random.default_rng(so)
+    d = rng.standard_normal((p.nt, len(p.rec))).astype(np.float32)
+    say(f"case: adjoint {ndim}d so{so} {p.padded}")
+    s = from_problem(p)
+    got = s.adjoint(p.nt, p.rec, d, p.src).cpu().numpy()
+    torch.cuda.synchronize()
+    s.close()
+    oracle.set_threads(THREADS)
+    ref = oracle.acoustic_adjoint(ndim, p.nbl, p.spacing, p.dt, so, p.vel, p.eta, p.src, p.rec,
+                                  d, p.nt)
+    oracle.set_threads(1)
+    e = rel(got, ref)
+    say(f"  F^T d rel L2 {e:.2e}")
+    assert e < 1e-4
+
+
+@pytest.mark.parametrize("ndim,so", [(2, 8), (3, 4), (3, 12)])
+def test_forward_adjoint_dot_product(ndim, so):
+    phys = (70, 1, 50) if ndim == 2 else (80, 30, 33)
+    p = with_sources(acoustic_problem(ndim, phys, 5, so, 70, seed=300 + so), nsrc=2)
+    rng = np.random.default_rng(so + 1)
+    q = rng.standard_normal(p.wavelet.shape).astype(np.float32)
+    d = rng.standard_normal((p.nt, len(p.rec))).astype(np.float32)
+    say(f"case: dot product {ndim}d so{so}")
+    s = from_problem(p)
+    fq = s.forward(p.nt, p.src, q, p.rec).cpu().numpy().astype(np.float64)
+    ftd = s.adjoint(p.nt, p.rec, d, p.src).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    s.close()
+    lhs, rhs = float(np.sum(fq * d)), float(np.sum(q * ftd))
+    scale = np.linalg.norm(fq) * np.linalg.norm(d)
+    say(f"  <Fq,d> {lhs:.6e}  <q,F^T d> {rhs:.6e}  gap/scale {abs(lhs - rhs) / scale:.2e}")
+    assert abs(lhs - rhs) < 1e-5 * scale
+
+
+def gpu_gradient(p, dobs, interval=0, wrt="m"):
+    s = from_problem(p)
+    tr = s.forward_checkpointed(p.nt, p.src, p.wavelet, p.rec, interval=interval)
+    res = tr - torch.from_numpy(dobs.astype(np.float32)).to(tr.device)
+    g, qg = s.gradient(res, wrt=wrt)
+    out = (g.cpu().numpy(), qg.cpu().numpy(), tr.cpu().numpy(), s.checkpoint_interval)
+    torch.cuda.synchronize()
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("ndim,so,interval", [(2, 4, 0), (2, 8, 13), (3, 2, 0), (3, 4, 1),
+                                              (3, 8, 0), (3, 8, 7), (3, 8, 1000), (3, 16, 0)])
+def test_gradient_vs_oracle(ndim, so, interval):
+    """dJ/dm and dJ/dq of J = 1/2 |d - dobs|^2 on a damped multi-tile grid,
+    for several checkpoint intervals (1 = checkpoint every step, 1000 = one
+    segment, nothing recomputed)."""
+    phys = (80, 1, 60) if ndim == 2 else (75, 30, 34)
+    p = with_sources(acoustic_problem(ndim, phys, 6, so, 80, seed=400 + so), nsrc=2)
+    dobs = observed(p)
+    say(f"case: gradient {ndim}d so{so} interval {interval} {p.padded}")
+    g, qg, tr, used = gpu_gradient(p, dobs, interval)
+    gref, J, qref = oracle_gradient(p, dobs)
+    eg, eq = rel(g, gref), rel(qg, qref)
+    say(f"  interval used {used}  J {J:.4e}  grad rel L2 {eg:.2e}  wavelet grad {eq:.2e}")
+    assert eg < 2e-4 and eq < 1e-4
+
+
+def test_gradient_wrt_velocity_and_repeat():
+    """The velocity gradient is dJ/dm * (-2 / v^3); a second fd_gradient call
+    on the same store (the last segment now recomputed) gives the same bits."""
+    p = acoustic_problem(3, (70, 24, 30), 5, 8, 60, seed=17)
+    dobs = observed(p)
+    say("case: gradient wrt v, repeated call")
+    s = from_problem(p)
+    tr = s.forward_checkpointed(p.nt, p.src, p.wavelet, p.rec, interval=9)
+    res = tr - torch.from_numpy(dobs.astype(np.float32)).to(tr.device)
+    gv1, q1 = s.gradient(res, wrt="vel")
+    gv2, q2 = s.gradient(res, wrt="vel")
+    gm, _ = s.gradient(res, wrt="m")
+    gv1, gv2, q1, q2, gm = (t.cpu().numpy() for t in (gv1, gv2, q1, q2, gm))
+    torch.cuda.synchronize()
+    s.close()
+    assert np.array_equal(gv1, gv2) and np.array_equal(q1, q2)
+    gref, _, _ = oracle_gradient(p, dobs)
+    v = p.vel.astype(np.float64)
+    assert rel(gm, gref) < 2e-4
+    assert rel(gv1, gref * (-2.0 / v ** 3)) < 2e-4
+
+
+def test_autograd_function():
+    """torch.autograd through AcousticModeling: vel.grad and wavelet.grad of
+    1/2 |d - dobs|^2 against the oracle."""
+    p = with_sources(acoustic_problem(3, (60, 26, 30), 5, 4, 70, seed=23), nsrc=2)
+    dobs = observed(p)
+    say("case: autograd")
+    geom = dict(ndim=3, shape=p.shape, spacing=p.spacing, nbl=p.nbl, so=p.so, dt=p.dt, eta=p.eta,
+                src=p.src, rec=p.rec)
+    vel = torch.from_numpy(p.vel).cuda().requires_grad_(True)
+    q = torch.from_numpy(p.wavelet.astype(np.float32)).cuda().requires_grad_(True)
+    d = acoustic_modeling(vel, q, geom)
+    loss = 0.5 * ((d - torch.from_numpy(dobs.astype(np.float32)).cuda()) ** 2).sum()
+    loss.backward()
+    gv, gq = vel.grad.cpu().numpy(), q.grad.cpu().numpy()
+    torch.cuda.synchronize()
+    gref, J, qref = oracle_gradient(p, dobs)
+    say(f"  loss {loss.item():.6e} oracle J {J:.6e}")
+    assert abs(loss.item() - J) < 1e-4 * J
+    assert rel(gv, gref * (-2.0 / p.vel.astype(np.float64) ** 3)) < 2e-4
+    assert rel(gq, qref) < 1e-4
+
+
+def test_full_size_adjoint_dot_product():
+    """The 592^3 grid (512^3 + 40-point layer) in the launch configuration of
+    the benchmark: the forward/adjoint identity on a short run."""
+    from workloads import acoustic_3d
+    p = acoustic_3d(so=8, phys=512, nbl=40, nt=24, receivers="line")
+    rng = np.random.default_rng(8)
+    q = rng.standard_normal((p.nt, len(p.src))).astype(np.float32)
+    d = rng.standard_normal((p.nt, len(p.rec))).astype(np.float32)
+    say(f"case: full-size dot product {p.padded}")
+    s = from_problem(p)
+    fq = s.forward(p.nt, p.src, q, p.rec).cpu().numpy().astype(np.float64)
+    ftd = s.adjoint(p.nt, p.rec, d, p.src).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    s.close()
+    lhs, rhs = float(np.sum(fq * d)), float(np.sum(q * ftd))
+    scale = np.linalg.norm(fq) * np.linalg.norm(d)
+    say(f"  gap/scale {abs(lhs - rhs) / scale:.2e}")
+    assert scale > 0 and abs(lhs - rhs) < 1e-5 * scale
+
+
+def test_gradient_errors():
+    p = acoustic_problem(3, (20, 20, 20), 4, 4, 10, seed=6)
+    s = from_problem(p)
+    say("case: gradient error paths")
+    d = torch.zeros((p.nt, len(p.rec)), device="cuda")
+    g = torch.empty(s.field_shape, device="cuda")
+    # no checkpointed forward yet: rejected before any device work
+    with pytest.raises(P.FdError) as e:
+        P._binding.fd_gradient(s.ctx, p.nt, p.src, 0, p.rec, d.data_ptr(), 3, g.data_ptr(), 1 << 20,
+                               P.FD_WRT_M, g.data_ptr(), 0, s.stream)
+    assert e.value.code == P.FD_ERR_INVALID_ARG
+    s.forward_checkpointed(p.nt, p.src, p.wavelet, p.rec, interval=3)
+    st = s._ck
+    with pytest.raises(P.FdError) as e:   # a different interval than the forward run's
+        P._binding.fd_gradient(s.ctx, p.nt, st["src"], st["q"].data_ptr(), st["rec"], d.data_ptr(),
+                               4, st["ptr"], st["bytes"], P.FD_WRT_M, g.data_ptr(), 0, s.stream)
+    assert e.value.code == P.FD_ERR_INVALID_ARG
+    with pytest.raises(P.FdError) as e:   # unknown wrt
+        P._binding.fd_gradient(s.ctx, p.nt, st["src"], st["q"].data_ptr(), st["rec"], d.data_ptr(),
+                               3, st["ptr"], st["bytes"], 7, g.data_ptr(), 0, s.stream)
+    assert e.value.code == P.FD_ERR_INVALID_ARG
+    with pytest.raises(P.FdError) as e:   # store too small
+        P._binding.fd_forward_checkpointed(s.ctx, p.nt, st["src"], st["q"].data_ptr(), None, 0, 3,
+                                           st["ptr"], 1024, s.stream)
+    assert e.value.code == P.FD_ERR_WORKSPACE
+    torch.cuda.synchronize()
+    s.close()
+    # TTI contexts have no gradient
+    from tests._gpu_util import tti_problem
+    t = tti_problem((20, 20, 20), 4, 4, 4, seed=3)
+    st = from_problem(t)
+    with pytest.raises(P.FdError) as e:
+        st.forward_checkpointed(4, t.src, t.wavelet, t.rec)
+    assert e.value.code == P.FD_ERR_UNSUPPORTED
+    st.close()
