@@ -61,7 +61,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-pass", action="store_true")
-    ap.add_argument("--workload", choices=("acoustic", "tti"), default="acoustic")
+    ap.add_argument("--workload", choices=("acoustic", "tti", "gradient"), default="acoustic")
+    ap.add_argument("--interval", type=int, default=0)
     return ap.parse_args()
 
 
@@ -225,6 +226,68 @@ def tti_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def gradient_bench(args):
+    """FWI gradient of the 3D acoustic workload (so 8, 592^3 points, 1 shot):
+    checkpointed forward run of ``--steps`` steps, then the adjoint run with
+    segment recomputation and the imaging condition.  Algorithmic bytes per
+    point and step: forward 16, recomputed forward 16 + 4 (acceleration
+    stored), adjoint 16, imaging 24 (two FP32 reads, FP64 accumulator read and
+    written)."""
+    import torch
+
+    from paper_1608_03984_amd.solver import Solver
+    from workloads import DT, acoustic_3d, ricker
+
+    so = 8
+    p = acoustic_3d(so=so, phys=args.phys, nbl=40, nt=1, receivers="surface")
+    npts = p.npoints
+    dev = torch.device("cuda:0")
+    dt = DT[("acoustic_3d", so)]
+    s = Solver(3, p.shape, p.spacing, p.nbl, so, dt, p.vel, p.eta,
+               max_points=1 + p.rec.shape[0], device=dev)
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
+    def run(nt):
+        wav = torch.from_numpy(ricker(10.0, dt, nt)[:, None]).to(dev)
+        out = {}
+        out["t_fwd"] = timed(lambda: out.__setitem__(
+            "tr", s.forward_checkpointed(nt, p.src, wav, p.rec, interval=args.interval)), ev)
+        adj = out["tr"] * 0.5  # trace sensitivities of a synthetic misfit
+        out["t_grad"] = timed(lambda: out.__setitem__("g", s.gradient(adj, wrt="vel")), ev)
+        out["finite"] = bool(torch.isfinite(out["g"][0]).all().item())
+        out["interval"] = s.checkpoint_interval
+        out["store_gb"] = s._ck["bytes"] / 1e9
+        s._ck = None
+        return out
+
+    run(max(args.warmup, 4))
+    torch.cuda.empty_cache()
+    r = run(args.steps)
+    nt = args.steps
+    t_all = r["t_fwd"] + r["t_grad"]
+    I = r["interval"]
+    last = nt - (nt - 1) // I * I           # steps of the last segment (not recomputed)
+    alg = npts * (16 * nt + 4 * last + 20 * (nt - last) + 16 * nt + 24 * nt)
+    ach = alg / t_all / 1e9
+    s.close()
+    line = {
+        "metric": "FWI gradient Gpt/s (3D acoustic so8)", "value": round(npts * nt / t_all / 1e9, 3),
+        "unit": "Gpt/s", "n_gpus": 1, "steps": nt, "warmup": args.warmup,
+        "ms_per_step": round(t_all / nt * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"FWI gradient, 3D acoustic {args.phys}^3 + 40-pt layer "
+                               f"({p.padded[0]}^3 points), so 8, 1 shot, {p.rec.shape[0]} "
+                               "receivers", "points": npts, "interval": I,
+                   "store_gb": round(r["store_gb"], 1)},
+        "forward_s": round(r["t_fwd"], 4), "gradient_s": round(r["t_grad"], 4),
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "whole gradient (algorithmic bytes of every pass / wall time)"},
+        "finite": r["finite"],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -236,6 +299,9 @@ def main():
         return
     if args.workload == "tti":
         tti_bench(args)
+        return
+    if args.workload == "gradient":
+        gradient_bench(args)
         return
     import torch
 
