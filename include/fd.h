@@ -159,6 +159,46 @@ int32_t fd_cfl_dt(const fd_grid* grid, double vmax, double* dt_max);
 int32_t fd_triad(float* a, const float* b, const float* c, float s, int64_t n, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* Several shots on one model (acoustic only)                                */
+/* ------------------------------------------------------------------------ */
+/*
+ * A survey runs many independent shots (source positions) on the same
+ * model.  Section 2 notes that the operational intensity of the stencil does
+ * not depend on how the work is split; sharing the model is what changes it:
+ * a context of nshots wavefields advances all of them per launch, and the
+ * tiled 3D kernel reads dt^2 v^2 (and the damping coefficient) once per tile
+ * for a group of shots, so the bytes per shot-point fall from 16 towards 12.
+ * Fields of shot k are selected with fd_get_shot_field / fd_set_shot_field;
+ * fd_forward, the adjoint and the gradient entry points accept only
+ * single-shot contexts.
+ */
+
+/* Workspace bytes for a context of nshots wavefields (1 <= nshots <= 4096)
+ * with room for max_points sparse points in total. */
+int32_t fd_workspace_bytes_shots(const fd_grid* grid, int32_t nshots, int32_t max_points,
+                                 uint64_t* bytes);
+
+/* fd_setup for nshots wavefields on one model (FD_ERR_UNSUPPORTED for TTI
+ * with nshots > 1).  fd_setup is this call with nshots = 1. */
+int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshots,
+                       void* workspace, uint64_t workspace_bytes, int32_t max_points,
+                       void* stream, fd_ctx** out);
+
+/* nt steps of Algorithm 1 for every shot of the context.  src holds the
+ * sources of all shots one after another (src->n = sum of src_counts, host
+ * array [nshots]), with wavelets src->data [nt][src->n]; rec likewise, with
+ * traces rec->data [nt][rec->n].  Shot k's points are injected into and
+ * sampled from shot k's wavefield only.  Flags and asynchrony as fd_forward. */
+int32_t fd_forward_shots(fd_ctx* ctx, int32_t nt, const fd_points* src, const int32_t* src_counts,
+                         const fd_points* rec, const int32_t* rec_counts, int32_t flags,
+                         void* stream);
+
+/* fd_get_field / fd_set_field for shot `shot` (0-based). */
+int32_t fd_get_shot_field(fd_ctx* ctx, int32_t shot, int32_t which, float* dst, void* stream);
+int32_t fd_set_shot_field(fd_ctx* ctx, int32_t shot, int32_t which, const float* src,
+                          void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* Adjoint and gradient (acoustic only)                                      */
 /* ------------------------------------------------------------------------ */
 /*
@@ -230,10 +270,13 @@ int32_t fd_adjoint(fd_ctx* ctx, int32_t nt, const fd_points* adj, const fd_point
  * FD_OPT_ZCHUNK: z-planes per thread block of the tiled 3D kernels (0 = auto).
  * FD_OPT_TILE: (x, y) tile of the tiled 3D acoustic kernel: 0 = 64x8 with 256
  *   threads, 1 = 64x16 with 256, 2 = 64x8 with 512, 3 = 64x16 with 512,
- *   -1 = the default for the space order. */
+ *   -1 = the default for the space order (and shot count).
+ * FD_OPT_SHOTS_PER_BLOCK: shots a block of the tiled 3D acoustic kernel
+ *   advances together (1, 2 or 4; 0 = default; 2 and 4 need tile 0 or 2). */
 #define FD_OPT_KERNEL 1
 #define FD_OPT_ZCHUNK 2
 #define FD_OPT_TILE 3
+#define FD_OPT_SHOTS_PER_BLOCK 4
 int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value);
 
 /* Frees the host context (not the workspace). NULL is accepted. */

@@ -33,6 +33,7 @@ FD_MAX_SPACE_ORDER = 16
 FD_OPT_KERNEL = 1
 FD_OPT_ZCHUNK = 2
 FD_OPT_TILE = 3
+FD_OPT_SHOTS_PER_BLOCK = 4
 
 FD_WRT_M = 0
 FD_WRT_VEL = 1
@@ -41,7 +42,8 @@ EXPORTS = (
     "fd_workspace_bytes", "fd_setup", "fd_forward", "fd_get_field", "fd_set_field",
     "fd_stencil_weights", "fd_cfl_dt", "fd_set_option", "fd_destroy", "fd_strerror",
     "fd_last_error", "fd_triad", "fd_checkpoint_bytes", "fd_forward_checkpointed", "fd_gradient",
-    "fd_adjoint",
+    "fd_adjoint", "fd_workspace_bytes_shots", "fd_setup_shots", "fd_forward_shots",
+    "fd_get_shot_field", "fd_set_shot_field",
 )
 
 
@@ -108,6 +110,13 @@ def lib() -> ctypes.CDLL:
             "fd_forward_checkpointed": (i32, [vp, i32, pp, pp, i32, vp, ctypes.c_uint64, vp]),
             "fd_gradient": (i32, [vp, i32, pp, pp, i32, vp, ctypes.c_uint64, i32, vp, vp, vp]),
             "fd_adjoint": (i32, [vp, i32, pp, pp, vp]),
+            "fd_workspace_bytes_shots": (i32, [gp, i32, i32, u64p]),
+            "fd_setup_shots": (i32, [gp, mp, i32, vp, ctypes.c_uint64, i32, vp,
+                                     ctypes.POINTER(vp)]),
+            "fd_forward_shots": (i32, [vp, i32, pp, ctypes.POINTER(i32), pp,
+                                       ctypes.POINTER(i32), i32, vp]),
+            "fd_get_shot_field": (i32, [vp, i32, i32, vp, vp]),
+            "fd_set_shot_field": (i32, [vp, i32, i32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -262,3 +271,50 @@ def fd_adjoint(ctx, nt: int, adj_coords, adj_data_ptr, out_coords, out_data_ptr,
                             ctypes.byref(op) if op else None, ctypes.c_void_p(stream))
     del keep_a, keep_o
     _check(code, "fd_adjoint", ctx)
+
+
+def fd_workspace_bytes_shots(grid: FdGrid, nshots: int, max_points: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check(lib().fd_workspace_bytes_shots(ctypes.byref(grid), int(nshots), int(max_points),
+                                          ctypes.byref(out)), "fd_workspace_bytes_shots")
+    return int(out.value)
+
+
+def fd_setup_shots(grid: FdGrid, model: FdModel, nshots: int, workspace_ptr: int,
+                   workspace_bytes: int, max_points: int, stream: int):
+    ctx = ctypes.c_void_p(0)
+    _check(lib().fd_setup_shots(ctypes.byref(grid), ctypes.byref(model), int(nshots),
+                                ctypes.c_void_p(workspace_ptr), int(workspace_bytes),
+                                int(max_points), ctypes.c_void_p(stream), ctypes.byref(ctx)),
+           "fd_setup_shots")
+    return ctx
+
+
+def _counts(c):
+    if c is None:
+        return None, None
+    a = np.ascontiguousarray(c, dtype=np.int32)
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), a
+
+
+def fd_forward_shots(ctx, nt: int, src_coords, src_counts, src_data_ptr, rec_coords, rec_counts,
+                     rec_data_ptr, flags: int, stream: int):
+    sp, keep_s = _points(src_coords, src_data_ptr)
+    rp, keep_r = _points(rec_coords, rec_data_ptr)
+    sc, keep_sc = _counts(src_counts)
+    rc, keep_rc = _counts(rec_counts)
+    code = lib().fd_forward_shots(ctx, int(nt), ctypes.byref(sp) if sp else None, sc,
+                                  ctypes.byref(rp) if rp else None, rc, int(flags),
+                                  ctypes.c_void_p(stream))
+    del keep_s, keep_r, keep_sc, keep_rc
+    _check(code, "fd_forward_shots", ctx)
+
+
+def fd_get_shot_field(ctx, shot: int, which: int, dst_ptr: int, stream: int):
+    _check(lib().fd_get_shot_field(ctx, int(shot), int(which), ctypes.c_void_p(dst_ptr),
+                                   ctypes.c_void_p(stream)), "fd_get_shot_field", ctx)
+
+
+def fd_set_shot_field(ctx, shot: int, which: int, src_ptr: int, stream: int):
+    _check(lib().fd_set_shot_field(ctx, int(shot), int(which), ctypes.c_void_p(src_ptr),
+                                   ctypes.c_void_p(stream)), "fd_set_shot_field", ctx)

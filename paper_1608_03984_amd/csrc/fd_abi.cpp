@@ -26,6 +26,7 @@ struct fd_ctx {
     Layout L;
     bool damping;
     bool tti;
+    int32_t nshots;  // wavefields advanced together on the one model
     int32_t max_points;
     // workspace regions
     uint32_t* reduce;
@@ -34,7 +35,7 @@ struct fd_ctx {
     float* e;
     float* d;
     float* c[6];
-    float* u[2];  // acoustic u / TTI p: two levels
+    float* u[2];  // acoustic u / TTI p: two levels (shot k at + k * L.volume)
     float* r[2];  // TTI r: two levels
     int32_t* dflag;
     SparsePoint* pts;
@@ -46,10 +47,12 @@ struct fd_ctx {
     int variant;
     int tile_cfg;
     int zchunk_opt;
+    int shots_per_block;
     int tile_y;
     bool flags_stale;
     // cached sparse-point coordinates of the last upload
     std::vector<double> src_coords, rec_coords;
+    std::vector<int32_t> src_counts, rec_counts;  // points per shot of the last upload
     int nsrc_dev, nrec_dev;
     // checkpoint store filled by the last fd_forward_checkpointed
     const void* ck_store;
@@ -179,9 +182,11 @@ struct Carve {
 
 int min_tile_y() { return 8; }
 
+constexpr int32_t kMaxShots = 4096;
+
 // Workspace plan; when base is non-null the pointers are filled in.
-uint64_t plan_workspace(const fd_grid* g, const Layout& L, int32_t max_points, fd_ctx* ctx,
-                        char* base) {
+uint64_t plan_workspace(const fd_grid* g, const Layout& L, int32_t nshots, int32_t max_points,
+                        fd_ctx* ctx, char* base) {
     Carve cv;
     const uint64_t vol = (uint64_t)L.volume * sizeof(float);
     const bool tti = g->physics == FD_TTI;
@@ -194,8 +199,8 @@ uint64_t plan_workspace(const fd_grid* g, const Layout& L, int32_t max_points, f
         o_d = cv.take(vol);
         for (int k = 0; k < 6; ++k) o_c[k] = cv.take(vol);
     }
-    const uint64_t o_u0 = cv.take(vol);
-    const uint64_t o_u1 = cv.take(vol);
+    const uint64_t o_u0 = cv.take(vol * (uint64_t)nshots);
+    const uint64_t o_u1 = cv.take(vol * (uint64_t)nshots);
     if (tti) {
         o_r[0] = cv.take(vol);
         o_r[1] = cv.take(vol);
@@ -259,7 +264,7 @@ bool locate(const fd_ctx* ctx, const double* c, SparsePoint* P) {
     P->fx = (float)frac[0];
     P->fy = (float)frac[1];
     P->fz = (float)frac[2];
-    P->pad = 0;
+    P->shot = 0;
     return true;
 }
 
@@ -268,8 +273,18 @@ bool locate(const fd_ctx* ctx, const double* c, SparsePoint* P) {
 // where the wider register queue leaves room for fewer rows per block.
 int default_tile(int radius) { return radius <= 4 ? 3 : 0; }
 
-void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, fd::AcousticStep* a,
-               fd::TTIStep* t) {
+// Several shots: 64 x 8 tiles of 512 threads (configuration 2) with 4 shots
+// per block up to radius 4 and 2 above (the register queues and LDS staging
+// grow with the shots per block).
+int default_shots_per_block(int radius, int nshots) {
+    if (nshots <= 1) return 1;
+    const int sb = radius <= 4 ? 4 : 2;
+    return nshots < sb ? (nshots >= 2 ? 2 : 1) : sb;
+}
+int shots_tile(int radius) { (void)radius; return 2; }
+
+void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, int ngroups,
+               fd::AcousticStep* a, fd::TTIStep* t) {
     const Layout& L = ctx->L;
     const int ntx = (L.nx + fd::kTileX - 1) / fd::kTileX;
     const int nty = (L.ny + tile_y - 1) / tile_y;
@@ -277,8 +292,9 @@ void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, fd::Ac
     if (zc <= 0) {
         // Split z so the grid holds about 768 blocks (three 256-thread blocks
         // per CU): every z chunk re-reads 2R planes and runs R pipeline-fill
-        // steps, so high orders round the chunk count down.
-        const int64_t xy = (int64_t)ntx * nty;
+        // steps, so high orders round the chunk count down.  Groups of shots
+        // multiply the blocks of one z chunk.
+        const int64_t xy = (int64_t)ntx * nty * ngroups;
         int64_t nzc = radius <= 4 ? (768 + xy / 2) / xy : 768 / xy;
         if (nzc < 1) nzc = 1;
         zc = (int)((L.nz + nzc - 1) / nzc);
@@ -287,10 +303,10 @@ void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, fd::Ac
     if (zc > L.nz) zc = L.nz;
     const int nzc = (L.nz + zc - 1) / zc;
     const int ntiles = ntx * nty * nzc;
-    const int nblocks = (int)round_up(ntiles, 8);
+    const int nblocks = (int)round_up((int64_t)ntiles * ngroups, 8);
     if (a) {
         a->ntx = ntx; a->nty = nty; a->nzc = nzc; a->zchunk = zc;
-        a->ntiles = ntiles; a->nblocks = nblocks;
+        a->ntiles = ntiles; a->nblocks = nblocks; a->ngroups = ngroups;
     }
     if (t) {
         t->ntx = ntx; t->nty = nty; t->nzc = nzc; t->zchunk = zc;
@@ -300,12 +316,18 @@ void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, fd::Ac
 
 // Upload the sparse-point table [first..., second...] when the coordinates
 // differ from the last upload.
+// counts1 / counts2 give the points per shot (NULL: all in shot 0).
 int32_t sync_points(fd_ctx* ctx, int n1, const double* c1, int n2, const double* c2,
-                    const char* what1, const char* what2, hipStream_t s) {
+                    const char* what1, const char* what2, hipStream_t s,
+                    const int32_t* counts1 = nullptr, const int32_t* counts2 = nullptr) {
     const int nd = ctx->g.ndim;
     std::vector<double> a(n1 ? c1 : nullptr, n1 ? c1 + (size_t)n1 * nd : nullptr);
     std::vector<double> b(n2 ? c2 : nullptr, n2 ? c2 + (size_t)n2 * nd : nullptr);
-    if (n1 == ctx->nsrc_dev && n2 == ctx->nrec_dev && a == ctx->src_coords && b == ctx->rec_coords)
+    const int ns = counts1 || counts2 ? ctx->nshots : 0;
+    std::vector<int32_t> k1(counts1 ? counts1 : nullptr, counts1 ? counts1 + ns : nullptr);
+    std::vector<int32_t> k2(counts2 ? counts2 : nullptr, counts2 ? counts2 + ns : nullptr);
+    if (n1 == ctx->nsrc_dev && n2 == ctx->nrec_dev && a == ctx->src_coords &&
+        b == ctx->rec_coords && k1 == ctx->src_counts && k2 == ctx->rec_counts)
         return FD_OK;
     std::vector<SparsePoint> host((size_t)n1 + n2);
     for (int i = 0; i < n1; ++i)
@@ -316,6 +338,15 @@ int32_t sync_points(fd_ctx* ctx, int n1, const double* c1, int n2, const double*
         if (!locate(ctx, &b[(size_t)i * nd], &host[(size_t)n1 + i]))
             return fail(ctx, FD_ERR_INVALID_ARG,
                         std::string(what2) + " " + std::to_string(i) + " outside the grid");
+    // shot of each point from the per-shot counts (validated by the caller)
+    auto assign = [&](const std::vector<int32_t>& k, size_t first, int n) {
+        size_t i = first;
+        for (size_t shot = 0; shot < k.size(); ++shot)
+            for (int j = 0; j < k[shot]; ++j) host[i++].shot = (int32_t)shot;
+        (void)n;
+    };
+    if (!k1.empty()) assign(k1, 0, n1);
+    if (!k2.empty()) assign(k2, (size_t)n1, n2);
     if (!host.empty()) {
         hipError_t he = hipMemcpyAsync(ctx->pts, host.data(), host.size() * sizeof(SparsePoint),
                                        hipMemcpyHostToDevice, s);
@@ -324,6 +355,8 @@ int32_t sync_points(fd_ctx* ctx, int n1, const double* c1, int n2, const double*
     }
     ctx->src_coords.swap(a);
     ctx->rec_coords.swap(b);
+    ctx->src_counts.swap(k1);
+    ctx->rec_counts.swap(k2);
     ctx->nsrc_dev = n1;
     ctx->nrec_dev = n2;
     return FD_OK;
@@ -359,7 +392,11 @@ fd::AcousticStep acoustic_params(const fd_ctx* ctx) {
         p.cy[j] = ctx->w2[1][j];
         p.cz[j] = ctx->w2[2][j];
     }
-    tile_grid(ctx, ctx->tile_y, ctx->zchunk_opt, ctx->radius, &p, nullptr);
+    p.nshots = ctx->nshots;
+    p.shot_stride = ctx->L.volume;
+    const int sb = ctx->nshots > 1 ? ctx->shots_per_block : 1;
+    tile_grid(ctx, ctx->tile_y, ctx->zchunk_opt, ctx->radius, (ctx->nshots + sb - 1) / sb, &p,
+              nullptr);
     return p;
 }
 
@@ -369,7 +406,8 @@ hipError_t acoustic_stencil(const fd_ctx* ctx, fd::AcousticStep& p, const float*
     p.uc = uc;
     p.up = up;
     p.acc = acc;
-    return fd::launch_acoustic(p, ctx->g.ndim, ctx->radius, ctx->variant, ctx->tile_cfg, s);
+    return fd::launch_acoustic(p, ctx->g.ndim, ctx->radius, ctx->variant, ctx->tile_cfg,
+                               ctx->nshots > 1 ? ctx->shots_per_block : 1, s);
 }
 
 // Checkpoint store layout (all regions 256-byte aligned):
@@ -451,30 +489,44 @@ int32_t fd_cfl_dt(const fd_grid* grid, double vmax, double* dt_max) {
     return FD_OK;
 }
 
-int32_t fd_workspace_bytes(const fd_grid* grid, int32_t max_points, uint64_t* bytes) {
+int32_t fd_workspace_bytes_shots(const fd_grid* grid, int32_t nshots, int32_t max_points,
+                                 uint64_t* bytes) {
     std::string msg;
-    if (!bytes || max_points < 0) return FD_ERR_INVALID_ARG;
+    if (!bytes || max_points < 0 || nshots < 1 || nshots > kMaxShots) return FD_ERR_INVALID_ARG;
     const int32_t rc = validate_grid(grid, msg);
     if (rc != FD_OK) return rc;
+    if (nshots > 1 && grid->physics != FD_ACOUSTIC) return FD_ERR_UNSUPPORTED;
     const Layout L = make_layout(grid);
-    *bytes = plan_workspace(grid, L, max_points, nullptr, nullptr);
+    *bytes = plan_workspace(grid, L, nshots, max_points, nullptr, nullptr);
     return FD_OK;
+}
+
+int32_t fd_workspace_bytes(const fd_grid* grid, int32_t max_points, uint64_t* bytes) {
+    return fd_workspace_bytes_shots(grid, 1, max_points, bytes);
 }
 
 int32_t fd_setup(const fd_grid* grid, const fd_model* model, void* workspace,
                  uint64_t workspace_bytes, int32_t max_points, void* stream, fd_ctx** out) {
+    return fd_setup_shots(grid, model, 1, workspace, workspace_bytes, max_points, stream, out);
+}
+
+int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshots,
+                       void* workspace, uint64_t workspace_bytes, int32_t max_points,
+                       void* stream, fd_ctx** out) {
     std::string msg;
     if (!out) return FD_ERR_INVALID_ARG;
     *out = nullptr;
     int32_t rc = validate_grid(grid, msg);
     if (rc != FD_OK) return rc;
     if (!model || !model->vel || max_points < 0 || !workspace) return FD_ERR_INVALID_ARG;
+    if (nshots < 1 || nshots > kMaxShots) return FD_ERR_INVALID_ARG;
     const bool tti = grid->physics == FD_TTI;
+    if (tti && nshots > 1) return FD_ERR_UNSUPPORTED;
     if (tti && (!model->epsilon || !model->delta || !model->theta || !model->phi))
         return FD_ERR_INVALID_ARG;
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return FD_ERR_WORKSPACE;
     const Layout L = make_layout(grid);
-    const uint64_t need = plan_workspace(grid, L, max_points, nullptr, nullptr);
+    const uint64_t need = plan_workspace(grid, L, nshots, max_points, nullptr, nullptr);
     if (workspace_bytes < need) return FD_ERR_WORKSPACE;
 
     fd_ctx* ctx = new (std::nothrow) fd_ctx();
@@ -483,11 +535,13 @@ int32_t fd_setup(const fd_grid* grid, const fd_model* model, void* workspace,
     ctx->radius = grid->space_order / 2;
     ctx->L = L;
     ctx->tti = tti;
+    ctx->nshots = nshots;
+    ctx->shots_per_block = default_shots_per_block(ctx->radius, nshots);
     ctx->damping = model->eta != nullptr;
     ctx->max_points = max_points;
     ctx->cur = 1;
     ctx->variant = 0;
-    ctx->tile_cfg = default_tile(ctx->radius);
+    ctx->tile_cfg = nshots > 1 ? shots_tile(ctx->radius) : default_tile(ctx->radius);
     ctx->zchunk_opt = 0;
     ctx->tile_y = tti ? fd::tti_tile_y(ctx->radius) : fd::acoustic_tile_y(ctx->tile_cfg);
     ctx->nsrc_dev = ctx->nrec_dev = -1;
@@ -495,7 +549,7 @@ int32_t fd_setup(const fd_grid* grid, const fd_model* model, void* workspace,
     ctx->ck_store = nullptr;
     ctx->ck_nt = ctx->ck_interval = 0;
     ctx->ck_last_acc = false;
-    plan_workspace(grid, L, max_points, ctx, static_cast<char*>(workspace));
+    plan_workspace(grid, L, nshots, max_points, ctx, static_cast<char*>(workspace));
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     // zero everything (ghost rings must be zero), then derive coefficients
@@ -579,11 +633,27 @@ int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value) {
             return FD_OK;
         case FD_OPT_TILE: {
             if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "the tile option applies to acoustic");
-            const int v = value < 0 ? default_tile(ctx->radius) : (int)value;
+            const int v = value < 0 ? (ctx->nshots > 1 ? shots_tile(ctx->radius)
+                                                       : default_tile(ctx->radius))
+                                    : (int)value;
             if (v < 0 || v > 3) return fail(ctx, FD_ERR_INVALID_ARG, "tile configuration is 0..3");
+            if (ctx->nshots > 1 && ctx->shots_per_block > 1 && v != 0 && v != 2)
+                return fail(ctx, FD_ERR_UNSUPPORTED,
+                            "several shots per block are built for tile configurations 0 and 2");
             ctx->tile_cfg = v;
             ctx->tile_y = fd::acoustic_tile_y(v);
             ctx->flags_stale = true;  // rebuilt on the caller's stream by fd_forward
+            return FD_OK;
+        }
+        case FD_OPT_SHOTS_PER_BLOCK: {
+            const int v = value <= 0 ? default_shots_per_block(ctx->radius, ctx->nshots)
+                                     : (int)value;
+            if (v != 1 && v != 2 && v != 4)
+                return fail(ctx, FD_ERR_INVALID_ARG, "shots per block is 1, 2 or 4");
+            if (v > 1 && ctx->tile_cfg != 0 && ctx->tile_cfg != 2)
+                return fail(ctx, FD_ERR_UNSUPPORTED,
+                            "several shots per block are built for tile configurations 0 and 2");
+            ctx->shots_per_block = v;
             return FD_OK;
         }
         default: return fail(ctx, FD_ERR_INVALID_ARG, "unknown option");
@@ -594,6 +664,8 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
                    int32_t flags, void* stream) {
     if (!ctx) return FD_ERR_INVALID_ARG;
     ctx->err.clear();
+    if (ctx->nshots > 1)
+        return fail(ctx, FD_ERR_INVALID_ARG, "a context of several shots steps with fd_forward_shots");
     if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
     int32_t rc = check_points_arg(ctx, nt, src, "source");
     if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver");
@@ -632,10 +704,10 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
             he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, s);
             if (he == hipSuccess && nsrc)
                 he = fd::launch_inject(un, ctx->A, sig, spts, nsrc, src->data + (size_t)n * nsrc,
-                                       scale, ctx->L, nd, s);
+                                       scale, ctx->L, nd, ctx->L.volume, s);
             if (he == hipSuccess && nrec)
                 he = fd::launch_record(un, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
-                                       nd, s);
+                                       nd, ctx->L.volume, s);
             if (he != hipSuccess) return hip_fail(ctx, he, "step");
             ctx->cur = 1 - ctx->cur;
         }
@@ -657,7 +729,7 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
             p.w1y[j] = ctx->w1[1][j];
             p.w1z[j] = ctx->w1[2][j];
         }
-        tile_grid(ctx, ctx->tile_y, ctx->zchunk_opt, ctx->radius, nullptr, &p);
+        tile_grid(ctx, ctx->tile_y, ctx->zchunk_opt, ctx->radius, 1, nullptr, &p);
         for (int n = 0; n < nt; ++n) {
             float* pn = ctx->u[1 - ctx->cur];
             float* rn = ctx->r[1 - ctx->cur];
@@ -668,13 +740,15 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
             he = fd::launch_tti(p, ctx->radius, ctx->variant, s);
             if (he == hipSuccess && nsrc) {
                 const float* q = src->data + (size_t)n * nsrc;
-                he = fd::launch_inject(pn, ctx->A, sig, spts, nsrc, q, scale, ctx->L, 3, s);
+                he = fd::launch_inject(pn, ctx->A, sig, spts, nsrc, q, scale, ctx->L, 3,
+                                       ctx->L.volume, s);
                 if (he == hipSuccess)
-                    he = fd::launch_inject(rn, ctx->A, sig, spts, nsrc, q, scale, ctx->L, 3, s);
+                    he = fd::launch_inject(rn, ctx->A, sig, spts, nsrc, q, scale, ctx->L, 3,
+                                           ctx->L.volume, s);
             }
             if (he == hipSuccess && nrec)
                 he = fd::launch_record(pn, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
-                                       3, s);
+                                       3, ctx->L.volume, s);
             if (he != hipSuccess) return hip_fail(ctx, he, "step");
             ctx->cur = 1 - ctx->cur;
         }
@@ -684,7 +758,7 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
 
 int32_t fd_checkpoint_bytes(const fd_ctx* ctx, int32_t nt, int32_t interval, uint64_t* bytes,
                             int32_t* interval_out) {
-    if (!ctx || !bytes || nt < 0) return FD_ERR_INVALID_ARG;
+    if (!ctx || !bytes || nt < 0 || ctx->nshots > 1) return FD_ERR_INVALID_ARG;
     if (ctx->tti) return FD_ERR_UNSUPPORTED;
     const int I = resolve_interval(ctx, nt, interval);
     *bytes = plan_store(ctx, nt, I, nullptr).bytes;
@@ -718,15 +792,16 @@ hipError_t forward_segment(fd_ctx* ctx, fd::AcousticStep& p, const Store* slots,
         he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, acc, s);
         if (he == hipSuccess && nsrc) {
             const float* q = src->data + (size_t)n * nsrc;
-            he = fd::launch_inject(un, ctx->A, sig, ctx->pts, nsrc, q, scale, ctx->L, nd, s);
+            he = fd::launch_inject(un, ctx->A, sig, ctx->pts, nsrc, q, scale, ctx->L, nd,
+                                   ctx->L.volume, s);
             // the acceleration carries the source term without the damping divisor
             if (he == hipSuccess && acc)
                 he = fd::launch_inject(acc, ctx->A, nullptr, ctx->pts, nsrc, q, scale, ctx->L, nd,
-                                       s);
+                                       ctx->L.volume, s);
         }
         if (he == hipSuccess && nrec)
             he = fd::launch_record(un, ctx->pts + nsrc, nrec, rec->data + (size_t)n * nrec, 1.f,
-                                   ctx->L, nd, s);
+                                   ctx->L, nd, ctx->L.volume, s);
         ctx->cur = 1 - ctx->cur;
     }
     return he;
@@ -743,10 +818,11 @@ hipError_t adjoint_step(fd_ctx* ctx, fd::AcousticStep& p, const float* mu1, floa
     hipError_t he = acoustic_stencil(ctx, p, mu1, mu2, nullptr, s);
     if (he == hipSuccess && nadj)
         he = fd::launch_inject(mu2, ctx->A, sig, ctx->pts + nsrc, nadj,
-                               adj->data + (size_t)(k - 1) * nadj, 1.f, ctx->L, nd, s);
+                               adj->data + (size_t)(k - 1) * nadj, 1.f, ctx->L, nd, ctx->L.volume,
+                               s);
     if (he == hipSuccess && nsrc && qgrad)
         he = fd::launch_record(mu2, ctx->pts, nsrc, qgrad + (size_t)(k - 1) * nsrc,
-                               (float)(1.0 / cell_volume(ctx)), ctx->L, nd, s);
+                               (float)(1.0 / cell_volume(ctx)), ctx->L, nd, ctx->L.volume, s);
     return he;
 }
 
@@ -757,6 +833,8 @@ int32_t fd_forward_checkpointed(fd_ctx* ctx, int32_t nt, const fd_points* src,
                                 uint64_t store_bytes, void* stream) {
     if (!ctx) return FD_ERR_INVALID_ARG;
     ctx->err.clear();
+    if (ctx->nshots > 1)
+        return fail(ctx, FD_ERR_INVALID_ARG, "a context of several shots steps with fd_forward_shots");
     if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "gradients are built for acoustic only");
     if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
     int32_t rc = check_points_arg(ctx, nt, src, "source");
@@ -803,6 +881,8 @@ int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_poin
                     float* grad, float* wavelet_grad, void* stream) {
     if (!ctx) return FD_ERR_INVALID_ARG;
     ctx->err.clear();
+    if (ctx->nshots > 1)
+        return fail(ctx, FD_ERR_INVALID_ARG, "gradients are single-shot contexts");
     if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "gradients are built for acoustic only");
     if (wrt != FD_WRT_M && wrt != FD_WRT_VEL) return fail(ctx, FD_ERR_INVALID_ARG, "wrt");
     if (!grad) return fail(ctx, FD_ERR_INVALID_ARG, "grad is NULL");
@@ -853,6 +933,8 @@ int32_t fd_adjoint(fd_ctx* ctx, int32_t nt, const fd_points* adj, const fd_point
                    void* stream) {
     if (!ctx) return FD_ERR_INVALID_ARG;
     ctx->err.clear();
+    if (ctx->nshots > 1)
+        return fail(ctx, FD_ERR_INVALID_ARG, "a context of several shots steps with fd_forward_shots");
     if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "the adjoint is built for acoustic only");
     if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
     int32_t rc = check_points_arg(ctx, nt, adj, "adjoint source");
@@ -882,30 +964,104 @@ int32_t fd_adjoint(fd_ctx* ctx, int32_t nt, const fd_points* adj, const fd_point
     return FD_OK;
 }
 
-static float* field_ptr(fd_ctx* ctx, int32_t which) {
+int32_t fd_forward_shots(fd_ctx* ctx, int32_t nt, const fd_points* src, const int32_t* src_counts,
+                         const fd_points* rec, const int32_t* rec_counts, int32_t flags,
+                         void* stream) {
+    if (!ctx) return FD_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "several shots are built for acoustic only");
+    if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
+    int32_t rc = check_points_arg(ctx, nt, src, "source");
+    if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver");
+    if (rc != FD_OK) return rc;
+    const int nsrc = src ? src->n : 0, nrec = rec ? rec->n : 0;
+    if ((int64_t)nsrc + nrec > ctx->max_points)
+        return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
+    // per-shot counts must cover the points exactly
+    auto check_counts = [&](const int32_t* k, int n, const char* what) -> int32_t {
+        if (n == 0) return FD_OK;
+        if (!k) return fail(ctx, FD_ERR_INVALID_ARG, std::string(what) + " counts missing");
+        int64_t t = 0;
+        for (int i = 0; i < ctx->nshots; ++i) {
+            if (k[i] < 0) return fail(ctx, FD_ERR_INVALID_ARG, std::string(what) + " count < 0");
+            t += k[i];
+        }
+        if (t != n)
+            return fail(ctx, FD_ERR_INVALID_ARG, std::string(what) + " counts do not sum to n");
+        return FD_OK;
+    };
+    rc = check_counts(src_counts, nsrc, "source");
+    if (rc == FD_OK) rc = check_counts(rec_counts, nrec, "receiver");
+    if (rc != FD_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nd = ctx->g.ndim;
+    rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nrec, rec ? rec->coords : nullptr,
+                     "source", "receiver", s, nsrc ? src_counts : nullptr,
+                     nrec ? rec_counts : nullptr);
+    if (rc != FD_OK) return rc;
+    hipError_t he = hipSuccess;
+    if (ctx->flags_stale) {
+        he = refresh_flags(ctx, s);
+        if (he != hipSuccess) return hip_fail(ctx, he, "damping flags");
+        ctx->flags_stale = false;
+    }
+    if (flags & FD_ZERO_STATE)
+        for (int k = 0; k < 2 && he == hipSuccess; ++k)
+            he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume * ctx->nshots, s);
+    if (he != hipSuccess) return hip_fail(ctx, he, "zero state");
+    const float scale = (float)(1.0 / cell_volume(ctx));
+    const float* sig = ctx->damping ? ctx->sig : nullptr;
+    fd::AcousticStep p = acoustic_params(ctx);
+    for (int n = 0; n < nt; ++n) {
+        float* un = ctx->u[1 - ctx->cur];
+        he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, s);
+        if (he == hipSuccess && nsrc)
+            he = fd::launch_inject(un, ctx->A, sig, ctx->pts, nsrc, src->data + (size_t)n * nsrc,
+                                   scale, ctx->L, nd, ctx->L.volume, s);
+        if (he == hipSuccess && nrec)
+            he = fd::launch_record(un, ctx->pts + nsrc, nrec, rec->data + (size_t)n * nrec, 1.f,
+                                   ctx->L, nd, ctx->L.volume, s);
+        if (he != hipSuccess) return hip_fail(ctx, he, "step");
+        ctx->cur = 1 - ctx->cur;
+    }
+    return FD_OK;
+}
+
+static float* field_ptr(fd_ctx* ctx, int32_t shot, int32_t which) {
+    if (shot < 0 || shot >= ctx->nshots) return nullptr;
+    const int64_t o = (int64_t)shot * ctx->L.volume;
     switch (which) {
-        case FD_FIELD_PREV: return ctx->u[1 - ctx->cur];
-        case FD_FIELD_CUR: return ctx->u[ctx->cur];
+        case FD_FIELD_PREV: return ctx->u[1 - ctx->cur] + o;
+        case FD_FIELD_CUR: return ctx->u[ctx->cur] + o;
         case FD_FIELD_R_PREV: return ctx->tti ? ctx->r[1 - ctx->cur] : nullptr;
         case FD_FIELD_R_CUR: return ctx->tti ? ctx->r[ctx->cur] : nullptr;
         default: return nullptr;
     }
 }
 
-int32_t fd_get_field(fd_ctx* ctx, int32_t which, float* dst, void* stream) {
+int32_t fd_get_shot_field(fd_ctx* ctx, int32_t shot, int32_t which, float* dst, void* stream) {
     if (!ctx) return FD_ERR_INVALID_ARG;
-    float* f = field_ptr(ctx, which);
-    if (!f || !dst) return fail(ctx, FD_ERR_INVALID_ARG, "bad field selector or pointer");
+    float* f = field_ptr(ctx, shot, which);
+    if (!f || !dst) return fail(ctx, FD_ERR_INVALID_ARG, "bad shot, field selector or pointer");
     const hipError_t he = fd::launch_pack(f, dst, ctx->L, static_cast<hipStream_t>(stream));
     return he == hipSuccess ? FD_OK : hip_fail(ctx, he, "get_field");
 }
 
-int32_t fd_set_field(fd_ctx* ctx, int32_t which, const float* src, void* stream) {
+int32_t fd_set_shot_field(fd_ctx* ctx, int32_t shot, int32_t which, const float* src,
+                          void* stream) {
     if (!ctx) return FD_ERR_INVALID_ARG;
-    float* f = field_ptr(ctx, which);
-    if (!f || !src) return fail(ctx, FD_ERR_INVALID_ARG, "bad field selector or pointer");
+    float* f = field_ptr(ctx, shot, which);
+    if (!f || !src) return fail(ctx, FD_ERR_INVALID_ARG, "bad shot, field selector or pointer");
     const hipError_t he = fd::launch_unpack(src, f, ctx->L, static_cast<hipStream_t>(stream));
     return he == hipSuccess ? FD_OK : hip_fail(ctx, he, "set_field");
+}
+
+int32_t fd_get_field(fd_ctx* ctx, int32_t which, float* dst, void* stream) {
+    return fd_get_shot_field(ctx, 0, which, dst, stream);
+}
+
+int32_t fd_set_field(fd_ctx* ctx, int32_t which, const float* src, void* stream) {
+    return fd_set_shot_field(ctx, 0, which, src, stream);
 }
 
 int32_t fd_destroy(fd_ctx* ctx) {

@@ -108,8 +108,9 @@ constexpr uint32_t kOOB = 0x80000000u;  // any offset at or past the record limi
 constexpr int kRecords = 0x7fffffff;
 
 
-template <int R, int NW, int VY, bool ACC>
+template <int R, int NW, int VY, int SB, bool ACC>
 struct TiledAcoustic {
+    static_assert(!ACC || SB == 1, "acceleration output is single-shot");
     static constexpr int TY = NW * VY;
     static constexpr int LW = kTileX + 2 * R;
     static constexpr int LH = TY + 2 * R + 1;  // last row: sink for idle halo lanes
@@ -118,15 +119,17 @@ struct TiledAcoustic {
     static constexpr int NXH = (2 * R * TY + 64 * NW - 1) / (64 * NW);
     static constexpr int LDS_FLOATS = LH * LW;
     static constexpr int LQ_FLOATS = (R + 1) * TY * kTileX;  // ring of Lx + Ly, R+1 planes
+    static constexpr int SMEM_FLOATS = SB * (2 * LDS_FLOATS + LQ_FLOATS);
 
     const AcousticStep& p;
     float* lds;
-    const float* ub;  // tile origin (x0 - R, y0 - R) of u^n, plane 0
-    float* pb;        // same for u^{n-1} / u^{n+1}
-    float* cb;        // same for the acceleration output (ACC)
-    const float* ab;  // same for A
-    const float* sb;  // same for the damping coefficient
-    const float* zpl; // an all-zero plane (ghost plane of A) at the tile origin
+    const float* ub[SB];  // tile origin (x0 - R, y0 - R) of u^n, plane 0, per shot
+    float* pb[SB];        // same for u^{n-1} / u^{n+1}
+    int lim[SB];          // store record limit: 0 for the padding shots of a ragged group
+    float* cb;            // same for the acceleration output (ACC)
+    const float* ab;      // same for A (shared by the shots)
+    const float* sb;      // same for the damping coefficient
+    const float* zpl;     // an all-zero plane (ghost plane of A) at the tile origin
     cflag_t* flags;
     int64_t plane;
     int z0, z1, nz, ty, tx, nty, ntx;
@@ -134,13 +137,22 @@ struct TiledAcoustic {
     int flagbuf;      // damping flag of the next plane to fetch
     uint32_t oc[VY], ohy[NYH], ohx[NXH];  // byte offsets inside the tile (kOOB outside)
     int ly_[NYH], lx_[NXH];
-    float q[U][VY];   // centre values, planes z-R .. z+R
-    float* lq;        // LDS ring: Lx + Ly of planes z .. z+R, slot (plane - zs) mod (R+1)
-    float nxt[2][VY], prv[2][VY], aa[2][VY], sg[2][VY], hy[2][NYH], hx[2][NXH];
+    float q[SB][U][VY];  // centre values, planes z-R .. z+R
+    float nxt[2][SB][VY], prv[2][SB][VY], hy[2][SB][NYH], hx[2][SB][NXH];
+    float aa[2][VY], sg[2][VY];
     int damp[2];
 
-    __device__ TiledAcoustic(const AcousticStep& ps, float* l, float* lqr)
-        : p(ps), lds(l), lq(lqr) {}
+    __device__ TiledAcoustic(const AcousticStep& ps, float* l) : p(ps), lds(l) {}
+
+    // staging tile of shot s, register slot S; LDS ring of Lx + Ly of shot s
+    // (planes z .. z+R, slot (plane - zs) mod (R+1), each lane reading back
+    // only what it wrote)
+    __device__ __forceinline__ float* tile_of(int s, int S) const {
+        return lds + (2 * s + S) * LDS_FLOATS;
+    }
+    __device__ __forceinline__ float* ring_of(int s) const {
+        return lds + 2 * SB * LDS_FLOATS + s * LQ_FLOATS;
+    }
 
     __device__ __forceinline__ int flag_of(int z) const {
         if (z < 0 || z >= nz) return 0;
@@ -148,25 +160,32 @@ struct TiledAcoustic {
     }
 
     // Operands of the step whose output plane is zc: the head plane zc + R
-    // (centre and halo) and u^{n-1}, A and damping of plane zc.  Head planes
-    // beyond the grid are zero ghost planes of the volume; the operands of a
-    // step without output come from the all-zero plane.
+    // (centre and halo) of every shot and u^{n-1} of plane zc, with A and
+    // damping of plane zc loaded once for all shots.  Head planes beyond the
+    // grid are zero ghost planes of the volume; the operands of a step
+    // without output come from the all-zero plane.
     template <int S>
     __device__ __forceinline__ void fetch(int zc) {
-        const auto rh = rsrc(ub + (int64_t)(zc + R) * plane);
 #pragma unroll
-        for (int v = 0; v < VY; ++v) nxt[S][v] = bload(rh, oc[v]);
+        for (int s = 0; s < SB; ++s) {
+            const auto rh = rsrc(ub[s] + (int64_t)(zc + R) * plane);
 #pragma unroll
-        for (int k = 0; k < NYH; ++k) hy[S][k] = bload(rh, ohy[k]);
+            for (int v = 0; v < VY; ++v) nxt[S][s][v] = bload(rh, oc[v]);
 #pragma unroll
-        for (int k = 0; k < NXH; ++k) hx[S][k] = bload(rh, ohx[k]);
+            for (int k = 0; k < NYH; ++k) hy[S][s][k] = bload(rh, ohy[k]);
+#pragma unroll
+            for (int k = 0; k < NXH; ++k) hx[S][s][k] = bload(rh, ohx[k]);
+        }
         const bool out = zc >= z0 && zc < z1;
         const int64_t zo = (int64_t)zc * plane;
-        const auto rp = rsrc(out ? pb + zo : zpl);
         const auto ra = rsrc(out ? ab + zo : zpl);
 #pragma unroll
         for (int v = 0; v < VY; ++v) {
-            prv[S][v] = bload<kBufNT>(rp, oc[v]);
+#pragma unroll
+            for (int s = 0; s < SB; ++s) {
+                const auto rp = rsrc(out ? pb[s] + zo : zpl);
+                prv[S][s][v] = bload<kBufNT>(rp, oc[v]);
+            }
             aa[S][v] = bload<kBufNT>(ra, oc[v]);
         }
         const int d = (out && flagbuf != 0) ? 1 : 0;
@@ -184,59 +203,72 @@ struct TiledAcoustic {
         constexpr int H = (K + 2 * R) % U;  // head plane z + R
         constexpr int C = (K + R) % U;      // output plane z
 #pragma unroll
-        for (int v = 0; v < VY; ++v) q[H][v] = nxt[S][v];
-        float* tile = lds + S * LDS_FLOATS;
+        for (int s = 0; s < SB; ++s) {
 #pragma unroll
-        for (int v = 0; v < VY; ++v) tile[(R + w * VY + v) * LW + R + lane] = q[H][v];
+            for (int v = 0; v < VY; ++v) q[s][H][v] = nxt[S][s][v];
+            float* tile = tile_of(s, S);
 #pragma unroll
-        for (int k = 0; k < NYH; ++k) tile[ly_[k]] = hy[S][k];
+            for (int v = 0; v < VY; ++v) tile[(R + w * VY + v) * LW + R + lane] = q[s][H][v];
 #pragma unroll
-        for (int k = 0; k < NXH; ++k) tile[lx_[k]] = hx[S][k];
+            for (int k = 0; k < NYH; ++k) tile[ly_[k]] = hy[S][s][k];
+#pragma unroll
+            for (int k = 0; k < NXH; ++k) tile[lx_[k]] = hx[S][s][k];
+        }
         __syncthreads();
 
         // in-plane Laplacian of the head plane
-        float cw[VY + 2 * R];
 #pragma unroll
-        for (int k = 0; k < VY + 2 * R; ++k) cw[k] = tile[(w * VY + k) * LW + R + lane];
+        for (int s = 0; s < SB; ++s) {
+            const float* tile = tile_of(s, S);
+            float cw[VY + 2 * R];
 #pragma unroll
-        for (int v = 0; v < VY; ++v) {
-            const float* row = tile + (R + w * VY + v) * LW + R + lane;
-            float lx = 0.f, ly = 0.f;
+            for (int k = 0; k < VY + 2 * R; ++k) cw[k] = tile[(w * VY + k) * LW + R + lane];
 #pragma unroll
-            for (int j = 1; j <= R; ++j) lx = fmaf(p.cx[j], row[j] + row[-j], lx);
+            for (int v = 0; v < VY; ++v) {
+                const float* row = tile + (R + w * VY + v) * LW + R + lane;
+                float lx = 0.f, ly = 0.f;
 #pragma unroll
-            for (int j = 1; j <= R; ++j) ly = fmaf(p.cy[j], cw[v + R + j] + cw[v + R - j], ly);
-            lq[((K + R) % (R + 1)) * TY * kTileX + (w * VY + v) * kTileX + lane] = lx + ly;
+                for (int j = 1; j <= R; ++j) lx = fmaf(p.cx[j], row[j] + row[-j], lx);
+#pragma unroll
+                for (int j = 1; j <= R; ++j) ly = fmaf(p.cy[j], cw[v + R + j] + cw[v + R - j], ly);
+                ring_of(s)[((K + R) % (R + 1)) * TY * kTileX + (w * VY + v) * kTileX + lane] =
+                    lx + ly;
+            }
         }
 
         // output plane z; the R steps before the chunk store nothing (their
         // store buffer has a zero record limit), so every step issues the
         // same memory operations
-        const auto ro = __builtin_amdgcn_make_buffer_rsrc(pb + (int64_t)z * plane, 0,
-                                                          z >= z0 ? kRecords : 0, 0x00020000);
-        float nv[VY], av[VY];
 #pragma unroll
-        for (int v = 0; v < VY; ++v) {
-            float lz = 0.f;
+        for (int s = 0; s < SB; ++s) {
+            const auto ro = __builtin_amdgcn_make_buffer_rsrc(pb[s] + (int64_t)z * plane, 0,
+                                                              z >= z0 ? lim[s] : 0, 0x00020000);
+            float nv[VY], av[VY];
 #pragma unroll
-            for (int j = 1; j <= R; ++j)
-                lz = fmaf(p.cz[j], q[(C + j) % U][v] + q[(C + U - j) % U][v], lz);
-            const float lxy = lq[(K % (R + 1)) * TY * kTileX + (w * VY + v) * kTileX + lane];
-            const float lap = fmaf(p.c0, q[C][v], lxy + lz);
-            av[v] = aa[S][v] * lap;
-            nv[v] = fmaf(aa[S][v], lap, 2.f * q[C][v] - prv[S][v]);
-            if (damp[S]) {
-                const float sv = sg[S][v];
-                nv[v] = (2.f * q[C][v] - (1.f - sv) * prv[S][v] + aa[S][v] * lap) / (1.f + sv);
+            for (int v = 0; v < VY; ++v) {
+                float lz = 0.f;
+#pragma unroll
+                for (int j = 1; j <= R; ++j)
+                    lz = fmaf(p.cz[j], q[s][(C + j) % U][v] + q[s][(C + U - j) % U][v], lz);
+                const float lxy =
+                    ring_of(s)[(K % (R + 1)) * TY * kTileX + (w * VY + v) * kTileX + lane];
+                const float lap = fmaf(p.c0, q[s][C][v], lxy + lz);
+                av[v] = aa[S][v] * lap;
+                nv[v] = fmaf(aa[S][v], lap, 2.f * q[s][C][v] - prv[S][s][v]);
+                if (damp[S]) {
+                    const float sv = sg[S][v];
+                    nv[v] = (2.f * q[s][C][v] - (1.f - sv) * prv[S][s][v] + aa[S][v] * lap) /
+                            (1.f + sv);
+                }
             }
-        }
 #pragma unroll
-        for (int v = 0; v < VY; ++v) bstore_nt(ro, oc[v], nv[v]);
-        if constexpr (ACC) {
-            const auto rc = __builtin_amdgcn_make_buffer_rsrc(cb + (int64_t)z * plane, 0,
-                                                              z >= z0 ? kRecords : 0, 0x00020000);
+            for (int v = 0; v < VY; ++v) bstore_nt(ro, oc[v], nv[v]);
+            if constexpr (ACC) {
+                const auto rc = __builtin_amdgcn_make_buffer_rsrc(
+                    cb + (int64_t)z * plane, 0, z >= z0 ? kRecords : 0, 0x00020000);
 #pragma unroll
-            for (int v = 0; v < VY; ++v) bstore_nt(rc, oc[v], av[v]);
+                for (int v = 0; v < VY; ++v) bstore_nt(rc, oc[v], av[v]);
+            }
         }
         fetch<S>(z + 2);
         return true;
@@ -249,8 +281,9 @@ struct TiledAcoustic {
 
     __device__ void run() {
         const int b = blockIdx.x;
-        const int t = (b & 7) * (p.nblocks >> 3) + (b >> 3);
-        if (t >= p.ntiles) return;
+        const int item = (b & 7) * (p.nblocks >> 3) + (b >> 3);
+        if (item >= p.ntiles * p.ngroups) return;
+        const int t = item % p.ntiles, group = item / p.ntiles;
         ntx = p.ntx;
         nty = p.nty;
         tx = t % ntx;
@@ -268,9 +301,17 @@ struct TiledAcoustic {
         plane = p.L.plane;
         const int pitch = p.L.pitch;
         const int64_t org = p.L.origin + (int64_t)(y0 - R) * pitch + (x0 - R);
-        ub = p.uc + org;
-        pb = p.up + org;
-        cb = ACC ? p.acc + org : pb;
+#pragma unroll
+        for (int s = 0; s < SB; ++s) {
+            // padding shots of a ragged last group re-read the last shot and
+            // store nothing
+            const int shot = group * SB + s;
+            const int se = shot < p.nshots ? shot : p.nshots - 1;
+            ub[s] = p.uc + se * p.shot_stride + org;
+            pb[s] = p.up + se * p.shot_stride + org;
+            lim[s] = shot < p.nshots ? kRecords : 0;
+        }
+        cb = ACC ? p.acc + org : pb[0];
         ab = p.A + org;
         sb = (p.sig ? p.sig : p.A) + org;
         zpl = p.A + org - (int64_t)kGhostYZ * plane;
@@ -306,15 +347,19 @@ struct TiledAcoustic {
         // plane zs - R + i (mod U); planes z0-R .. z0-1 are primed here.
         const int zs = z0 - R;
 #pragma unroll
-        for (int i = 0; i < U; ++i)
+        for (int s = 0; s < SB; ++s)
 #pragma unroll
-            for (int v = 0; v < VY; ++v) q[i][v] = 0.f;
+            for (int i = 0; i < U; ++i)
 #pragma unroll
-        for (int i = R; i < 2 * R; ++i) {
-            const auto r = rsrc(ub + (int64_t)(zs - R + i) * plane);
+                for (int v = 0; v < VY; ++v) q[s][i][v] = 0.f;
 #pragma unroll
-            for (int v = 0; v < VY; ++v) q[i][v] = bload(r, oc[v]);
-        }
+        for (int s = 0; s < SB; ++s)
+#pragma unroll
+            for (int i = R; i < 2 * R; ++i) {
+                const auto r = rsrc(ub[s] + (int64_t)(zs - R + i) * plane);
+#pragma unroll
+                for (int v = 0; v < VY; ++v) q[s][i][v] = bload(r, oc[v]);
+            }
         flagbuf = flag_of(zs);
         fetch<0>(zs);
         fetch<1>(zs + 1);
@@ -323,47 +368,67 @@ struct TiledAcoustic {
     }
 };
 
-template <int R, int NW, int VY, bool ACC>
+template <int R, int NW, int VY, int SB, bool ACC>
 __global__ __launch_bounds__(64 * NW) void acoustic3d_tiled(AcousticStep p) {
-    using T = TiledAcoustic<R, NW, VY, ACC>;
-    __shared__ float lds[2 * T::LDS_FLOATS + T::LQ_FLOATS];
-    T k(p, lds, lds + 2 * T::LDS_FLOATS);
+    using T = TiledAcoustic<R, NW, VY, SB, ACC>;
+    __shared__ float lds[T::SMEM_FLOATS];
+    T k(p, lds);
     k.run();
 }
 
 template <int R>
 hipError_t launch_direct(const AcousticStep& p, int ndim, hipStream_t s) {
     const int gx = (p.L.nx + kTileX - 1) / kTileX;
-    if (ndim == 2) {
-        hipLaunchKernelGGL((acoustic_direct<2, R>), dim3(gx, (p.L.nz + 3) / 4), dim3(64, 4), 0, s,
-                           p);
-    } else {
-        hipLaunchKernelGGL((acoustic_direct<3, R>), dim3(gx, (p.L.ny + 3) / 4, p.L.nz),
-                           dim3(64, 4), 0, s, p);
+    // one launch per shot (the direct kernel serves 2D and the plain variant)
+    for (int shot = 0; shot < p.nshots; ++shot) {
+        AcousticStep q = p;
+        q.uc = p.uc + shot * p.shot_stride;
+        q.up = p.up + shot * p.shot_stride;
+        if (ndim == 2) {
+            hipLaunchKernelGGL((acoustic_direct<2, R>), dim3(gx, (p.L.nz + 3) / 4), dim3(64, 4),
+                               0, s, q);
+        } else {
+            hipLaunchKernelGGL((acoustic_direct<3, R>), dim3(gx, (p.L.ny + 3) / 4, p.L.nz),
+                               dim3(64, 4), 0, s, q);
+        }
     }
     return hipGetLastError();
 }
 
-template <int R, int NW, int VY>
+template <int R, int NW, int VY, int SB>
 hipError_t launch_tiled(const AcousticStep& p, hipStream_t s) {
-    if (p.acc)
-        hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, true>), dim3(p.nblocks), dim3(64 * NW), 0,
-                           s, p);
-    else
-        hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, false>), dim3(p.nblocks), dim3(64 * NW),
-                           0, s, p);
+    if constexpr (SB == 1) {
+        if (p.acc) {
+            hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, 1, true>), dim3(p.nblocks),
+                               dim3(64 * NW), 0, s, p);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, SB, false>), dim3(p.nblocks), dim3(64 * NW),
+                       0, s, p);
     return hipGetLastError();
 }
 
+// Tile configurations: 0 = 64 x 8 (4 waves x 2 rows), 1 = 64 x 16 (4 x 4),
+// 2 = 64 x 8 (8 waves x 1 row), 3 = 64 x 16 (8 x 2).  Shots per block 2 and 4
+// are built for configurations 0 and 2.
 template <int R>
-hipError_t launch_tiled_cfg(const AcousticStep& p, int cfg, hipStream_t s) {
-    switch (cfg) {
-        case 0: return launch_tiled<R, 4, 2>(p, s);   // 64 x 8 tile
-        case 1: return launch_tiled<R, 4, 4>(p, s);   // 64 x 16
-        case 2: return launch_tiled<R, 8, 1>(p, s);   // 64 x 8, 512 threads
-        case 3: return launch_tiled<R, 8, 2>(p, s);   // 64 x 16, 512 threads
-        default: return hipErrorInvalidValue;
+hipError_t launch_tiled_cfg(const AcousticStep& p, int cfg, int sb, hipStream_t s) {
+    if (sb == 1) {
+        switch (cfg) {
+            case 0: return launch_tiled<R, 4, 2, 1>(p, s);
+            case 1: return launch_tiled<R, 4, 4, 1>(p, s);
+            case 2: return launch_tiled<R, 8, 1, 1>(p, s);
+            case 3: return launch_tiled<R, 8, 2, 1>(p, s);
+            default: return hipErrorInvalidValue;
+        }
     }
+    if (p.acc) return hipErrorInvalidValue;
+    if (cfg == 0 && sb == 2) return launch_tiled<R, 4, 2, 2>(p, s);
+    if (cfg == 0 && sb == 4) return launch_tiled<R, 4, 2, 4>(p, s);
+    if (cfg == 2 && sb == 2) return launch_tiled<R, 8, 1, 2>(p, s);
+    if (cfg == 2 && sb == 4) return launch_tiled<R, 8, 1, 4>(p, s);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -374,11 +439,12 @@ int acoustic_tile_y(int cfg) {
 }
 
 hipError_t launch_acoustic(const AcousticStep& p, int ndim, int radius, int variant, int cfg,
-                           hipStream_t s) {
+                           int shots_per_block, hipStream_t s) {
     const bool tiled = ndim == 3 && variant == 0;
-#define FD_CASE(RR)                                                     \
-    case RR:                                                            \
-        return tiled ? launch_tiled_cfg<RR>(p, cfg, s) : launch_direct<RR>(p, ndim, s);
+#define FD_CASE(RR)                                                             \
+    case RR:                                                                    \
+        return tiled ? launch_tiled_cfg<RR>(p, cfg, shots_per_block, s)         \
+                     : launch_direct<RR>(p, ndim, s);
     switch (radius) {
         FD_CASE(1)
         FD_CASE(2)

@@ -129,12 +129,14 @@ __global__ __launch_bounds__(kBlock) void damping_flags_kernel(const float* __re
     if (threadIdx.x == 0) flags[((int64_t)z * nty + ty) * ntx + tx] = any ? 1 : 0;
 }
 
-// One thread per (point, corner): u[corner] += w A q scale / (1 + s).
+// One thread per (point, corner): u[corner] += w A q scale / (1 + s), in the
+// volume of the point's shot.
 __global__ __launch_bounds__(kBlock) void inject_kernel(float* u, const float* __restrict__ A,
                                                         const float* __restrict__ sig,
                                                         const SparsePoint* __restrict__ pts,
                                                         int n, const float* __restrict__ q,
-                                                        float scale, Layout L, int ndim) {
+                                                        float scale, Layout L, int ndim,
+                                                        int64_t shot_stride) {
     const int ncorner = ndim == 3 ? 8 : 4;
     const int k = blockIdx.x * kBlock + threadIdx.x;
     if (k >= n * ncorner) return;
@@ -147,18 +149,20 @@ __global__ __launch_bounds__(kBlock) void inject_kernel(float* u, const float* _
     if (w == 0.f) return;
     const int64_t i = P.base + dx + (int64_t)dy * L.pitch + (int64_t)dz * L.plane;
     const float sg = sig ? sig[i] : 0.f;
-    atomicAdd(&u[i], w * A[i] * q[s] * scale / (1.f + sg));
+    atomicAdd(&u[P.shot * shot_stride + i], w * A[i] * q[s] * scale / (1.f + sg));
 }
 
 // One thread per receiver: multilinear interpolation of u, times scale.
 __global__ __launch_bounds__(kBlock) void record_kernel(const float* __restrict__ u,
                                                         const SparsePoint* __restrict__ pts,
                                                         int n, float* __restrict__ out,
-                                                        float scale, Layout L, int ndim) {
+                                                        float scale, Layout L, int ndim,
+                                                        int64_t shot_stride) {
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
     const SparsePoint P = pts[j];
     const int ncorner = ndim == 3 ? 8 : 4;
+    const float* us = u + P.shot * shot_stride;
     float acc = 0.f;
     for (int c = 0; c < ncorner; ++c) {
         const int dx = c & 1;
@@ -166,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void record_kernel(const float* __restrict_
         const int dz = ndim == 3 ? c >> 2 : c >> 1;
         const float w =
             (dx ? P.fx : 1.f - P.fx) * (dy ? P.fy : 1.f - P.fy) * (dz ? P.fz : 1.f - P.fz);
-        if (w != 0.f) acc += w * u[P.base + dx + (int64_t)dy * L.pitch + (int64_t)dz * L.plane];
+        if (w != 0.f) acc += w * us[P.base + dx + (int64_t)dy * L.pitch + (int64_t)dz * L.plane];
     }
     out[j] = acc * scale;
 }
@@ -213,19 +217,19 @@ hipError_t launch_damping_flags(const float* sig, int32_t* flags, const Layout& 
 
 hipError_t launch_inject(float* u, const float* A, const float* sig, const SparsePoint* pts,
                          int n, const float* q, float scale, const Layout& L, int ndim,
-                         hipStream_t s) {
+                         int64_t shot_stride, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int total = n * (ndim == 3 ? 8 : 4);
     hipLaunchKernelGGL(inject_kernel, dim3((total + kBlock - 1) / kBlock), dim3(kBlock), 0, s, u,
-                       A, sig, pts, n, q, scale, L, ndim);
+                       A, sig, pts, n, q, scale, L, ndim, shot_stride);
     return hipGetLastError();
 }
 
 hipError_t launch_record(const float* u, const SparsePoint* pts, int n, float* out, float scale,
-                         const Layout& L, int ndim, hipStream_t s) {
+                         const Layout& L, int ndim, int64_t shot_stride, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(record_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, u, pts,
-                       n, out, scale, L, ndim);
+                       n, out, scale, L, ndim, shot_stride);
     return hipGetLastError();
 }
 

@@ -32,11 +32,12 @@ struct Layout {
 };
 
 // A sparse point after host-side preprocessing: flat offset of its lowest
-// interpolation corner and the fractional position in that cell per axis.
+// interpolation corner, the fractional position in that cell per axis, and
+// the shot (wavefield) it belongs to.
 struct SparsePoint {
     int64_t base;
     float fx, fy, fz;
-    int32_t pad;
+    int32_t shot;
 };
 
 // Acoustic step: u^{n+1} = [2u^n - (1-s)u^{n-1} + A L u^n]/(1+s), written
@@ -53,6 +54,8 @@ struct AcousticStep {
     Layout L;
     int32_t ntx, nty, nzc, zchunk;  // tile grid (tiled kernels)
     int32_t ntiles, nblocks;        // ntx*nty*nzc and the launched (multiple of 8) count
+    int32_t nshots, ngroups;        // wavefields advanced together; groups of shots per block
+    int64_t shot_stride;            // floats between the volumes of consecutive shots
 };
 
 // TTI step (3D).  Per point the coefficient fields are
@@ -107,11 +110,12 @@ hipError_t launch_damping_flags(const float* sig, int32_t* flags, const Layout& 
                                 int ntx, int nty, hipStream_t s);
 
 // sparse points
+// Shot k of a point writes / reads the volume u + k * shot_stride.
 hipError_t launch_inject(float* u, const float* A, const float* sig, const SparsePoint* pts,
                          int n, const float* q, float scale, const Layout& L, int ndim,
-                         hipStream_t s);
+                         int64_t shot_stride, hipStream_t s);
 hipError_t launch_record(const float* u, const SparsePoint* pts, int n, float* out, float scale,
-                         const Layout& L, int ndim, hipStream_t s);
+                         const Layout& L, int ndim, int64_t shot_stride, hipStream_t s);
 
 // adjoint / gradient
 // g[dense] += mu[vol] * acc[vol] over the interior (FP64 accumulation).
@@ -123,7 +127,7 @@ hipError_t launch_finish_gradient(const double* g, const float* A, float* out, c
 
 // stencils
 hipError_t launch_acoustic(const AcousticStep& p, int ndim, int radius, int variant, int tile_cfg,
-                           hipStream_t s);
+                           int shots_per_block, hipStream_t s);
 hipError_t launch_tti(const TTIStep& p, int radius, int variant, hipStream_t s);
 
 // Tile height (rows) of the tiled acoustic kernel for a tile configuration.

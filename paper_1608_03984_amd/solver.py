@@ -30,7 +30,7 @@ class Solver:
 
     def __init__(self, ndim, shape, spacing, nbl, space_order, dt, vel, eta=None, *,
                  physics="acoustic", epsilon=None, delta=None, theta=None, phi=None,
-                 max_points=1024, device="cuda"):
+                 max_points=1024, device="cuda", nshots=1):
         self.device = torch.device(device)
         self.ndim = int(ndim)
         self.grid = B.make_grid(ndim, shape, spacing, nbl, space_order, dt, PHYSICS[physics])
@@ -41,7 +41,8 @@ class Solver:
         else:
             self.field_shape = tuple(int(shape[a]) + 2 * nb for a in (2, 1, 0))
         self.max_points = int(max_points)
-        nbytes = B.fd_workspace_bytes(self.grid, self.max_points)
+        self.nshots = int(nshots)
+        nbytes = B.fd_workspace_bytes_shots(self.grid, self.nshots, self.max_points)
         self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self._ws.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
@@ -55,7 +56,8 @@ class Solver:
         m = B.FdModel()
         for k, v in keep.items():
             setattr(m, k, v.data_ptr() if v is not None else None)
-        self.ctx = B.fd_setup(self.grid, m, self._ws_ptr, nbytes, self.max_points, self.stream)
+        self.ctx = B.fd_setup_shots(self.grid, m, self.nshots, self._ws_ptr, nbytes,
+                                    self.max_points, self.stream)
         del keep  # fd_setup synchronised its stream: the model buffers are no longer read
 
     @property
@@ -133,16 +135,43 @@ class Solver:
         self._keep_adj = d
         return out
 
-    def get_field(self, which=B.FD_FIELD_CUR):
+    def forward_shots(self, nt, src_list, wavelet_list, rec_list, zero_state=True):
+        """nt steps of every shot: ``src_list[k]`` / ``rec_list[k]`` are shot
+        k's source and receiver coordinates, ``wavelet_list[k]`` its wavelets
+        [nt][nsrc_k].  Returns the list of per-shot traces [nt][nrec_k]."""
+        ns = self.nshots
+        srcs = [self._coords(c) if c is not None else np.zeros((0, self.ndim)) for c in src_list]
+        recs = [self._coords(c) if c is not None else np.zeros((0, self.ndim)) for c in rec_list]
+        if len(srcs) != ns or len(recs) != ns or len(wavelet_list) != ns:
+            raise ValueError("one source set, wavelet and receiver set per shot")
+        sc = np.array([len(c) for c in srcs], np.int32)
+        rc = np.array([len(c) for c in recs], np.int32)
+        src = np.concatenate(srcs) if sc.sum() else None
+        rec = np.concatenate(recs) if rc.sum() else None
+        q = None
+        if src is not None:
+            q = torch.cat([_dev(w, self.device).reshape(nt, int(k))
+                           for w, k in zip(wavelet_list, sc)], dim=1).contiguous()
+        traces = torch.empty((nt, int(rc.sum())), dtype=torch.float32, device=self.device)
+        B.fd_forward_shots(self.ctx, nt, src, sc if src is not None else None,
+                           q.data_ptr() if q is not None else 0, rec,
+                           rc if rec is not None else None,
+                           traces.data_ptr() if rec is not None else 0,
+                           B.FD_ZERO_STATE if zero_state else 0, self.stream)
+        self._keep_q = q
+        bounds = np.concatenate([[0], np.cumsum(rc)])
+        return [traces[:, bounds[k]:bounds[k + 1]] for k in range(ns)]
+
+    def get_field(self, which=B.FD_FIELD_CUR, shot=0):
         out = torch.empty(self.field_shape, dtype=torch.float32, device=self.device)
-        B.fd_get_field(self.ctx, which, out.data_ptr(), self.stream)
+        B.fd_get_shot_field(self.ctx, shot, which, out.data_ptr(), self.stream)
         return out
 
-    def set_field(self, which, value):
+    def set_field(self, which, value, shot=0):
         v = _dev(value, self.device)
         if tuple(v.shape) != self.field_shape:
             raise ValueError("field shape mismatch")
-        B.fd_set_field(self.ctx, which, v.data_ptr(), self.stream)
+        B.fd_set_shot_field(self.ctx, shot, which, v.data_ptr(), self.stream)
         self._keep_set = v
 
     def set_option(self, option, value):

@@ -1,0 +1,166 @@
+"""GPU parity of many shots advanced together (fd_setup_shots /
+fd_forward_shots) against single-shot runs of the same library and against
+the FP64 oracle.
+
+A multi-shot launch performs, per point and shot, the arithmetic of the
+single-shot kernel in the same order, so every shot's traces and final field
+must equal the single-shot run's bit for bit; against the oracle the
+full-run bar of the forward path applies (relative L2 1e-4).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_1608_03984_amd as P  # noqa: E402
+from paper_1608_03984_amd.solver import Solver  # noqa: E402
+from tests._gpu_util import THREADS, acoustic_problem, oracle_run_with_peak, rel, sample_points, say  # noqa: E402,E501
+from workloads import noise_state  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def survey(p, nshots, seed=3):
+    """Per-shot sources (one or two each), wavelets and receiver sets of
+    different sizes (one shot without receivers)."""
+    rng = np.random.default_rng(seed)
+    span = np.array(p.shape, np.float64) * np.array(p.spacing)
+    dims = [0, 2] if p.ndim == 2 else [0, 1, 2]
+    srcs, wavs, recs = [], [], []
+    for k in range(nshots):
+        ns = 1 + (k % 2)
+        srcs.append(0.15 * span[dims] + rng.random((ns, len(dims))) * 0.7 * span[dims])
+        wavs.append((p.wavelet * (1.0 + 0.3 * k) * rng.choice([-1.0, 1.0], ns)).astype(np.float32))
+        nr = 0 if k == 1 else 3 + 2 * k
+        recs.append(0.05 * span[dims] + rng.random((nr, len(dims))) * 0.9 * span[dims])
+    return srcs, wavs, recs
+
+
+def multi_run(p, srcs, wavs, recs, sb=None, tile=None):
+    s = Solver(p.ndim, p.shape, p.spacing, p.nbl, p.so, p.dt, p.vel, p.eta, nshots=len(srcs),
+               max_points=sum(len(a) for a in srcs) + sum(len(a) for a in recs) + 1)
+    if tile is not None:
+        s.set_option(P.FD_OPT_TILE, tile)
+    if sb is not None:
+        s.set_option(P.FD_OPT_SHOTS_PER_BLOCK, sb)
+    tr = s.forward_shots(p.nt, srcs, wavs, recs)
+    out = ([t.cpu().numpy() for t in tr],
+           [s.get_field(P.FD_FIELD_CUR, shot=k).cpu().numpy() for k in range(len(srcs))])
+    torch.cuda.synchronize()
+    s.close()
+    return out
+
+
+def single_run(p, src, wav, rec, tile=None):
+    s = Solver(p.ndim, p.shape, p.spacing, p.nbl, p.so, p.dt, p.vel, p.eta,
+               max_points=len(src) + len(rec) + 1)
+    if tile is not None:
+        s.set_option(P.FD_OPT_TILE, tile)
+    tr = s.forward(p.nt, src, wav, rec if len(rec) else None)
+    out = (tr.cpu().numpy() if tr is not None else np.zeros((p.nt, 0), np.float32),
+           s.get_field(P.FD_FIELD_CUR).cpu().numpy())
+    torch.cuda.synchronize()
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("so", [2, 4, 8, 12, 16])
+@pytest.mark.parametrize("sb,tile,nshots", [(2, 2, 5), (4, 2, 5), (2, 0, 3), (4, 0, 4)])
+def test_shots_equal_single_shot_runs(so, sb, tile, nshots):
+    """Ragged groups (5 shots in groups of 2 or 4) and full groups, both
+    tile configurations that are built for several shots per block."""
+    p = acoustic_problem(3, (90, 37, 41), 6, so, 60, seed=500 + so)
+    srcs, wavs, recs = survey(p, nshots)
+    say(f"case: shots so{so} sb{sb} tile{tile} nshots{nshots}")
+    trs, us = multi_run(p, srcs, wavs, recs, sb=sb, tile=tile)
+    for k in range(nshots):
+        t1, u1 = single_run(p, srcs[k], wavs[k], recs[k], tile=tile)
+        assert trs[k].shape == t1.shape
+        assert np.array_equal(trs[k], t1), f"shot {k} traces differ"
+        assert np.array_equal(us[k], u1), f"shot {k} field differs"
+
+
+@pytest.mark.parametrize("so", [4, 8])
+def test_shots_vs_oracle(so):
+    p = acoustic_problem(3, (70, 30, 34), 6, so, 80, seed=600 + so)
+    srcs, wavs, recs = survey(p, 3, seed=so)
+    say(f"case: shots vs oracle so{so}")
+    trs, us = multi_run(p, srcs, wavs, recs)
+    for k in range(3):
+        q = p
+        q.src, q.wavelet, q.rec = srcs[k], wavs[k], recs[k]
+        tref, st, peak = oracle_run_with_peak(q, chunk=20)
+        if recs[k].shape[0]:
+            assert rel(trs[k], tref) < 1e-4
+        assert np.linalg.norm(us[k] - st[1]) / peak < 1e-4
+
+
+def test_shots_2d_equal_single_shot_runs():
+    p = acoustic_problem(2, (67, 1, 45), 5, 8, 50, seed=700)
+    srcs, wavs, recs = survey(p, 4)
+    say("case: shots 2d")
+    trs, us = multi_run(p, srcs, wavs, recs)
+    for k in range(4):
+        t1, u1 = single_run(p, srcs[k], wavs[k], recs[k])
+        assert np.array_equal(trs[k], t1) and np.array_equal(us[k], u1)
+
+
+def test_shots_full_size_one_step_sampled():
+    """The 336^3 survey grid (256^3 + 40-point layer) with 16 shots in the
+    launch configuration of the benchmark: one step from a different
+    white-noise state per shot, sampled points of 4 shots against the oracle."""
+    from workloads import fwi_3d
+    p = fwi_3d(so=8, phys=256, nbl=40, nt=1, nshots=16, receivers="line")
+    shape = p.padded
+    say(f"case: shots full size {shape}")
+    s = Solver(3, p.shape, p.spacing, p.nbl, p.so, p.dt, p.vel, p.eta, nshots=16, max_points=4)
+    states = {}
+    for k in range(16):
+        up, uc = noise_state(shape, 100 + k), noise_state(shape, 200 + k)
+        s.set_field(P.FD_FIELD_PREV, up, shot=k)
+        s.set_field(P.FD_FIELD_CUR, uc, shot=k)
+        if k in (0, 5, 10, 15):
+            states[k] = (up, uc)
+        torch.cuda.synchronize()
+    s.forward_shots(1, [None] * 16, [np.zeros((1, 0), np.float32)] * 16, [None] * 16,
+                    zero_state=False)
+    got = {k: s.get_field(P.FD_FIELD_CUR, shot=k).cpu().numpy().ravel() for k in states}
+    torch.cuda.synchronize()
+    s.close()
+    pts = sample_points(shape, 3000, seed=9, radius=4)
+    oracle.set_threads(THREADS)
+    for k, (up, uc) in states.items():
+        ref = oracle.acoustic_step_points(3, p.spacing, p.dt, 8, p.vel, p.eta, up, uc, pts)
+        e = rel(got[k][pts], ref)
+        say(f"  shot {k}: sampled one-step rel L2 {e:.2e}")
+        assert e < 1e-5
+    oracle.set_threads(1)
+
+
+def test_shots_error_paths():
+    p = acoustic_problem(3, (20, 20, 20), 4, 4, 5, seed=8)
+    say("case: shots error paths")
+    s = Solver(3, p.shape, p.spacing, p.nbl, 4, p.dt, p.vel, p.eta, nshots=3, max_points=16)
+    with pytest.raises(P.FdError) as e:          # single-shot stepping on a survey context
+        s.forward(2, p.src, p.wavelet[:2], p.rec)
+    assert e.value.code == P.FD_ERR_INVALID_ARG
+    q = torch.zeros((5, 2), device="cuda")
+    with pytest.raises(P.FdError) as e:          # counts that do not sum to n
+        P._binding.fd_forward_shots(s.ctx, 5, np.zeros((2, 3)) + 50.0, [1, 0, 0], q.data_ptr(),
+                                    None, None, 0, P.FD_ZERO_STATE, s.stream)
+    assert e.value.code == P.FD_ERR_INVALID_ARG
+    with pytest.raises(P.FdError) as e:
+        s.set_option(P.FD_OPT_SHOTS_PER_BLOCK, 3)
+    assert e.value.code == P.FD_ERR_INVALID_ARG
+    with pytest.raises(P.FdError) as e:          # no such shot
+        s.get_field(P.FD_FIELD_CUR, shot=3)
+    assert e.value.code == P.FD_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    s.close()
+    from tests._gpu_util import tti_problem
+    t = tti_problem((16, 16, 16), 4, 4, 2, seed=2)
+    with pytest.raises(P.FdError) as e:
+        Solver(3, t.shape, t.spacing, t.nbl, 4, t.dt, t.vel, t.eta, physics="tti", epsilon=t.eps,
+               delta=t.delta, theta=t.theta, phi=t.phi, nshots=2)
+    assert e.value.code == P.FD_ERR_UNSUPPORTED

@@ -33,6 +33,13 @@ upsampled, rescaled, and edge-replicated into the layer):
     epsilon in [0, 0.3], delta in [0, 0.1] then delta <- min(delta, epsilon);
     tilt in [0, 45] deg, azimuth in [0, 90] deg; all smooth (correlation 16
     points); 10 Hz Ricker at the centre (x, y) and z = 25 m; 800 steps.
+  * ``fwi_3d``       -- the many-shot survey of a full-waveform inversion:
+    256^3 physical, h = 15 m, 40-point layer; true model of four layers
+    1.5 / 2.0 / 2.7 / 3.5 km/s times (1 + p), |p| <= 0.05 (correlation 12
+    points), start model the true model Gaussian-smoothed (sigma 10 points,
+    applied on the grid coarsened by COARSEN and upsampled back);
+    16 shots, one 8 Hz Ricker source each on a 4 x 4 grid at z = 30 m;
+    256 x 256 receivers at z = 30 m shared by all shots; 1200 steps.
 
 The time steps below are 0.4 times the CFL bound of Eq. (stability) at the
 workload's maximum velocity (for TTI, at the maximum horizontal P velocity
@@ -56,8 +63,11 @@ DT = {
     ("acoustic_3d", 16): 4.6117695896582113e-4,
     ("tti_3d", 4): 4.7057703276315164e-4,       # v_max 4200 * sqrt(1.6), h 12.5
     ("tti_3d", 8): 4.262068168671727e-4,
+    ("fwi_3d", 4): 8.16326530612245e-4,         # v_max 3675, h 15
+    ("fwi_3d", 8): 7.393559564382367e-4,
+    ("fwi_3d", 16): 6.917654384487317e-4,
 }
-VMAX = {"acoustic_2d": 1500.0, "acoustic_3d": 3675.0, "tti_3d": 4200.0}
+VMAX = {"acoustic_2d": 1500.0, "acoustic_3d": 3675.0, "tti_3d": 4200.0, "fwi_3d": 3675.0}
 EPS_MAX = 0.3
 
 
@@ -295,3 +305,49 @@ def tti_3d(so: int = 8, phys: int = 384, nbl: int = 40, nt: int = 800, seed: int
     w = ricker(10.0, dt, nt)[:, None]
     return Problem("tti_3d", 3, "tti", (n, n, n), (h, h, h), nbl, so, dt, nt, 10.0,
                    vel, eta, src, rec, w, eps=eps, delta=delta, theta=theta, phi=phi, seed=seed)
+
+
+def fwi_3d(so: int = 8, phys: int = 256, nbl: int = 40, nt: int = 1200, nshots: int = 16,
+           seed: int = 1612, receivers: str = "surface") -> Problem:
+    """Many-shot survey: true and smoothed start models, ``nshots`` single-
+    source shots on a square grid at z = 30 m, receivers shared by all shots.
+
+    ``src`` holds one source per shot ([nshots][3]); ``extra`` carries
+    ``vel_start`` (the smoothed start model) and ``nshots``.  ``receivers``
+    is "surface" (every physical (x, y) node) or "line" (every 8th node
+    along y = centre)."""
+    h = 15.0
+    n = phys
+    dt = DT[("fwi_3d", so)]
+    rng = np.random.default_rng(seed)
+    layers = np.array([1500.0, 2000.0, 2700.0, 3500.0])
+    z = np.arange(n)
+    vz = layers[np.minimum((4 * z) // n, 3)]
+    p = 0.05 * smooth_random((n, n, n), 12.0, rng)
+    vtrue = vz[:, None, None] * (1.0 + p)
+    # smoothed on the coarse grid (every COARSEN-th point), then upsampled
+    vstart = vtrue[::COARSEN, ::COARSEN, ::COARSEN]
+    for ax in range(3):
+        vstart = _smooth_axis(vstart, 10.0 / COARSEN, ax)
+    for ax in range(3):
+        vstart = _upsample_axis(vstart, n, ax)
+    vel = _pad_edge(vtrue, nbl).astype(np.float32)
+    vel0 = _pad_edge(vstart, nbl).astype(np.float32)
+    eta = damping_profile(vel.shape, nbl, (h, h, h), VMAX["fwi_3d"])
+    k = int(round(np.sqrt(nshots)))
+    k = k if k * k == nshots else nshots
+    side = np.linspace(0.125, 0.875, k) * (n - 1) * h
+    if k * k == nshots:
+        sx, sy = np.meshgrid(side, side, indexing="xy")
+        src = np.stack([sx.ravel(), sy.ravel(), np.full(nshots, 30.0)], axis=1)
+    else:
+        src = np.stack([side, np.full(nshots, (n - 1) * h / 2.0), np.full(nshots, 30.0)], axis=1)
+    if receivers == "surface":
+        gx, gy = np.meshgrid(np.arange(n) * h, np.arange(n) * h, indexing="xy")
+        rec = np.stack([gx.ravel(), gy.ravel(), np.full(n * n, 30.0)], axis=1)
+    else:
+        xs = np.arange(0, n, 8) * h
+        rec = np.stack([xs, np.full(xs.size, n * h / 2.0), np.full(xs.size, 30.0)], axis=1)
+    w = ricker(8.0, dt, nt)[:, None]
+    return Problem("fwi_3d", 3, "acoustic", (n, n, n), (h, h, h), nbl, so, dt, nt, 8.0, vel, eta,
+                   src, rec, w, seed=seed, extra={"vel_start": vel0, "nshots": nshots})
