@@ -61,7 +61,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-pass", action="store_true")
-    ap.add_argument("--workload", choices=("acoustic", "tti", "gradient"), default="acoustic")
+    ap.add_argument("--workload", choices=("acoustic", "tti", "gradient", "shots"),
+                    default="acoustic")
     ap.add_argument("--interval", type=int, default=0)
     return ap.parse_args()
 
@@ -288,6 +289,69 @@ def gradient_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def shots_bench(args):
+    """Survey of 16 shots on the 256^3 + 40-point-layer grid (336^3 points),
+    so 8, one source per shot, 256 x 256 receivers shared by the shots: all
+    shots advance in one launch per step, a group of shots sharing each read
+    of the model.  Algorithmic bytes per step and point: 12 per shot (read
+    u^n and u^(n-1), write u^(n+1)) plus 4 for dt^2 v^2 read once."""
+    import torch
+
+    from paper_1608_03984_amd.solver import Solver
+    from workloads import fwi_3d
+
+    S = 16
+    p = fwi_3d(so=8, phys=256 if args.phys == 512 else args.phys, nbl=40, nt=1, nshots=S,
+               receivers="surface")
+    npts = p.npoints
+    dev = torch.device("cuda:0")
+    from workloads import ricker
+    nt = args.warmup + args.steps
+    wav = ricker(8.0, p.dt, nt)[:, None].astype(np.float32)
+    srcs = [p.src[k:k + 1] for k in range(S)]
+    recs = [p.rec] * S
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    s = Solver(3, p.shape, p.spacing, p.nbl, p.so, p.dt, p.vel, p.eta, nshots=S,
+               max_points=S * (1 + p.rec.shape[0]), device=dev)
+    s.forward_shots(args.warmup, srcs, [wav[:args.warmup]] * S, recs)
+    tw = timed(lambda: s.forward_shots(args.steps, srcs, [wav[args.warmup:]] * S, recs,
+                                       zero_state=False), ev)
+    none, w0 = [None] * S, [np.zeros((1, 0), np.float32)] * S
+    s.forward_shots(args.warmup, none, w0, none, zero_state=False)
+    tk = timed(lambda: s.forward_shots(args.steps, none, w0, none, zero_state=False), ev)
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    # one shot at a time (a single-shot context, same kernels with one shot per block)
+    s1 = Solver(3, p.shape, p.spacing, p.nbl, p.so, p.dt, p.vel, p.eta,
+                max_points=1 + p.rec.shape[0], device=dev)
+    s1.forward(args.warmup, srcs[0], wav[:args.warmup], p.rec)
+    t1 = timed(lambda: s1.forward(args.steps, srcs[0], wav[args.warmup:], p.rec,
+                                  zero_state=False), ev)
+    s1.close()
+    kernel_s = tk / args.steps
+    ach = (12 * S + 4) * npts / kernel_s / 1e9
+    value = S * npts * args.steps / tw / 1e9
+    single = npts * args.steps / t1 / 1e9
+    line = {
+        "metric": "Gshot-pt/s (3D acoustic so8, 16 shots per launch)", "value": round(value, 3),
+        "unit": "Gpt/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(tw / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"survey of {S} shots, 3D acoustic {p.shape[0]}^3 + 40-pt layer "
+                               f"({p.padded[0]}^3 points), h=15 m, so 8, one source per shot, "
+                               f"{p.rec.shape[0]} receivers per shot", "points": npts,
+                   "shots": S},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "acoustic3d_tiled, 16 shots per launch "
+                               "((12 S + 4) B per point / launch time)"},
+        "stencil_ms": round(kernel_s * 1e3, 4),
+        "single_shot_gpts": round(single, 3), "speedup_vs_single_shot": round(value / single, 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -302,6 +366,9 @@ def main():
         return
     if args.workload == "gradient":
         gradient_bench(args)
+        return
+    if args.workload == "shots":
+        shots_bench(args)
         return
     import torch
 

@@ -273,15 +273,17 @@ bool locate(const fd_ctx* ctx, const double* c, SparsePoint* P) {
 // where the wider register queue leaves room for fewer rows per block.
 int default_tile(int radius) { return radius <= 4 ? 3 : 0; }
 
-// Several shots: 64 x 8 tiles of 512 threads (configuration 2) with 4 shots
-// per block up to radius 4 and 2 above (the register queues and LDS staging
-// grow with the shots per block).
+// Several shots (measured with 16 shots on the 336^3 survey grid): 4 shots
+// per block up to radius 2, 2 up to radius 6, one above, where the register
+// queues of several shots cost more occupancy than the shared model reads
+// save; 64 x 8 tiles of 512 threads (configuration 2), 64 x 8 of 256 above
+// radius 6.
 int default_shots_per_block(int radius, int nshots) {
     if (nshots <= 1) return 1;
-    const int sb = radius <= 4 ? 4 : 2;
+    const int sb = radius <= 2 ? 4 : (radius <= 6 ? 2 : 1);
     return nshots < sb ? (nshots >= 2 ? 2 : 1) : sb;
 }
-int shots_tile(int radius) { (void)radius; return 2; }
+int shots_tile(int radius) { return radius <= 6 ? 2 : 0; }
 
 void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, int ngroups,
                fd::AcousticStep* a, fd::TTIStep* t) {

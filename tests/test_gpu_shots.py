@@ -81,8 +81,10 @@ def test_shots_equal_single_shot_runs(so, sb, tile, nshots):
         assert np.array_equal(us[k], u1), f"shot {k} field differs"
 
 
-@pytest.mark.parametrize("so", [4, 8])
+@pytest.mark.parametrize("so", [4, 8, 16])
 def test_shots_vs_oracle(so):
+    """Default launch configuration per order (shots per block 2 or 4 up to
+    radius 6, one above)."""
     p = acoustic_problem(3, (70, 30, 34), 6, so, 80, seed=600 + so)
     srcs, wavs, recs = survey(p, 3, seed=so)
     say(f"case: shots vs oracle so{so}")
