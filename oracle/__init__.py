@@ -74,6 +74,10 @@ def _lib():
                                    dp, I, dp, dp, dp, dp]),
             "or_tti_step_points": (I, [lp, dp, D, I, fp, fp, fp, fp, fp, fp, fp, fp, fp, fp,
                                        L, lp, dp, dp]),
+            "or_vti_forward": (I, [I, lp, I, dp, D, I, fp, fp, fp, fp, I, dp, fp, I, dp, dp, I,
+                                   dp, dp, dp, dp]),
+            "or_vti_step_points": (I, [I, lp, dp, D, I, fp, fp, fp, fp, fp, fp, fp, fp, L, lp,
+                                       dp, dp]),
             "or_acoustic_adjoint": (I, [I, lp, I, dp, D, I, fp, fp, I, dp, dp, I, dp, dp, I]),
             "or_acoustic_gradient": (I, [I, lp, I, dp, D, I, fp, fp, I, dp, fp, I, dp, dp, I,
                                          dp, dp]),
@@ -159,6 +163,10 @@ def point_corners(ndim, shape_xyz, nbl, spacing, coord):
 # --------------------------------------------------------------------------
 # Acoustic
 # --------------------------------------------------------------------------
+
+def _pts(xyz, ndim):
+    return _as_f64(np.reshape(xyz, (-1, ndim)) if len(xyz) else np.zeros((0, ndim)))
+
 
 def _dims(ndim, field_shape):
     if ndim == 2:
@@ -275,12 +283,57 @@ def tti_step_points(spacing, dt, so, vel, eta, eps, delta, theta, phi, state, pt
 
 
 # --------------------------------------------------------------------------
-# Adjoint and gradient (acoustic)
+# VTI
 # --------------------------------------------------------------------------
 
-def _pts(xyz, ndim):
-    return _as_f64(np.reshape(xyz, (-1, ndim)) if len(xyz) else np.zeros((0, ndim)))
+def vti_forward(ndim, nbl, spacing, dt, so, vel, eta, eps, delta, src_xyz, wavelet, rec_xyz, nt,
+                state=None):
+    """VTI forward run (2D or 3D); ``state`` = (p_prev, p_cur, r_prev, r_cur)
+    or None.  Returns ``(traces[nt][nrec], (p_prev, p_cur, r_prev, r_cur))``."""
+    vel = _as_f32(vel)
+    shape = vel.shape
+    n = _dims(ndim, shape)
+    h = _as_f64(spacing)
+    src = _pts(src_xyz, ndim)
+    rec = _pts(rec_xyz, ndim)
+    nsrc, nrec = src.shape[0], rec.shape[0]
+    q = _as_f32(np.reshape(wavelet, (nt, nsrc)) if nsrc else np.zeros((nt, 0)))
+    if state is None:
+        st = [np.zeros(shape) for _ in range(4)]
+    else:
+        st = [np.array(x, dtype=np.float64, copy=True) for x in state]
+    tr = np.zeros((nt, max(nrec, 1)))
+    rc = _lib().or_vti_forward(
+        int(ndim), _l(n), int(nbl), _d(h), float(dt), int(so), _f(vel), _f(_as_f32(eta)),
+        _f(_as_f32(eps)), _f(_as_f32(delta)), int(nsrc), _d(src), _f(q), int(nrec), _d(rec),
+        _d(tr), int(nt), *[_d(x) for x in st])
+    if rc != 0:
+        raise ValueError("oracle rejected the VTI problem")
+    return tr[:, :nrec], tuple(st)
 
+
+def vti_step_points(ndim, spacing, dt, so, vel, eta, eps, delta, state, pts):
+    """One source-free VTI step at flat indices ``pts`` from an FP32 state
+    (p_prev, p_cur, r_prev, r_cur); returns (p_next, r_next) in FP64."""
+    vel = _as_f32(vel)
+    n = _dims(ndim, vel.shape)
+    h = _as_f64(spacing)
+    pts = np.ascontiguousarray(pts, dtype=np.int64)
+    op = np.zeros(pts.size)
+    orr = np.zeros(pts.size)
+    st = [_as_f32(x) for x in state]
+    rc = _lib().or_vti_step_points(
+        int(ndim), _l(n), _d(h), float(dt), int(so), _f(vel), _f(_as_f32(eta)),
+        _f(_as_f32(eps)), _f(_as_f32(delta)), *[_f(x) for x in st], int(pts.size), _l(pts),
+        _d(op), _d(orr))
+    if rc != 0:
+        raise ValueError("oracle rejected the VTI step")
+    return op, orr
+
+
+# --------------------------------------------------------------------------
+# Adjoint and gradient (acoustic)
+# --------------------------------------------------------------------------
 
 def acoustic_adjoint(ndim, nbl, spacing, dt, so, vel, eta, src_xyz, rec_xyz, d, nt):
     """F^T d: the transpose of the (zero-initial-state) map wavelet -> traces,

@@ -23,6 +23,8 @@
  *       * a damping layer (the paper leaves boundary treatment out of the
  *         model, section 2): u_tt + eta u_t = v^2 (lap u + q),
  *       * receivers sampled from the freshly updated field;
+ *   - the VTI pseudo-acoustic system, Eq. (vVTI), with the horizontal operator
+ *     D_xx (2D) or D_xx + D_yy (3D);
  *   - the TTI pseudo-acoustic system, Eq. (TTI), with the rotated operators of
  *     Eq. (DiffOp) written out term by term (G_xbar_xbar, G_ybar_ybar,
  *     G_zbar_zbar), cross derivatives as products of two first-derivative
@@ -536,6 +538,110 @@ int or_tti_step_points(const long* nxyz, const double* h, double dt, int so,
         long ix = i % n.nx, iy = (i / n.nx) % n.ny, iz = i / (n.nx * n.ny);
         tti_point(pp, pc, rp, rc, vel, eta, eps, delta, theta, phi, n, w2, w1, r, h, dt, ix, iy,
                   iz, &out_p[k], &out_r[k]);
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* VTI pseudo-acoustic system, Eq. (vVTI)                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Second derivative of f along one axis (0 = x, 1 = y, 2 = z) at a point:
+ * (w_0 f + sum_j w_j (f[+j] + f[-j])) / h_axis^2. */
+static double d2_axis(fld_t f, dims_t n, const double* w, int r, const double* h, long ix,
+                      long iy, long iz, int axis) {
+    long ex = axis == 0, ey = axis == 1, ez = axis == 2;
+    double acc = w[0] * at(f, n, ix, iy, iz);
+    for (int j = 1; j <= r; ++j)
+        acc += w[j] * (at(f, n, ix + j * ex, iy + j * ey, iz + j * ez) +
+                       at(f, n, ix - j * ex, iy - j * ey, iz - j * ez));
+    return acc / (h[axis] * h[axis]);
+}
+
+/* One VTI update at one point, Eq. (vVTI) with m = 1/v^2 and damping, the
+ * horizontal operator D_xx in 2D and D_xx + D_yy in 3D:
+ *   p+ = [2p - (1-s)p- + A((1+2eps) Dh p + sqrt(1+2delta) D_zz r)]/(1+s)
+ *   r+ = [2r - (1-s)r- + A(sqrt(1+2delta) Dh p + D_zz r)]/(1+s)            */
+static void vti_point(fld_t pp, fld_t pc, fld_t rp, fld_t rc, const float* vel, const float* eta,
+                      const float* eps, const float* delta, dims_t n, int ndim, const double* w,
+                      int r, const double* h, double dt, long ix, long iy, long iz, double* pn,
+                      double* rn) {
+    long i = (iz * n.ny + iy) * n.nx + ix;
+    double v = (double)vel[i];
+    double A = dt * dt * v * v;
+    double s = eta ? 0.5 * dt * (double)eta[i] : 0.0;
+    double dh = d2_axis(pc, n, w, r, h, ix, iy, iz, 0);
+    if (ndim == 3) dh += d2_axis(pc, n, w, r, h, ix, iy, iz, 1);
+    double dzz = d2_axis(rc, n, w, r, h, ix, iy, iz, 2);
+    double e2 = 1.0 + 2.0 * (double)eps[i];
+    double sd = sqrt(1.0 + 2.0 * (double)delta[i]);
+    *pn = (2.0 * fget(pc, i) - (1.0 - s) * fget(pp, i) + A * (e2 * dh + sd * dzz)) / (1.0 + s);
+    *rn = (2.0 * fget(rc, i) - (1.0 - s) * fget(rp, i) + A * (sd * dh + dzz)) / (1.0 + s);
+}
+
+/* VTI forward run (2D or 3D; 2D is ny = 1).  The source enters p and r;
+ * receivers sample p. */
+int or_vti_forward(int ndim, const long* nxyz, int nbl, const double* h, double dt, int so,
+                   const float* vel, const float* eta, const float* eps, const float* delta,
+                   int nsrc, const double* src_xyz, const float* wavelet,
+                   int nrec, const double* rec_xyz, double* traces,
+                   int nt, double* p_prev, double* p_cur, double* r_prev, double* r_cur) {
+    dims_t n = {nxyz[0], nxyz[1], nxyz[2]};
+    int r = so / 2;
+    double w[64];
+    if ((ndim != 2 && ndim != 3) || so < 2 || so % 2 || r > 63 || nt < 0) return OR_BAD;
+    if (ndim == 2 && n.ny != 1) return OR_BAD;
+    if (!check_points(ndim, n, nbl, h, nsrc, src_xyz)) return OR_BAD;
+    if (!check_points(ndim, n, nbl, h, nrec, rec_xyz)) return OR_BAD;
+    or_weights_d2(r, w);
+    long N = n.nx * n.ny * n.nz;
+    double* pn = (double*)malloc(sizeof(double) * (size_t)N);
+    double* rn = (double*)malloc(sizeof(double) * (size_t)N);
+    if (!pn || !rn) { free(pn); free(rn); return OR_BAD; }
+    for (int t = 0; t < nt; ++t) {
+        fld_t pp = {p_prev, NULL}, pc = {p_cur, NULL}, rp = {r_prev, NULL}, rc = {r_cur, NULL};
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+        for (long iz = 0; iz < n.nz; ++iz)
+            for (long iy = 0; iy < n.ny; ++iy)
+                for (long ix = 0; ix < n.nx; ++ix) {
+                    long i = (iz * n.ny + iy) * n.nx + ix;
+                    vti_point(pp, pc, rp, rc, vel, eta, eps, delta, n, ndim, w, r, h, dt, ix, iy,
+                              iz, &pn[i], &rn[i]);
+                }
+        const float* q = wavelet + (long)t * nsrc;
+        inject(pn, vel, eta, n, ndim, nbl, h, dt, nsrc, src_xyz, q);
+        inject(rn, vel, eta, n, ndim, nbl, h, dt, nsrc, src_xyz, q);
+        if (nrec > 0) record(pn, n, ndim, nbl, h, nrec, rec_xyz, traces + (long)t * nrec);
+        memcpy(p_prev, p_cur, sizeof(double) * (size_t)N);
+        memcpy(p_cur, pn, sizeof(double) * (size_t)N);
+        memcpy(r_prev, r_cur, sizeof(double) * (size_t)N);
+        memcpy(r_cur, rn, sizeof(double) * (size_t)N);
+    }
+    free(pn);
+    free(rn);
+    return OR_OK;
+}
+
+/* One VTI step at the listed points from an FP32 state (no source). */
+int or_vti_step_points(int ndim, const long* nxyz, const double* h, double dt, int so,
+                       const float* vel, const float* eta, const float* eps, const float* delta,
+                       const float* p_prev, const float* p_cur, const float* r_prev,
+                       const float* r_cur, long npts, const long* pts, double* out_p,
+                       double* out_r) {
+    dims_t n = {nxyz[0], nxyz[1], nxyz[2]};
+    int r = so / 2;
+    double w[64];
+    if ((ndim != 2 && ndim != 3) || so < 2 || so % 2 || r > 63) return OR_BAD;
+    or_weights_d2(r, w);
+    fld_t pp = {NULL, p_prev}, pc = {NULL, p_cur}, rp = {NULL, r_prev}, rc = {NULL, r_cur};
+    long N = n.nx * n.ny * n.nz;
+#pragma omp parallel for schedule(static) num_threads(g_threads)
+    for (long k = 0; k < npts; ++k) {
+        long i = pts[k];
+        if (i < 0 || i >= N) { out_p[k] = NAN; out_r[k] = NAN; continue; }
+        long ix = i % n.nx, iy = (i / n.nx) % n.ny, iz = i / (n.nx * n.ny);
+        vti_point(pp, pc, rp, rc, vel, eta, eps, delta, n, ndim, w, r, h, dt, ix, iy, iz,
+                  &out_p[k], &out_r[k]);
     }
     return OR_OK;
 }

@@ -15,6 +15,7 @@ import oracle
 from tests import test_oracle_acoustic as ta
 from tests import test_oracle_adjoint as tadj
 from tests import test_oracle_tti as tt
+from tests import test_oracle_vti as tv
 from tests import test_oracle_weights as tw
 
 SRC = Path(oracle.__file__).resolve().parent / "fd_oracle.c"
@@ -61,6 +62,11 @@ TTI = [
     lambda: tt.test_rotated_operators_dense_geometric(2),
     lambda: tt.test_tti_plane_wave_exact(4),
     tt.test_dense_bruteforce_tti_run,
+]
+VTI = [
+    lambda: tv.test_dense_bruteforce_vti_run(2, 8),
+    lambda: tv.test_dense_bruteforce_vti_run(3, 4),
+    lambda: tv.test_vti_plane_wave_exact(3, 2),
 ]
 ADJOINT = [
     lambda: tadj.test_adjoint_equals_dense_transpose(4),
@@ -109,6 +115,13 @@ MUTANTS = [
     ("tti coupling", "A * (e2 * hp + sd * gr.gzz)", "A * (e2 * hp + gr.gzz)", TTI),
     # TTI: Gzz coefficient of dzz uses sin instead of cos
     ("Gzz dzz", "+ ct * ct * d.dzz\n", "+ st * st * d.dzz\n", TTI),
+    # VTI: anisotropy factors exchanged in the p equation
+    ("vti factors", "A * (e2 * dh + sd * dzz)", "A * (sd * dh + e2 * dzz)", VTI),
+    # VTI: D_yy missing from the horizontal operator in 3D
+    ("vti dyy", "    if (ndim == 3) dh += d2_axis(pc, n, w, r, h, ix, iy, iz, 1);\n", "", VTI),
+    # VTI: vertical derivative taken of p instead of r
+    ("vti dzz field", "double dzz = d2_axis(rc, n, w, r, h, ix, iy, iz, 2);",
+     "double dzz = d2_axis(pc, n, w, r, h, ix, iy, iz, 2);", VTI),
     # adjoint: wrong sign of the damping factor on lambda^{k+2}
     ("adjoint damping", "(1.0 - s) * l2[i];", "(1.0 + s) * l2[i];", ADJOINT),
     # adjoint: B L applied instead of its transpose L B
