@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-pass", action="store_true")
-    ap.add_argument("--workload", choices=("acoustic", "tti", "gradient", "shots"),
+    ap.add_argument("--workload", choices=("acoustic", "tti", "vti", "gradient", "shots"),
                     default="acoustic")
     ap.add_argument("--interval", type=int, default=0)
     return ap.parse_args()
@@ -181,23 +181,27 @@ def cpu_baseline(problem, seconds: float):
     }
 
 
-def tti_bench(args):
+def tti_bench(args, physics="tti"):
     """TTI pseudo-acoustic, 384^3 + 40-point layer (464^3), space order 8:
-    60 algorithmic bytes and 964 paper FLOPs per point update (Table 1)."""
+    60 algorithmic bytes and 964 paper FLOPs per point update (Table 1).
+    With physics "vti": the same model without tilt, 36 bytes and
+    2 (6k + 8) = 124 paper FLOPs per point update."""
     import torch
 
     from paper_1608_03984_amd.solver import Solver
-    from workloads import tti_3d
+    from workloads import tti_3d, vti_3d
 
     phys = 384 if args.phys == 512 else args.phys
-    p = tti_3d(so=8, phys=phys, nbl=40, nt=1, receivers="line")
+    gen = tti_3d if physics == "tti" else vti_3d
+    p = gen(so=8, phys=phys, nbl=40, nt=1, receivers="line")
+    nbytes, nflops = (60, 964) if physics == "tti" else (36, 12 * 9 + 16)
     npts = p.npoints
     dev = torch.device("cuda:0")
     nt = args.warmup + args.steps
     from workloads import ricker
     wav = torch.from_numpy(ricker(10.0, p.dt, nt)[:, None]).to(dev)
     traces = torch.empty((nt, p.rec.shape[0]), dtype=torch.float32, device=dev)
-    s = Solver(3, p.shape, p.spacing, p.nbl, 8, p.dt, p.vel, p.eta, physics="tti",
+    s = Solver(3, p.shape, p.spacing, p.nbl, 8, p.dt, p.vel, p.eta, physics=physics,
                epsilon=p.eps, delta=p.delta, theta=p.theta, phi=p.phi,
                max_points=1 + p.rec.shape[0], device=dev)
     ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -209,19 +213,21 @@ def tti_bench(args):
     ok = bool(torch.isfinite(traces).all().item())
     s.close()
     kernel_s = tk / args.steps
-    ach = 60 * npts / kernel_s / 1e9
+    ach = nbytes * npts / kernel_s / 1e9
+    name = physics.upper()
     line = {
-        "metric": "Gpt/s (3D TTI so8)", "value": round(npts * args.steps / tw / 1e9, 3),
+        "metric": f"Gpt/s (3D {name} so8)", "value": round(npts * args.steps / tw / 1e9, 3),
         "unit": "Gpt/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(tw / args.steps * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"3D TTI, {phys}^3 + 40-pt layer ({p.padded[0]}^3 points), "
-                               "h=12.5 m, layered v, smooth eps/delta/theta/phi, so 8",
+        "config": {"workload": f"3D {name}, {phys}^3 + 40-pt layer ({p.padded[0]}^3 points), "
+                               "h=12.5 m, layered v, smooth eps/delta"
+                               + ("/theta/phi" if physics == "tti" else "") + ", so 8",
                    "points": npts},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "TTI stencil"},
-        "gflops_paper": round(964 * npts / kernel_s / 1e9, 1),
+                     "kernel": f"{name} stencil ({nbytes} B per point update)"},
+        "gflops_paper": round(nflops * npts / kernel_s / 1e9, 1),
         "stencil_ms": round(kernel_s * 1e3, 4), "finite": ok,
     }
     print(json.dumps(line), flush=True)
@@ -361,8 +367,8 @@ def main():
     if args.profile_pass:
         profile_pass(args)
         return
-    if args.workload == "tti":
-        tti_bench(args)
+    if args.workload in ("tti", "vti"):
+        tti_bench(args, args.workload)
         return
     if args.workload == "gradient":
         gradient_bench(args)

@@ -61,13 +61,14 @@ extern "C" {
 /* Physics. */
 #define FD_ACOUSTIC 0 /* Eq. (Acou), 2D or 3D */
 #define FD_TTI 1      /* Eq. (TTI) with Eq. (DiffOp), 3D */
+#define FD_VTI 2      /* Eq. (vVTI), 2D (D_xx) or 3D (D_xx + D_yy as the horizontal operator) */
 
 /* Wavefield selectors for fd_get_field / fd_set_field.  Acoustic uses the
- * first two; TTI uses all four (p and r). */
-#define FD_FIELD_PREV 0   /* u^{n-1}  (TTI: p^{n-1}) */
-#define FD_FIELD_CUR 1    /* u^{n}    (TTI: p^{n})   */
-#define FD_FIELD_R_PREV 2 /* TTI r^{n-1} */
-#define FD_FIELD_R_CUR 3  /* TTI r^{n}   */
+ * first two; VTI and TTI use all four (p and r). */
+#define FD_FIELD_PREV 0   /* u^{n-1}  (VTI/TTI: p^{n-1}) */
+#define FD_FIELD_CUR 1    /* u^{n}    (VTI/TTI: p^{n})   */
+#define FD_FIELD_R_PREV 2 /* VTI/TTI r^{n-1} */
+#define FD_FIELD_R_CUR 3  /* VTI/TTI r^{n}   */
 
 /* fd_forward flags. */
 #define FD_ZERO_STATE 1 /* start from the zero state of Eq. (Acou)/(TTI) */
@@ -78,7 +79,7 @@ extern "C" {
 typedef struct fd_grid {
     int32_t ndim;        /* 2 or 3 */
     int32_t space_order; /* even, 2..FD_MAX_SPACE_ORDER */
-    int32_t physics;     /* FD_ACOUSTIC or FD_TTI (TTI needs ndim == 3) */
+    int32_t physics;     /* FD_ACOUSTIC, FD_VTI or FD_TTI (TTI needs ndim == 3) */
     int32_t nbl;         /* absorbing-layer points added on both sides of each axis */
     int64_t shape[3];    /* physical points (nx, ny, nz); ny must be 1 in 2D */
     double spacing[3];   /* (hx, hy, hz) in metres; hy ignored in 2D */
@@ -91,10 +92,10 @@ typedef struct fd_model {
     const float* vel;     /* P velocity v (m/s), v > 0; m = 1/v^2 */
     const float* eta;     /* damping rate (1/s) of u_tt + eta u_t = v^2 (lap u + q);
                              NULL = no damping */
-    const float* epsilon; /* TTI: Thomsen epsilon (NULL for acoustic) */
-    const float* delta;   /* TTI: Thomsen delta, 0 <= ... <= epsilon is required */
-    const float* theta;   /* TTI: tilt from the vertical (radians) */
-    const float* phi;     /* TTI: azimuth (radians) */
+    const float* epsilon; /* VTI/TTI: Thomsen epsilon (NULL for acoustic) */
+    const float* delta;   /* VTI/TTI: Thomsen delta, 0 <= ... <= epsilon is required */
+    const float* theta;   /* TTI: tilt from the vertical (radians; NULL for VTI) */
+    const float* phi;     /* TTI: azimuth (radians; NULL for VTI) */
 } fd_model;
 
 /* A set of sparse points (sources or receivers). */

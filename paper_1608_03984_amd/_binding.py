@@ -21,6 +21,7 @@ FD_ERR_NONFINITE = 6
 
 FD_ACOUSTIC = 0
 FD_TTI = 1
+FD_VTI = 2
 
 FD_FIELD_PREV = 0
 FD_FIELD_CUR = 1

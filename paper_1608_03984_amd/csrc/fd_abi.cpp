@@ -26,6 +26,7 @@ struct fd_ctx {
     Layout L;
     bool damping;
     bool tti;
+    bool vti;
     int32_t nshots;  // wavefields advanced together on the one model
     int32_t max_points;
     // workspace regions
@@ -131,7 +132,7 @@ int32_t validate_grid(const fd_grid* g, std::string& msg) {
         return msg = "space_order must be even and >= 2", FD_ERR_INVALID_ARG;
     if (g->space_order > FD_MAX_SPACE_ORDER)
         return msg = "space_order above 16 is not built", FD_ERR_UNSUPPORTED;
-    if (g->physics != FD_ACOUSTIC && g->physics != FD_TTI)
+    if (g->physics != FD_ACOUSTIC && g->physics != FD_TTI && g->physics != FD_VTI)
         return msg = "unknown physics", FD_ERR_INVALID_ARG;
     if (g->physics == FD_TTI && g->ndim != 3)
         return msg = "TTI is built for 3D grids only", FD_ERR_UNSUPPORTED;
@@ -190,18 +191,20 @@ uint64_t plan_workspace(const fd_grid* g, const Layout& L, int32_t nshots, int32
     Carve cv;
     const uint64_t vol = (uint64_t)L.volume * sizeof(float);
     const bool tti = g->physics == FD_TTI;
+    const bool aniso = g->physics != FD_ACOUSTIC;  // two wavefields p, r and e, d
     const uint64_t o_red = cv.take(256);
     const uint64_t o_A = cv.take(vol);
     const uint64_t o_sig = cv.take(vol);
     uint64_t o_e = 0, o_d = 0, o_c[6] = {0, 0, 0, 0, 0, 0}, o_r[2] = {0, 0};
-    if (tti) {
+    if (aniso) {
         o_e = cv.take(vol);
         o_d = cv.take(vol);
-        for (int k = 0; k < 6; ++k) o_c[k] = cv.take(vol);
     }
+    if (tti)
+        for (int k = 0; k < 6; ++k) o_c[k] = cv.take(vol);
     const uint64_t o_u0 = cv.take(vol * (uint64_t)nshots);
     const uint64_t o_u1 = cv.take(vol * (uint64_t)nshots);
-    if (tti) {
+    if (aniso) {
         o_r[0] = cv.take(vol);
         o_r[1] = cv.take(vol);
     }
@@ -213,13 +216,13 @@ uint64_t plan_workspace(const fd_grid* g, const Layout& L, int32_t nshots, int32
         ctx->reduce = reinterpret_cast<uint32_t*>(base + o_red);
         ctx->A = reinterpret_cast<float*>(base + o_A);
         ctx->sig = reinterpret_cast<float*>(base + o_sig);
-        ctx->e = tti ? reinterpret_cast<float*>(base + o_e) : nullptr;
-        ctx->d = tti ? reinterpret_cast<float*>(base + o_d) : nullptr;
+        ctx->e = aniso ? reinterpret_cast<float*>(base + o_e) : nullptr;
+        ctx->d = aniso ? reinterpret_cast<float*>(base + o_d) : nullptr;
         for (int k = 0; k < 6; ++k) ctx->c[k] = tti ? reinterpret_cast<float*>(base + o_c[k]) : nullptr;
         ctx->u[0] = reinterpret_cast<float*>(base + o_u0);
         ctx->u[1] = reinterpret_cast<float*>(base + o_u1);
-        ctx->r[0] = tti ? reinterpret_cast<float*>(base + o_r[0]) : nullptr;
-        ctx->r[1] = tti ? reinterpret_cast<float*>(base + o_r[1]) : nullptr;
+        ctx->r[0] = aniso ? reinterpret_cast<float*>(base + o_r[0]) : nullptr;
+        ctx->r[1] = aniso ? reinterpret_cast<float*>(base + o_r[1]) : nullptr;
         ctx->dflag = reinterpret_cast<int32_t*>(base + o_flag);
         ctx->pts = reinterpret_cast<SparsePoint*>(base + o_pts);
     }
@@ -523,9 +526,11 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
     if (!model || !model->vel || max_points < 0 || !workspace) return FD_ERR_INVALID_ARG;
     if (nshots < 1 || nshots > kMaxShots) return FD_ERR_INVALID_ARG;
     const bool tti = grid->physics == FD_TTI;
-    if (tti && nshots > 1) return FD_ERR_UNSUPPORTED;
+    const bool vti = grid->physics == FD_VTI;
+    if ((tti || vti) && nshots > 1) return FD_ERR_UNSUPPORTED;
     if (tti && (!model->epsilon || !model->delta || !model->theta || !model->phi))
         return FD_ERR_INVALID_ARG;
+    if (vti && (!model->epsilon || !model->delta)) return FD_ERR_INVALID_ARG;
     if (reinterpret_cast<uintptr_t>(workspace) % 256) return FD_ERR_WORKSPACE;
     const Layout L = make_layout(grid);
     const uint64_t need = plan_workspace(grid, L, nshots, max_points, nullptr, nullptr);
@@ -537,6 +542,7 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
     ctx->radius = grid->space_order / 2;
     ctx->L = L;
     ctx->tti = tti;
+    ctx->vti = vti;
     ctx->nshots = nshots;
     ctx->shots_per_block = default_shots_per_block(ctx->radius, nshots);
     ctx->damping = model->eta != nullptr;
@@ -545,7 +551,8 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
     ctx->variant = 0;
     ctx->tile_cfg = nshots > 1 ? shots_tile(ctx->radius) : default_tile(ctx->radius);
     ctx->zchunk_opt = 0;
-    ctx->tile_y = tti ? fd::tti_tile_y(ctx->radius) : fd::acoustic_tile_y(ctx->tile_cfg);
+    ctx->tile_y = tti ? fd::tti_tile_y(ctx->radius)
+                      : vti ? fd::vti_tile_y(ctx->radius) : fd::acoustic_tile_y(ctx->tile_cfg);
     ctx->nsrc_dev = ctx->nrec_dev = -1;
     ctx->flags_stale = false;
     ctx->ck_store = nullptr;
@@ -568,8 +575,8 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
     sa.eta = model->eta;
     sa.eps = model->epsilon;
     sa.delta = model->delta;
-    sa.theta = model->theta;
-    sa.phi = model->phi;
+    sa.theta = tti ? model->theta : nullptr;
+    sa.phi = tti ? model->phi : nullptr;
     sa.dt = (float)grid->dt;
     sa.A = ctx->A;
     sa.sig = ctx->damping ? ctx->sig : nullptr;
@@ -634,7 +641,8 @@ int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value) {
             ctx->zchunk_opt = (int)value;
             return FD_OK;
         case FD_OPT_TILE: {
-            if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "the tile option applies to acoustic");
+            if (ctx->tti || ctx->vti)
+                return fail(ctx, FD_ERR_UNSUPPORTED, "the tile option applies to acoustic");
             const int v = value < 0 ? (ctx->nshots > 1 ? shots_tile(ctx->radius)
                                                        : default_tile(ctx->radius))
                                     : (int)value;
@@ -689,7 +697,7 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
     }
     if (flags & FD_ZERO_STATE) {
         for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume, s);
-        if (ctx->tti)
+        if (ctx->r[0])
             for (int k = 0; k < 2 && he == hipSuccess; ++k)
                 he = fd::launch_fill_zero(ctx->r[k], ctx->L.volume, s);
         if (he != hipSuccess) return hip_fail(ctx, he, "zero state");
@@ -699,7 +707,53 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
     const SparsePoint* rpts = ctx->pts + nsrc;
     const float* sig = ctx->damping ? ctx->sig : nullptr;
 
-    if (!ctx->tti) {
+    if (ctx->vti) {
+        fd::VTIStep p;
+        std::memset(&p, 0, sizeof(p));
+        p.A = ctx->A;
+        p.sig = sig;
+        p.dflag = nd == 3 ? ctx->dflag : nullptr;
+        p.e = ctx->e;
+        p.d = ctx->d;
+        p.L = ctx->L;
+        p.c0h = (float)((double)ctx->w2[0][0] + (nd == 3 ? (double)ctx->w2[1][0] : 0.0));
+        p.c0z = ctx->w2[2][0];
+        for (int j = 0; j <= fd::kMaxRadius; ++j) {
+            p.cx[j] = ctx->w2[0][j];
+            p.cy[j] = ctx->w2[1][j];
+            p.cz[j] = ctx->w2[2][j];
+        }
+        fd::TTIStep grid_only;
+        tile_grid(ctx, ctx->tile_y, ctx->zchunk_opt, ctx->radius, 1, nullptr, &grid_only);
+        p.ntx = grid_only.ntx;
+        p.nty = grid_only.nty;
+        p.nzc = grid_only.nzc;
+        p.zchunk = grid_only.zchunk;
+        p.ntiles = grid_only.ntiles;
+        p.nblocks = grid_only.nblocks;
+        for (int n = 0; n < nt; ++n) {
+            float* pn = ctx->u[1 - ctx->cur];
+            float* rn = ctx->r[1 - ctx->cur];
+            p.pc = ctx->u[ctx->cur];
+            p.rc = ctx->r[ctx->cur];
+            p.pp = pn;
+            p.rp = rn;
+            he = fd::launch_vti(p, nd, ctx->radius, ctx->variant, s);
+            if (he == hipSuccess && nsrc) {
+                const float* q = src->data + (size_t)n * nsrc;
+                he = fd::launch_inject(pn, ctx->A, sig, spts, nsrc, q, scale, ctx->L, nd,
+                                       ctx->L.volume, s);
+                if (he == hipSuccess)
+                    he = fd::launch_inject(rn, ctx->A, sig, spts, nsrc, q, scale, ctx->L, nd,
+                                           ctx->L.volume, s);
+            }
+            if (he == hipSuccess && nrec)
+                he = fd::launch_record(pn, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
+                                       nd, ctx->L.volume, s);
+            if (he != hipSuccess) return hip_fail(ctx, he, "step");
+            ctx->cur = 1 - ctx->cur;
+        }
+    } else if (!ctx->tti) {
         fd::AcousticStep p = acoustic_params(ctx);
         for (int n = 0; n < nt; ++n) {
             float* un = ctx->u[1 - ctx->cur];  // holds u^{n-1}, receives u^{n+1}
@@ -761,7 +815,7 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
 int32_t fd_checkpoint_bytes(const fd_ctx* ctx, int32_t nt, int32_t interval, uint64_t* bytes,
                             int32_t* interval_out) {
     if (!ctx || !bytes || nt < 0 || ctx->nshots > 1) return FD_ERR_INVALID_ARG;
-    if (ctx->tti) return FD_ERR_UNSUPPORTED;
+    if (ctx->tti || ctx->vti) return FD_ERR_UNSUPPORTED;
     const int I = resolve_interval(ctx, nt, interval);
     *bytes = plan_store(ctx, nt, I, nullptr).bytes;
     if (interval_out) *interval_out = I;
@@ -837,7 +891,8 @@ int32_t fd_forward_checkpointed(fd_ctx* ctx, int32_t nt, const fd_points* src,
     ctx->err.clear();
     if (ctx->nshots > 1)
         return fail(ctx, FD_ERR_INVALID_ARG, "a context of several shots steps with fd_forward_shots");
-    if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "gradients are built for acoustic only");
+    if (ctx->tti || ctx->vti)
+        return fail(ctx, FD_ERR_UNSUPPORTED, "gradients are built for acoustic only");
     if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
     int32_t rc = check_points_arg(ctx, nt, src, "source");
     if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver");
@@ -885,7 +940,8 @@ int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_poin
     ctx->err.clear();
     if (ctx->nshots > 1)
         return fail(ctx, FD_ERR_INVALID_ARG, "gradients are single-shot contexts");
-    if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "gradients are built for acoustic only");
+    if (ctx->tti || ctx->vti)
+        return fail(ctx, FD_ERR_UNSUPPORTED, "gradients are built for acoustic only");
     if (wrt != FD_WRT_M && wrt != FD_WRT_VEL) return fail(ctx, FD_ERR_INVALID_ARG, "wrt");
     if (!grad) return fail(ctx, FD_ERR_INVALID_ARG, "grad is NULL");
     const int I = resolve_interval(ctx, nt, interval);
@@ -937,7 +993,8 @@ int32_t fd_adjoint(fd_ctx* ctx, int32_t nt, const fd_points* adj, const fd_point
     ctx->err.clear();
     if (ctx->nshots > 1)
         return fail(ctx, FD_ERR_INVALID_ARG, "a context of several shots steps with fd_forward_shots");
-    if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "the adjoint is built for acoustic only");
+    if (ctx->tti || ctx->vti)
+        return fail(ctx, FD_ERR_UNSUPPORTED, "the adjoint is built for acoustic only");
     if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
     int32_t rc = check_points_arg(ctx, nt, adj, "adjoint source");
     if (rc == FD_OK) rc = check_points_arg(ctx, nt, out, "source");
@@ -971,7 +1028,8 @@ int32_t fd_forward_shots(fd_ctx* ctx, int32_t nt, const fd_points* src, const in
                          void* stream) {
     if (!ctx) return FD_ERR_INVALID_ARG;
     ctx->err.clear();
-    if (ctx->tti) return fail(ctx, FD_ERR_UNSUPPORTED, "several shots are built for acoustic only");
+    if (ctx->tti || ctx->vti)
+        return fail(ctx, FD_ERR_UNSUPPORTED, "several shots are built for acoustic only");
     if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
     int32_t rc = check_points_arg(ctx, nt, src, "source");
     if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver");
@@ -1035,8 +1093,8 @@ static float* field_ptr(fd_ctx* ctx, int32_t shot, int32_t which) {
     switch (which) {
         case FD_FIELD_PREV: return ctx->u[1 - ctx->cur] + o;
         case FD_FIELD_CUR: return ctx->u[ctx->cur] + o;
-        case FD_FIELD_R_PREV: return ctx->tti ? ctx->r[1 - ctx->cur] : nullptr;
-        case FD_FIELD_R_CUR: return ctx->tti ? ctx->r[ctx->cur] : nullptr;
+        case FD_FIELD_R_PREV: return ctx->r[0] ? ctx->r[1 - ctx->cur] : nullptr;
+        case FD_FIELD_R_CUR: return ctx->r[0] ? ctx->r[ctx->cur] : nullptr;
         default: return nullptr;
     }
 }

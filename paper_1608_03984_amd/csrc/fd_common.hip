@@ -46,11 +46,12 @@ __global__ __launch_bounds__(kBlock) void unpack_kernel(const float* __restrict_
 }
 
 // Derive the per-point coefficients the time loop reads, in FP32:
-//   A = (dt v)^2, s = eta dt / 2, and for TTI e = 1 + 2 eps, d = sqrt(1 + 2 delta),
+//   A = (dt v)^2, s = eta dt / 2, for VTI and TTI e = 1 + 2 eps,
+//   d = sqrt(1 + 2 delta), and for TTI
 //   c1 = sin^2(th) cos^2(ph), c2 = sin^2(th) sin^2(ph), c3 = cos^2(th),
 //   c4 = sin(2ph) sin^2(th), c5 = sin(ph) sin(2th), c6 = cos(ph) sin(2th)
 // (the weights of Dxx, Dyy, Dzz, Dxy, Dyz, Dxz in G_zbar_zbar, Eq. (DiffOp)).
-// Also reduces the fastest speed (v, or v sqrt(1 + 2 eps) for TTI) and flags
+// Also reduces the fastest speed (v, or v sqrt(1 + 2 eps) for VTI and TTI) and flags
 // invalid values and delta > eps.
 __global__ __launch_bounds__(kBlock) void setup_kernel(SetupArgs a) {
     __shared__ float smax[kBlock / 64];
@@ -75,15 +76,20 @@ __global__ __launch_bounds__(kBlock) void setup_kernel(SetupArgs a) {
             if (!(et >= 0.f) || !isfinite(et)) bad = 1;
             a.sig[k] = 0.5f * a.dt * et;
         }
-        if (a.e) {
-            const float ep = a.eps[i], de = a.delta[i], th = a.theta[i], ph = a.phi[i];
-            if (!isfinite(ep) || !isfinite(de) || !isfinite(th) || !isfinite(ph)) bad = 1;
+        if (a.e) {  // VTI and TTI
+            const float ep = a.eps[i], de = a.delta[i];
+            if (!isfinite(ep) || !isfinite(de)) bad = 1;
             const float e = 1.f + 2.f * ep;
             const float d2 = 1.f + 2.f * de;
             if (!(e > 0.f) || !(d2 > 0.f)) bad = 1;
             if (de > ep) dgt = 1;
             a.e[k] = e;
             a.d[k] = sqrtf(fmaxf(d2, 0.f));
+            speed = v * sqrtf(fmaxf(e, 0.f));
+        }
+        if (a.c[0]) {  // TTI rotation factors
+            const float th = a.theta[i], ph = a.phi[i];
+            if (!isfinite(th) || !isfinite(ph)) bad = 1;
             float st, ct, sp, cp;
             sincosf(th, &st, &ct);
             sincosf(ph, &sp, &cp);
@@ -94,7 +100,6 @@ __global__ __launch_bounds__(kBlock) void setup_kernel(SetupArgs a) {
             a.c[3][k] = 2.f * sp * cp * st2;
             a.c[4][k] = sp * 2.f * st * ct;
             a.c[5][k] = cp * 2.f * st * ct;
-            speed = v * sqrtf(fmaxf(e, 0.f));
         }
         if (isfinite(speed)) vmax = fmaxf(vmax, speed);
     }

@@ -80,6 +80,26 @@ struct TTIStep {
     int32_t ntiles, nblocks;
 };
 
+// VTI step (2D or 3D), Eq. (vVTI): Dh = Dxx (+ Dyy in 3D) of p and Dzz of r,
+//   Dh p = c0h p + sum_j cx[j](p[x+j]+p[x-j]) + cy[j](p[y+j]+p[y-j]),
+//   Dzz r = c0z r + sum_j cz[j](r[z+j]+r[z-j]).
+struct VTIStep {
+    const float* __restrict__ pc;
+    const float* __restrict__ rc;
+    float* pp;  // p^{n-1} in, p^{n+1} out
+    float* rp;  // r^{n-1} in, r^{n+1} out
+    const float* __restrict__ A;
+    const float* __restrict__ sig;
+    const int32_t* __restrict__ dflag;
+    const float* __restrict__ e;  // 1 + 2 eps
+    const float* __restrict__ d;  // sqrt(1 + 2 delta)
+    float c0h, c0z;
+    float cx[kMaxRadius + 1], cy[kMaxRadius + 1], cz[kMaxRadius + 1];
+    Layout L;
+    int32_t ntx, nty, nzc, zchunk;
+    int32_t ntiles, nblocks;
+};
+
 // ---------------------------------------------------------------------------
 // Launchers (defined in the .hip files), all asynchronous on `s`.
 // ---------------------------------------------------------------------------
@@ -129,9 +149,11 @@ hipError_t launch_finish_gradient(const double* g, const float* A, float* out, c
 hipError_t launch_acoustic(const AcousticStep& p, int ndim, int radius, int variant, int tile_cfg,
                            int shots_per_block, hipStream_t s);
 hipError_t launch_tti(const TTIStep& p, int radius, int variant, hipStream_t s);
+hipError_t launch_vti(const VTIStep& p, int ndim, int radius, int variant, hipStream_t s);
 
 // Tile height (rows) of the tiled acoustic kernel for a tile configuration.
 int acoustic_tile_y(int tile_cfg);
 int tti_tile_y(int radius);
+int vti_tile_y(int radius);
 
 }  // namespace fd

@@ -10,7 +10,7 @@ import torch
 
 from . import _binding as B
 
-PHYSICS = {"acoustic": B.FD_ACOUSTIC, "tti": B.FD_TTI}
+PHYSICS = {"acoustic": B.FD_ACOUSTIC, "tti": B.FD_TTI, "vti": B.FD_VTI}
 
 
 def _dev(a, device):

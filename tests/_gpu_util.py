@@ -68,6 +68,12 @@ def oracle_run_with_peak(p, chunk=10):
                                                      p.eta, p.src, p.wavelet[done:done + k], p.rec,
                                                      k, up, uc)
                 state = (up, uc)
+            elif p.physics == "vti":
+                tr, state = oracle.vti_forward(p.ndim, p.nbl, p.spacing, p.dt, p.so, p.vel,
+                                               p.eta, p.eps, p.delta, p.src,
+                                               p.wavelet[done:done + k], p.rec, k,
+                                               None if uc is None else state)
+                uc = state[1]
             else:
                 tr, state = oracle.tti_forward(p.nbl, p.spacing, p.dt, p.so, p.vel, p.eta, p.eps,
                                                p.delta, p.theta, p.phi, p.src,
@@ -123,3 +129,34 @@ def tti_problem(phys, nbl, so, nt, seed, h=(12.5, 12.5, 12.5), nrec=20):
     rec[1::2, 0] -= 0.3 * h[0]   # odd receivers off grid, all inside the array
     return Problem("tti-test", 3, "tti", (nx, ny, nz), h, nbl, so, dt, nt, f0, vel, eta, src, rec,
                    q, eps=eps, delta=delta, theta=theta, phi=phi, seed=seed)
+
+
+def vti_problem(ndim, phys, nbl, so, nt, seed, h=(12.5, 12.5, 12.5), nrec=20):
+    """Layered velocity with smooth epsilon and delta (delta <= epsilon), no
+    tilt: the VTI counterpart of ``tti_problem`` (2D uses the x-z plane)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = phys
+    pad = (nz + 2 * nbl, nx + 2 * nbl) if ndim == 2 else (nz + 2 * nbl, ny + 2 * nbl, nx + 2 * nbl)
+    zz = np.arange(pad[0])[(slice(None),) + (None,) * (ndim - 1)]
+    v = (1500.0 + 2500.0 * zz / pad[0]) * (1 + 0.05 * smooth_random(pad, 6.0, rng))
+    unit = lambda a: (a - a.min()) / (a.max() - a.min())
+    eps = 0.3 * unit(smooth_random(pad, 6.0, rng))
+    delta = np.minimum(0.1 * unit(smooth_random(pad, 6.0, rng)), eps)
+    vel, eps, delta = (a.astype(np.float32) for a in (v, eps, delta))
+    delta = np.minimum(delta, eps)
+    vmax = float(np.max(vel.astype(np.float64) * np.sqrt(1 + 2 * eps.astype(np.float64))))
+    eta = damping_profile(pad, nbl, h, float(vel.max()))
+    dt = 0.4 * oracle.cfl_dt(ndim, so, h, vmax)
+    f0 = 0.25 * 1500.0 / (6 * max(h))
+    q = ricker(f0, dt, nt)[:, None]
+    if ndim == 2:
+        src = np.array([[0.45 * nx * h[0] + 1.1, 0.4 * nz * h[2] + 0.7]])
+        xs = np.linspace(-nbl * h[0], (nx + nbl - 1) * h[0], nrec)
+        rec = np.stack([xs, np.full(nrec, 2.0 * h[2])], 1)
+    else:
+        src = np.array([[0.45 * nx * h[0] + 1.1, 0.5 * ny * h[1] - 2.3, 0.4 * nz * h[2] + 0.7]])
+        xs = np.linspace(-nbl * h[0], (nx + nbl - 1) * h[0], nrec)
+        rec = np.stack([xs, np.full(nrec, 0.5 * ny * h[1]), np.full(nrec, 2.0 * h[2])], 1)
+    rec[1::2, 0] -= 0.3 * h[0]
+    return Problem("vti-test", ndim, "vti", (nx, ny if ndim == 3 else 1, nz), h, nbl, so, dt, nt,
+                   f0, vel, eta, src, rec, q, eps=eps, delta=delta, seed=seed)

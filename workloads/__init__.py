@@ -33,6 +33,8 @@ upsampled, rescaled, and edge-replicated into the layer):
     epsilon in [0, 0.3], delta in [0, 0.1] then delta <- min(delta, epsilon);
     tilt in [0, 45] deg, azimuth in [0, 90] deg; all smooth (correlation 16
     points); 10 Hz Ricker at the centre (x, y) and z = 25 m; 800 steps.
+  * ``vti_3d``       -- the ``tti_3d`` model without tilt and azimuth (VTI
+    pseudo-acoustic), same grid, time steps and source.
   * ``fwi_3d``       -- the many-shot survey of a full-waveform inversion:
     256^3 physical, h = 15 m, 40-point layer; true model of four layers
     1.5 / 2.0 / 2.7 / 3.5 km/s times (1 + p), |p| <= 0.05 (correlation 12
@@ -351,3 +353,12 @@ def fwi_3d(so: int = 8, phys: int = 256, nbl: int = 40, nt: int = 1200, nshots: 
     w = ricker(8.0, dt, nt)[:, None]
     return Problem("fwi_3d", 3, "acoustic", (n, n, n), (h, h, h), nbl, so, dt, nt, 8.0, vel, eta,
                    src, rec, w, seed=seed, extra={"vel_start": vel0, "nshots": nshots})
+
+
+def vti_3d(so: int = 8, phys: int = 384, nbl: int = 40, nt: int = 800, seed: int = 1611,
+           receivers: str = "line") -> Problem:
+    """3D VTI pseudo-acoustic: the ``tti_3d`` velocity, epsilon and delta
+    fields (delta <= epsilon) with no tilt or azimuth."""
+    p = tti_3d(so=so, phys=phys, nbl=nbl, nt=nt, seed=seed, receivers=receivers)
+    p.name, p.physics, p.theta, p.phi = "vti_3d", "vti", None, None
+    return p
