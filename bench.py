@@ -61,7 +61,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-pass", action="store_true")
-    ap.add_argument("--workload", choices=("acoustic", "tti", "vti", "gradient", "shots"),
+    ap.add_argument("--workload",
+                    choices=("acoustic", "tti", "vti", "gradient", "shots", "cost"),
                     default="acoustic")
     ap.add_argument("--interval", type=int, default=0)
     return ap.parse_args()
@@ -358,6 +359,65 @@ def shots_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def cost_bench(args):
+    """Cost-to-solution of section 6 measured: the fixed physical problem of
+    Tables 2 and 3 (500^3 points at second order, p points per wavelength
+    from 6 down, the same final time) run for real at orders 2, 6, 12 and 16
+    (16 with p interpolated between the printed rows), against the MI355X
+    roofline prediction of the perfmodel module (Table 1 FLOPs, 16 B per
+    point, 8 TB/s).  Homogeneous v = 1500 m/s, h = 10 m at second order, no
+    absorbing layer, a 10 Hz Ricker source at the centre, 64 receivers."""
+    import torch
+
+    from paper_1608_03984_amd import perfmodel as M
+    from paper_1608_03984_amd.solver import Solver
+    from workloads import ricker
+
+    dev = torch.device("cuda:0")
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    rows = []
+    for order in (2, 6, 12, 16):
+        r = M.cost_row(order)
+        n = r.n_axis
+        h = 10.0 * r.h
+        v = 1500.0
+        dt = r.dt * 10.0 / v * (1.0 - 1e-6)     # inside the CFL bound by 1e-6
+        vel = np.full((n, n, n), v, np.float32)
+        src = np.array([[n * h / 2, n * h / 2, n * h / 2]])
+        xs = np.linspace(0.0, (n - 1) * h, 64)
+        rec = np.stack([xs, np.full(64, n * h / 2), np.full(64, 2 * h)], 1)
+        wav = ricker(10.0, dt, r.nt)[:, None].astype(np.float32)
+        s = Solver(3, (n, n, n), (h, h, h), 0, order, dt, vel, None, max_points=65, device=dev)
+        s.forward(5, src, wav[:5], rec)                         # warm-up
+        t = timed(lambda: s.forward(r.nt, src, wav, rec), ev)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        # the model's N is (500/h)^3; the run uses n_axis^3 points
+        pred = r.runtime_s(M.MI355X_HBM_GBS, M.MI355X_FP32_GFLOPS) * n ** 3 / r.N
+        rows.append({"order": order, "p": round(r.p, 4), "h_m": round(h, 3), "n_axis": n,
+                     "N_model": r.N, "points": n ** 3, "nt": r.nt,
+                     "gflop_paper": round(r.gflop, 1), "oi": round(r.oi(), 4),
+                     "predicted_s": round(pred, 4), "measured_s": round(t, 4),
+                     "frac_of_roofline": round(pred / t, 4),
+                     "gpts": round(n ** 3 * r.nt / t / 1e9, 2)})
+        print(f"# order {order}: {n}^3 x {r.nt} steps: {t:.3f} s (roofline {pred:.3f} s)",
+              file=sys.stderr, flush=True)
+    best = min(rows, key=lambda x: x["measured_s"])
+    line = {
+        "metric": "cost-to-solution s (3D acoustic, fixed physics of Tables 2-3)",
+        "value": best["measured_s"], "unit": "s", "n_gpus": 1, "steps": None,
+        "warmup": 5, "ms_per_step": None, "higher_is_better": False, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "fixed physical problem of Tables 2-3: 500^3 points at order 2, "
+                               "p points per wavelength 6/5/4/3.33 at orders 2/6/12/16, common "
+                               "final time of 1000 second-order steps, homogeneous 1500 m/s",
+                   "best_order": best["order"]},
+        "rows": rows,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -375,6 +435,9 @@ def main():
         return
     if args.workload == "shots":
         shots_bench(args)
+        return
+    if args.workload == "cost":
+        cost_bench(args)
         return
     import torch
 
