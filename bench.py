@@ -239,8 +239,9 @@ def gradient_bench(args):
     checkpointed forward run of ``--steps`` steps, then the adjoint run with
     segment recomputation and the imaging condition.  Algorithmic bytes per
     point and step: forward 16, recomputed forward 16 + 4 (acceleration
-    stored), adjoint 16, imaging 24 (two FP32 reads, FP64 accumulator read and
-    written)."""
+    stored), adjoint 16, imaging 16 (adjoint field and acceleration read,
+    FP32 partial sum read and written), plus 16 per point for each flush of
+    the partial sums into the total (every 32 steps)."""
     import torch
 
     from paper_1608_03984_amd.solver import Solver
@@ -275,7 +276,8 @@ def gradient_bench(args):
     t_all = r["t_fwd"] + r["t_grad"]
     I = r["interval"]
     last = nt - (nt - 1) // I * I           # steps of the last segment (not recomputed)
-    alg = npts * (16 * nt + 4 * last + 20 * (nt - last) + 16 * nt + 24 * nt)
+    flushes = (nt + 31) // 32
+    alg = npts * (16 * nt + 4 * last + 20 * (nt - last) + 16 * nt + 16 * nt + 16 * flushes)
     ach = alg / t_all / 1e9
     s.close()
     line = {

@@ -185,6 +185,11 @@ int min_tile_y() { return 8; }
 
 constexpr int32_t kMaxShots = 4096;
 
+// The imaging condition is summed in FP32 in two levels: a partial sum over
+// at most this many adjoint steps, then the running total (bounded rounding
+// without FP64 on the device).
+constexpr int kFlushSteps = 32;
+
 // Workspace plan; when base is non-null the pointers are filled in.
 uint64_t plan_workspace(const fd_grid* g, const Layout& L, int32_t nshots, int32_t max_points,
                         fd_ctx* ctx, char* base) {
@@ -419,14 +424,17 @@ hipError_t acoustic_stencil(const fd_ctx* ctx, fd::AcousticStep& p, const float*
 //   ck[2 * nck]  dense fields (u^{n-1}, u^n) at n = 0, I, 2I, ...
 //   acc[I]       padded volumes: accelerations of one segment
 //   mu[2]        padded volumes: adjoint levels
-//   g            dense FP64 gradient accumulator
+//   gpart        padded volume: partial sum of the imaging condition over at
+//                most kFlushSteps adjoint steps
+//   gsum         dense field: sum of the flushed partial sums
 struct Store {
     int nck = 0;
     int64_t dense = 0;       // floats per dense field (rounded to 64)
     float* ck = nullptr;
     float* acc = nullptr;
     float* mu[2] = {nullptr, nullptr};
-    double* g = nullptr;
+    float* gpart = nullptr;
+    float* gsum = nullptr;
     uint64_t bytes = 0;
     float* ckf(int k) const { return ck + (int64_t)k * dense; }
     float* slot(const fd_ctx* ctx, int i) const { return acc + (int64_t)i * ctx->L.volume; }
@@ -442,14 +450,16 @@ Store plan_store(const fd_ctx* ctx, int nt, int interval, char* base) {
     const uint64_t o_acc = cv.take((uint64_t)interval * L.volume * sizeof(float));
     const uint64_t o_mu0 = cv.take((uint64_t)L.volume * sizeof(float));
     const uint64_t o_mu1 = cv.take((uint64_t)L.volume * sizeof(float));
-    const uint64_t o_g = cv.take((uint64_t)st.dense * sizeof(double));
+    const uint64_t o_gp = cv.take((uint64_t)L.volume * sizeof(float));
+    const uint64_t o_gs = cv.take((uint64_t)st.dense * sizeof(float));
     st.bytes = cv.off;
     if (base) {
         st.ck = reinterpret_cast<float*>(base + o_ck);
         st.acc = reinterpret_cast<float*>(base + o_acc);
         st.mu[0] = reinterpret_cast<float*>(base + o_mu0);
         st.mu[1] = reinterpret_cast<float*>(base + o_mu1);
-        st.g = reinterpret_cast<double*>(base + o_g);
+        st.gpart = reinterpret_cast<float*>(base + o_gp);
+        st.gsum = reinterpret_cast<float*>(base + o_gs);
     }
     return st;
 }
@@ -963,7 +973,9 @@ int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_poin
     const Store st = plan_store(ctx, nt, I, static_cast<char*>(store));
     hipError_t he = hipSuccess;
     for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(st.mu[k], ctx->L.volume, s);
-    if (he == hipSuccess) he = fd::launch_fill_zero(reinterpret_cast<float*>(st.g), 2 * st.dense, s);
+    if (he == hipSuccess) he = fd::launch_fill_zero(st.gpart, ctx->L.volume, s);
+    if (he == hipSuccess) he = fd::launch_fill_zero(st.gsum, st.dense, s);
+    int pending = 0;  // adjoint steps accumulated in gpart since the last flush
     fd::AcousticStep p = acoustic_params(ctx);
     int m = 0;  // st.mu[m] holds mu^{k+1}, st.mu[1-m] mu^{k+2}
     for (int j = st.nck - 1; j >= 0 && he == hipSuccess; --j) {
@@ -976,13 +988,20 @@ int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_poin
         }
         for (int k = n1; k > n0 && he == hipSuccess; --k) {
             he = adjoint_step(ctx, p, st.mu[m], st.mu[1 - m], k, nsrc, wavelet_grad, adj, nadj, s);
-            if (he == hipSuccess) he = fd::launch_image(st.mu[1 - m], st.slot(ctx, k - 1 - n0), st.g, ctx->L, s);
+            if (he == hipSuccess)
+                he = fd::launch_image(st.mu[1 - m], st.slot(ctx, k - 1 - n0), st.gpart, ctx->L, s);
+            if (he == hipSuccess && ++pending == kFlushSteps) {
+                he = fd::launch_flush_gradient(st.gpart, st.gsum, ctx->L, s);
+                pending = 0;
+            }
             m = 1 - m;
         }
     }
     ctx->ck_last_acc = false;  // the segment slots now hold the first segment
+    if (he == hipSuccess && pending) he = fd::launch_flush_gradient(st.gpart, st.gsum, ctx->L, s);
     if (he == hipSuccess)
-        he = fd::launch_finish_gradient(st.g, ctx->A, grad, ctx->L, ctx->g.dt, wrt == FD_WRT_VEL, s);
+        he = fd::launch_finish_gradient(st.gsum, ctx->A, grad, ctx->L, ctx->g.dt, wrt == FD_WRT_VEL,
+                                        s);
     if (he != hipSuccess) return hip_fail(ctx, he, "gradient");
     return FD_OK;
 }

@@ -6,10 +6,13 @@
 // state) and a^k = A L u^{k-1} + injected source (the acceleration term the
 // forward step stores), the gradient with respect to m = 1/v^2 is
 //   dJ/dm = -(1/dt^2) sum_k mu^k a^k.
-// The per-step correlation is accumulated in FP64 over a dense array; a final
-// pass scales it and, for the gradient with respect to v, applies
-// dm/dv = -2/v^3.  Both kernels stream (no reuse): 16 bytes per point per step
-// for the correlation (two FP32 reads, one FP64 read and write).
+// The per-step correlation is summed in FP32 in two levels: into a partial
+// sum on the padded layout of the fields (16 bytes per point and step: mu and
+// the acceleration read, the partial sum read and written), flushed every few
+// tens of steps into a dense total, which keeps the rounding of long sums
+// bounded without FP64 on the device.  A
+// final pass scales the total and, for the gradient with respect to v,
+// applies dm/dv = -2/v^3.
 #include "fd_internal.h"
 
 namespace fd {
@@ -22,7 +25,19 @@ constexpr int kRows = 4;  // rows of 64 points per 256-thread block
 // (strided when nz exceeds the grid).
 __global__ __launch_bounds__(256) void image_kernel(const float* __restrict__ mu,
                                                     const float* __restrict__ acc,
-                                                    double* __restrict__ g, Layout L, int ntx) {
+                                                    float* __restrict__ gpart, Layout L, int ntx) {
+    const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+    const int x = tx * kTileX + (threadIdx.x & 63);
+    const int y = ty * kRows + (threadIdx.x >> 6);
+    if (x >= L.nx || y >= L.ny) return;
+    for (int z = blockIdx.y; z < L.nz; z += gridDim.y) {
+        const int64_t v = L.origin + (int64_t)z * L.plane + (int64_t)y * L.pitch + x;
+        gpart[v] = fmaf(mu[v], acc[v], gpart[v]);
+    }
+}
+
+__global__ __launch_bounds__(256) void flush_kernel(float* __restrict__ gpart,
+                                                    float* __restrict__ gsum, Layout L, int ntx) {
     const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
     const int x = tx * kTileX + (threadIdx.x & 63);
     const int y = ty * kRows + (threadIdx.x >> 6);
@@ -30,14 +45,15 @@ __global__ __launch_bounds__(256) void image_kernel(const float* __restrict__ mu
     for (int z = blockIdx.y; z < L.nz; z += gridDim.y) {
         const int64_t v = L.origin + (int64_t)z * L.plane + (int64_t)y * L.pitch + x;
         const int64_t d = ((int64_t)z * L.ny + y) * L.nx + x;
-        g[d] += (double)mu[v] * (double)acc[v];  // exact product, no FP32 underflow
+        gsum[d] += gpart[v];
+        gpart[v] = 0.f;
     }
 }
 
-__global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ g,
+__global__ __launch_bounds__(256) void finish_kernel(const float* __restrict__ gsum,
                                                      const float* __restrict__ A,
                                                      float* __restrict__ out, Layout L, int ntx,
-                                                     double dt, int wrt_vel) {
+                                                     float dt, float inv_dt2, int wrt_vel) {
     const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
     const int x = tx * kTileX + (threadIdx.x & 63);
     const int y = ty * kRows + (threadIdx.x >> 6);
@@ -47,10 +63,10 @@ __global__ __launch_bounds__(256) void finish_kernel(const double* __restrict__ 
         const int64_t d = ((int64_t)z * L.ny + y) * L.nx + x;
         if (wrt_vel) {
             // dJ/dv = dJ/dm * (-2 / v^3), v = sqrt(A) / dt
-            const double a = (double)A[v];
-            out[d] = (float)(g[d] * 2.0 * dt / (a * sqrt(a)));
+            const float a = A[v];
+            out[d] = gsum[d] * (2.f * dt) / (a * sqrtf(a));
         } else {
-            out[d] = (float)(-g[d] / (dt * dt));
+            out[d] = -gsum[d] * inv_dt2;
         }
     }
 }
@@ -63,19 +79,27 @@ dim3 plane_grid(const Layout& L, int& ntx) {
 
 }  // namespace
 
-hipError_t launch_image(const float* mu, const float* acc, double* g, const Layout& L,
+hipError_t launch_image(const float* mu, const float* acc, float* gpart, const Layout& L,
                         hipStream_t s) {
     int ntx;
     const dim3 grid = plane_grid(L, ntx);
-    hipLaunchKernelGGL(image_kernel, grid, dim3(256), 0, s, mu, acc, g, L, ntx);
+    hipLaunchKernelGGL(image_kernel, grid, dim3(256), 0, s, mu, acc, gpart, L, ntx);
     return hipGetLastError();
 }
 
-hipError_t launch_finish_gradient(const double* g, const float* A, float* out, const Layout& L,
+hipError_t launch_flush_gradient(float* gpart, float* gsum, const Layout& L, hipStream_t s) {
+    int ntx;
+    const dim3 grid = plane_grid(L, ntx);
+    hipLaunchKernelGGL(flush_kernel, grid, dim3(256), 0, s, gpart, gsum, L, ntx);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_gradient(const float* gsum, const float* A, float* out, const Layout& L,
                                   double dt, int wrt_vel, hipStream_t s) {
     int ntx;
     const dim3 grid = plane_grid(L, ntx);
-    hipLaunchKernelGGL(finish_kernel, grid, dim3(256), 0, s, g, A, out, L, ntx, dt, wrt_vel);
+    hipLaunchKernelGGL(finish_kernel, grid, dim3(256), 0, s, gsum, A, out, L, ntx, (float)dt,
+                       (float)(1.0 / (dt * dt)), wrt_vel);
     return hipGetLastError();
 }
 

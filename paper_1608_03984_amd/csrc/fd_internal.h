@@ -137,12 +137,14 @@ hipError_t launch_inject(float* u, const float* A, const float* sig, const Spars
 hipError_t launch_record(const float* u, const SparsePoint* pts, int n, float* out, float scale,
                          const Layout& L, int ndim, int64_t shot_stride, hipStream_t s);
 
-// adjoint / gradient
-// g[dense] += mu[vol] * acc[vol] over the interior (FP64 accumulation).
-hipError_t launch_image(const float* mu, const float* acc, double* g, const Layout& L,
+// adjoint / gradient (FP32, two-level summation)
+// gpart[vol] += mu[vol] * acc[vol] over the interior.
+hipError_t launch_image(const float* mu, const float* acc, float* gpart, const Layout& L,
                         hipStream_t s);
-// out[dense] = g * -1/dt^2 (wrt m = 1/v^2) or g * 2 dt / A^{3/2} (wrt v).
-hipError_t launch_finish_gradient(const double* g, const float* A, float* out, const Layout& L,
+// gsum[dense] += gpart[vol]; gpart[vol] = 0 over the interior.
+hipError_t launch_flush_gradient(float* gpart, float* gsum, const Layout& L, hipStream_t s);
+// out[dense] = gsum * -1/dt^2 (wrt m = 1/v^2) or gsum * 2 dt / A^{3/2} (wrt v).
+hipError_t launch_finish_gradient(const float* gsum, const float* A, float* out, const Layout& L,
                                   double dt, int wrt_vel, hipStream_t s);
 
 // stencils

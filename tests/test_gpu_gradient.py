@@ -6,8 +6,9 @@ Tolerances.  The adjoint run is a forward-type run of the same FP32 kernels,
 so its output is held to the full-run bar of the forward path, relative L2
 1e-4.  The gradient is a sum over time of products of two such FP32 fields
 (adjoint state times the forward acceleration), each within 1e-4 of the
-oracle's, accumulated in FP64: relative L2 2e-4 (the sum of the two factors'
-bounds).  The dot-product identity between the GPU forward and adjoint holds
+oracle's, summed in FP32 in two levels (partial sums of at most 32 steps):
+relative L2 2e-4 (the sum of the two factors' bounds; the summation adds
+rounding of order 32 eps relative to the sum of magnitudes).  The dot-product identity between the GPU forward and adjoint holds
 to FP32 rounding of the two runs, 1e-5 relative to |Fq| |d|.
 """
 import numpy as np
