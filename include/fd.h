@@ -266,6 +266,96 @@ int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_poin
 int32_t fd_adjoint(fd_ctx* ctx, int32_t nt, const fd_points* adj, const fd_points* out,
                    void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Learned coarse-grid correction (acoustic)                                 */
+/* ------------------------------------------------------------------------ */
+/*
+ * Not in the paper: its cost study (section 6) trades space order against
+ * grid spacing at a fixed physical problem; this is the learned end of that
+ * trade.  A coarse, low-order solver is corrected every few steps by a small
+ * network so that its state tracks a fine, high-order solution sampled at the
+ * coarse points.  The network is three 3 x 3 x 3 convolution layers
+ *   y1 = relu(conv(x, w1) + b1), y2 = relu(conv(y1, w2) + b2),
+ *   d = conv(y2, w3) + b3,
+ * conv(x, w)[p][co] = sum_tap sum_ci x[p + off(tap)][ci] w[tap][ci][co] (zero
+ * padding, tap = 9 (dz+1) + 3 (dy+1) + (dx+1)), run on the BF16 matrix cores
+ * with FP32 accumulation.  Its input x has 8 channels (s u^n, s u^{n-1},
+ * v / vref - 1, zeros), s = 1 / max|u^n|, and its 2 output channels d are the
+ * corrections of u^n and u^{n-1} in the same units.
+ *
+ * Layouts: activations are channels-last BF16 (uint16_t bit patterns)
+ * [nz][ny][nx][c] with c = 8 or 16 over the padded grid, 16-byte aligned.
+ * Every layer's parameters are stored padded to 16 x 16 channels as FP32
+ * [27][16 ci][16 co] followed by the bias [16] (FD_CNN_LAYER_FLOATS floats;
+ * unused channels are zero), which is also the layout of the weight
+ * gradient.  shape[] is (nz, ny, nx).  All calls are asynchronous on
+ * `stream`; the caller owns every buffer.
+ */
+#define FD_CNN_LAYER_FLOATS (27 * 256 + 16)
+#define FD_CNN_RELU 0   /* y = bf16(relu(conv + b)), 16 channels */
+#define FD_CNN_LINEAR 1 /* yf = conv + b in FP32, first cout_store channels */
+#define FD_CNN_MASKED 2 /* y = bf16(conv * (mask > 0)), 16 channels, no bias (backward data) */
+
+/* Elements (uint16_t) of a packed layer operand for cin_pad = 8 or 16. */
+int32_t fd_cnn_packed_elems(int32_t cin_pad, int64_t* elems);
+
+/* Pack one layer (layer = FD_CNN_LAYER_FLOATS FP32 values, layout above) into
+ * the matrix-core operand for inputs of cin_pad channels.  transpose != 0
+ * packs the backward-data operator instead (flipped taps, exchanged
+ * channels). */
+int32_t fd_cnn_pack(const float* layer, int32_t cin_pad, int32_t transpose, uint16_t* packed,
+                    void* stream);
+
+/* One convolution: x [shape][cin_pad] BF16 -> y (modes RELU, MASKED: BF16
+ * [shape][16]) or yf (mode LINEAR: FP32 [shape][cout_store]).  bias: the 16
+ * FP32 bias values (ignored by MASKED); mask: BF16 [shape][16] (MASKED
+ * only). */
+int32_t fd_cnn_conv(const uint16_t* x, int32_t cin_pad, const int64_t* shape,
+                    const uint16_t* packed, const float* bias, int32_t mode, const uint16_t* mask,
+                    int32_t cout_store, uint16_t* y, float* yf, void* stream);
+
+/* FP32 scratch (floats) the weight gradient needs for this shape. */
+int32_t fd_cnn_wgrad_scratch(const int64_t* shape, int64_t* floats);
+
+/* Weight and bias gradient of one layer: dw[tap][ci][co] = sum_p
+ * x[p + off(tap)][ci] dz[p][co], db[co] = sum_p dz[p][co], written to
+ * grad (FD_CNN_LAYER_FLOATS FP32, layout above).  x: BF16 [shape][cx],
+ * dz: BF16 [shape][cz]; (cx, cz) = (8, 16), (16, 16) or (16, 8). */
+int32_t fd_cnn_wgrad(const uint16_t* x, int32_t cx, const uint16_t* dz, int32_t cz,
+                     const int64_t* shape, float* scratch, int64_t scratch_floats, float* grad,
+                     void* stream);
+
+/* Masked mean-square loss L = 1/(2n) sum_mask |out - target|^2 (out, target
+ * FP32 [nvox][cout]; mask uint8 [nvox]; inv_n = 1/n): dz = dL/dout as BF16
+ * [nvox][cpad] and L added to *loss (FP32, device). */
+int32_t fd_cnn_loss_grad(const float* out, const float* target, const uint8_t* mask,
+                         int64_t nvox, int32_t cout, int32_t cpad, float inv_n, uint16_t* dz,
+                         float* loss, void* stream);
+
+/* Adam step t >= 1 on n FP32 parameters (bias-corrected). */
+int32_t fd_cnn_adam(float* param, const float* grad, float* m, float* v, int64_t n, int32_t t,
+                    float lr, float beta1, float beta2, float eps, void* stream);
+
+/* Network input from a single-shot acoustic context's current state: x
+ * (BF16 [padded shape][8]); *scale_bits receives max|u^n| (FP32 bits). */
+int32_t fd_cnn_features(fd_ctx* ctx, float vref, uint32_t* scale_bits, uint16_t* x,
+                        void* stream);
+
+/* Apply the network output d (FP32 [padded shape][2]): u^n += d0 max|u^n|,
+ * u^{n-1} += d1 max|u^n| with the scale of the matching fd_cnn_features. */
+int32_t fd_cnn_correct(fd_ctx* ctx, const float* d, const uint32_t* scale_bits, void* stream);
+
+/* Training target: t = (ref_cur - u^n, ref_prev - u^{n-1}) / max|u^n| (FP32
+ * [padded shape][2]) for dense reference fields of the context's padded
+ * shape. */
+int32_t fd_cnn_residual(fd_ctx* ctx, const float* ref_cur, const float* ref_prev,
+                        const uint32_t* scale_bits, float* target, void* stream);
+
+/* Every stride-th point (all axes, from index 0) of a wavefield level into a
+ * dense array of ceil(N_a / stride) points per axis: the coarse-grid samples
+ * of a fine solution. */
+int32_t fd_restrict(fd_ctx* ctx, int32_t which, int32_t stride, float* dst, void* stream);
+
 /* Tuning options (kernel variant / launch shape), mainly for benchmarking.
  * FD_OPT_KERNEL: 0 = tiled (default), 1 = direct global-memory kernel.
  * FD_OPT_ZCHUNK: z-planes per thread block of the tiled 3D kernels (0 = auto).

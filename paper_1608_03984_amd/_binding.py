@@ -39,12 +39,19 @@ FD_OPT_SHOTS_PER_BLOCK = 4
 FD_WRT_M = 0
 FD_WRT_VEL = 1
 
+FD_CNN_LAYER_FLOATS = 27 * 256 + 16
+FD_CNN_RELU = 0
+FD_CNN_LINEAR = 1
+FD_CNN_MASKED = 2
+
 EXPORTS = (
     "fd_workspace_bytes", "fd_setup", "fd_forward", "fd_get_field", "fd_set_field",
     "fd_stencil_weights", "fd_cfl_dt", "fd_set_option", "fd_destroy", "fd_strerror",
     "fd_last_error", "fd_triad", "fd_checkpoint_bytes", "fd_forward_checkpointed", "fd_gradient",
     "fd_adjoint", "fd_workspace_bytes_shots", "fd_setup_shots", "fd_forward_shots",
-    "fd_get_shot_field", "fd_set_shot_field",
+    "fd_get_shot_field", "fd_set_shot_field", "fd_cnn_packed_elems", "fd_cnn_pack", "fd_cnn_conv",
+    "fd_cnn_wgrad_scratch", "fd_cnn_wgrad", "fd_cnn_loss_grad", "fd_cnn_adam", "fd_cnn_features",
+    "fd_cnn_correct", "fd_cnn_residual", "fd_restrict",
 )
 
 
@@ -118,6 +125,22 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(i32), i32, vp]),
             "fd_get_shot_field": (i32, [vp, i32, i32, vp, vp]),
             "fd_set_shot_field": (i32, [vp, i32, i32, vp, vp]),
+            "fd_cnn_packed_elems": (i32, [i32, ctypes.POINTER(ctypes.c_int64)]),
+            "fd_cnn_pack": (i32, [vp, i32, i32, vp, vp]),
+            "fd_cnn_conv": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int64), vp, vp, i32, vp, i32,
+                                  vp, vp, vp]),
+            "fd_cnn_wgrad_scratch": (i32, [ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(ctypes.c_int64)]),
+            "fd_cnn_wgrad": (i32, [vp, i32, vp, i32, ctypes.POINTER(ctypes.c_int64), vp,
+                                   ctypes.c_int64, vp, vp]),
+            "fd_cnn_loss_grad": (i32, [vp, vp, vp, ctypes.c_int64, i32, i32, ctypes.c_float, vp,
+                                       vp, vp]),
+            "fd_cnn_adam": (i32, [vp, vp, vp, vp, ctypes.c_int64, i32, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]),
+            "fd_cnn_features": (i32, [vp, ctypes.c_float, vp, vp, vp]),
+            "fd_cnn_correct": (i32, [vp, vp, vp, vp]),
+            "fd_cnn_residual": (i32, [vp, vp, vp, vp, vp, vp]),
+            "fd_restrict": (i32, [vp, i32, i32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -319,3 +342,74 @@ def fd_get_shot_field(ctx, shot: int, which: int, dst_ptr: int, stream: int):
 def fd_set_shot_field(ctx, shot: int, which: int, src_ptr: int, stream: int):
     _check(lib().fd_set_shot_field(ctx, int(shot), int(which), ctypes.c_void_p(src_ptr),
                                    ctypes.c_void_p(stream)), "fd_set_shot_field", ctx)
+
+
+def _shape3(shape):
+    return (ctypes.c_int64 * 3)(*[int(v) for v in shape])
+
+
+def _vp(ptr):
+    return ctypes.c_void_p(int(ptr) if ptr else 0)
+
+
+def fd_cnn_packed_elems(cin_pad: int) -> int:
+    out = ctypes.c_int64(0)
+    _check(lib().fd_cnn_packed_elems(int(cin_pad), ctypes.byref(out)), "fd_cnn_packed_elems")
+    return int(out.value)
+
+
+def fd_cnn_pack(layer_ptr, cin_pad, transpose, packed_ptr, stream):
+    _check(lib().fd_cnn_pack(_vp(layer_ptr), int(cin_pad), int(transpose), _vp(packed_ptr),
+                             _vp(stream)), "fd_cnn_pack")
+
+
+def fd_cnn_conv(x_ptr, cin_pad, shape, packed_ptr, bias_ptr, mode, mask_ptr, cout_store, y_ptr,
+                yf_ptr, stream):
+    _check(lib().fd_cnn_conv(_vp(x_ptr), int(cin_pad), _shape3(shape), _vp(packed_ptr),
+                             _vp(bias_ptr), int(mode), _vp(mask_ptr), int(cout_store), _vp(y_ptr),
+                             _vp(yf_ptr), _vp(stream)), "fd_cnn_conv")
+
+
+def fd_cnn_wgrad_scratch(shape) -> int:
+    out = ctypes.c_int64(0)
+    _check(lib().fd_cnn_wgrad_scratch(_shape3(shape), ctypes.byref(out)), "fd_cnn_wgrad_scratch")
+    return int(out.value)
+
+
+def fd_cnn_wgrad(x_ptr, cx, dz_ptr, cz, shape, scratch_ptr, scratch_floats, grad_ptr, stream):
+    _check(lib().fd_cnn_wgrad(_vp(x_ptr), int(cx), _vp(dz_ptr), int(cz), _shape3(shape),
+                              _vp(scratch_ptr), int(scratch_floats), _vp(grad_ptr), _vp(stream)),
+           "fd_cnn_wgrad")
+
+
+def fd_cnn_loss_grad(out_ptr, target_ptr, mask_ptr, nvox, cout, cpad, inv_n, dz_ptr, loss_ptr,
+                     stream):
+    _check(lib().fd_cnn_loss_grad(_vp(out_ptr), _vp(target_ptr), _vp(mask_ptr), int(nvox),
+                                  int(cout), int(cpad), float(inv_n), _vp(dz_ptr), _vp(loss_ptr),
+                                  _vp(stream)), "fd_cnn_loss_grad")
+
+
+def fd_cnn_adam(p_ptr, g_ptr, m_ptr, v_ptr, n, t, lr, beta1, beta2, eps, stream):
+    _check(lib().fd_cnn_adam(_vp(p_ptr), _vp(g_ptr), _vp(m_ptr), _vp(v_ptr), int(n), int(t),
+                             float(lr), float(beta1), float(beta2), float(eps), _vp(stream)),
+           "fd_cnn_adam")
+
+
+def fd_cnn_features(ctx, vref, bits_ptr, x_ptr, stream):
+    _check(lib().fd_cnn_features(ctx, float(vref), _vp(bits_ptr), _vp(x_ptr), _vp(stream)),
+           "fd_cnn_features", ctx)
+
+
+def fd_cnn_correct(ctx, d_ptr, bits_ptr, stream):
+    _check(lib().fd_cnn_correct(ctx, _vp(d_ptr), _vp(bits_ptr), _vp(stream)), "fd_cnn_correct",
+           ctx)
+
+
+def fd_cnn_residual(ctx, ref_cur_ptr, ref_prev_ptr, bits_ptr, target_ptr, stream):
+    _check(lib().fd_cnn_residual(ctx, _vp(ref_cur_ptr), _vp(ref_prev_ptr), _vp(bits_ptr),
+                                 _vp(target_ptr), _vp(stream)), "fd_cnn_residual", ctx)
+
+
+def fd_restrict(ctx, which, stride, dst_ptr, stream):
+    _check(lib().fd_restrict(ctx, int(which), int(stride), _vp(dst_ptr), _vp(stream)),
+           "fd_restrict", ctx)

@@ -15,7 +15,7 @@ OBJDIR = ROOT / "_build"
 LIB = PKG / "libfd.so"
 
 SOURCES = ["fd_abi.cpp", "fd_common.hip", "fd_acoustic.hip", "fd_tti.hip", "fd_vti.hip",
-           "fd_adjoint.hip", "fd_probe.hip"]
+           "fd_adjoint.hip", "fd_cnn.hip", "fd_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1148,6 +1148,144 @@ int32_t fd_destroy(fd_ctx* ctx) {
     return FD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// correction network
+// ---------------------------------------------------------------------------
+
+static bool cnn_shape_ok(const int64_t* shape) {
+    if (!shape) return false;
+    for (int a = 0; a < 3; ++a)
+        if (shape[a] < 1 || shape[a] > 65535) return false;
+    return shape[0] * shape[1] * shape[2] < ((int64_t)1 << 40);
+}
+
+static bool aligned16(const void* p) { return p && reinterpret_cast<uintptr_t>(p) % 16 == 0; }
+
+int32_t fd_cnn_packed_elems(int32_t cin_pad, int64_t* elems) {
+    if (!elems || (cin_pad != 8 && cin_pad != 16)) return FD_ERR_INVALID_ARG;
+    *elems = fd::cnn_packed_elems(cin_pad);
+    return FD_OK;
+}
+
+int32_t fd_cnn_pack(const float* layer, int32_t cin_pad, int32_t transpose, uint16_t* packed,
+                    void* stream) {
+    if (!layer || !aligned16(packed) || (cin_pad != 8 && cin_pad != 16)) return FD_ERR_INVALID_ARG;
+    const hipError_t e = fd::launch_cnn_pack(layer, 16, 16, cin_pad, transpose ? 1 : 0, packed,
+                                             static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FD_OK : FD_ERR_DEVICE;
+}
+
+int32_t fd_cnn_conv(const uint16_t* x, int32_t cin_pad, const int64_t* shape,
+                    const uint16_t* packed, const float* bias, int32_t mode, const uint16_t* mask,
+                    int32_t cout_store, uint16_t* y, float* yf, void* stream) {
+    if (!cnn_shape_ok(shape) || !aligned16(x) || !aligned16(packed) ||
+        (cin_pad != 8 && cin_pad != 16))
+        return FD_ERR_INVALID_ARG;
+    if (mode == FD_CNN_RELU && (!bias || !aligned16(y))) return FD_ERR_INVALID_ARG;
+    if (mode == FD_CNN_LINEAR && (!bias || !yf || cout_store < 1 || cout_store > 16))
+        return FD_ERR_INVALID_ARG;
+    if (mode == FD_CNN_MASKED && (!mask || !aligned16(y))) return FD_ERR_INVALID_ARG;
+    if (mode != FD_CNN_RELU && mode != FD_CNN_LINEAR && mode != FD_CNN_MASKED)
+        return FD_ERR_INVALID_ARG;
+    const hipError_t e = fd::launch_cnn_conv(x, cin_pad, (int)shape[0], (int)shape[1],
+                                             (int)shape[2], packed, bias, mode, mask, cout_store,
+                                             y, yf, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FD_OK : FD_ERR_DEVICE;
+}
+
+static const int kWgradZChunk = 8;
+
+int32_t fd_cnn_wgrad_scratch(const int64_t* shape, int64_t* floats) {
+    if (!cnn_shape_ok(shape) || !floats) return FD_ERR_INVALID_ARG;
+    *floats = (int64_t)fd::cnn_wgrad_slots((int)shape[0], (int)shape[1], (int)shape[2],
+                                           kWgradZChunk) *
+              FD_CNN_LAYER_FLOATS;
+    return FD_OK;
+}
+
+int32_t fd_cnn_wgrad(const uint16_t* x, int32_t cx, const uint16_t* dz, int32_t cz,
+                     const int64_t* shape, float* scratch, int64_t scratch_floats, float* grad,
+                     void* stream) {
+    int64_t need = 0;
+    if (fd_cnn_wgrad_scratch(shape, &need) != FD_OK || !x || !dz || !scratch || !grad)
+        return FD_ERR_INVALID_ARG;
+    if (!((cx == 8 && cz == 16) || (cx == 16 && cz == 16) || (cx == 16 && cz == 8)))
+        return FD_ERR_INVALID_ARG;
+    if (scratch_floats < need) return FD_ERR_WORKSPACE;
+    const hipError_t e = fd::launch_cnn_wgrad(x, cx, dz, cz, (int)shape[0], (int)shape[1],
+                                              (int)shape[2], kWgradZChunk, scratch, grad,
+                                              static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FD_OK : FD_ERR_DEVICE;
+}
+
+int32_t fd_cnn_loss_grad(const float* out, const float* target, const uint8_t* mask,
+                         int64_t nvox, int32_t cout, int32_t cpad, float inv_n, uint16_t* dz,
+                         float* loss, void* stream) {
+    if (!out || !target || !mask || !dz || !loss || nvox < 1 || cout < 1 || cpad < cout ||
+        cpad > 16)
+        return FD_ERR_INVALID_ARG;
+    const hipError_t e = fd::launch_cnn_loss_grad(out, target, mask, nvox, cout, cpad, inv_n, dz,
+                                                  loss, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FD_OK : FD_ERR_DEVICE;
+}
+
+int32_t fd_cnn_adam(float* param, const float* grad, float* m, float* v, int64_t n, int32_t t,
+                    float lr, float beta1, float beta2, float eps, void* stream) {
+    if (!param || !grad || !m || !v || n < 1 || t < 1) return FD_ERR_INVALID_ARG;
+    const hipError_t e = fd::launch_cnn_adam(param, grad, m, v, n, t, lr, beta1, beta2, eps,
+                                             static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FD_OK : FD_ERR_DEVICE;
+}
+
+static int32_t cnn_ctx_ok(fd_ctx* ctx) {
+    if (!ctx) return FD_ERR_INVALID_ARG;
+    if (ctx->tti || ctx->vti || ctx->nshots != 1)
+        return fail(ctx, FD_ERR_UNSUPPORTED, "the correction works on single-shot acoustic contexts");
+    return FD_OK;
+}
+
+int32_t fd_cnn_features(fd_ctx* ctx, float vref, uint32_t* scale_bits, uint16_t* x,
+                        void* stream) {
+    int32_t rc = cnn_ctx_ok(ctx);
+    if (rc != FD_OK) return rc;
+    if (!scale_bits || !aligned16(x) || !(vref > 0.f))
+        return fail(ctx, FD_ERR_INVALID_ARG, "features: bad pointer or vref");
+    const hipError_t e = fd::launch_cnn_features(ctx->u[ctx->cur], ctx->u[1 - ctx->cur], ctx->A,
+                                                 ctx->L, (float)(1.0 / (ctx->g.dt * vref)),
+                                                 scale_bits, x, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FD_OK : hip_fail(ctx, e, "features");
+}
+
+int32_t fd_cnn_correct(fd_ctx* ctx, const float* d, const uint32_t* scale_bits, void* stream) {
+    int32_t rc = cnn_ctx_ok(ctx);
+    if (rc != FD_OK) return rc;
+    if (!d || !scale_bits) return fail(ctx, FD_ERR_INVALID_ARG, "correct: bad pointer");
+    const hipError_t e = fd::launch_cnn_correct(ctx->u[ctx->cur], ctx->u[1 - ctx->cur], ctx->L, d,
+                                                scale_bits, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FD_OK : hip_fail(ctx, e, "correct");
+}
+
+int32_t fd_cnn_residual(fd_ctx* ctx, const float* ref_cur, const float* ref_prev,
+                        const uint32_t* scale_bits, float* target, void* stream) {
+    int32_t rc = cnn_ctx_ok(ctx);
+    if (rc != FD_OK) return rc;
+    if (!ref_cur || !ref_prev || !scale_bits || !target)
+        return fail(ctx, FD_ERR_INVALID_ARG, "residual: bad pointer");
+    const hipError_t e = fd::launch_cnn_residual(ref_cur, ref_prev, ctx->u[ctx->cur],
+                                                 ctx->u[1 - ctx->cur], ctx->L, scale_bits, target,
+                                                 static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FD_OK : hip_fail(ctx, e, "residual");
+}
+
+int32_t fd_restrict(fd_ctx* ctx, int32_t which, int32_t stride, float* dst, void* stream) {
+    if (!ctx) return FD_ERR_INVALID_ARG;
+    float* f = field_ptr(ctx, 0, which);
+    if (!f || !dst || stride < 1) return fail(ctx, FD_ERR_INVALID_ARG, "restrict: bad argument");
+    const hipError_t e = fd::launch_restrict(f, ctx->L, stride, dst,
+                                             static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FD_OK : hip_fail(ctx, e, "restrict");
+}
+
 const char* fd_strerror(int32_t status) {
     switch (status) {
         case FD_OK: return "success";

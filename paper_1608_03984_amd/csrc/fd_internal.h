@@ -147,6 +147,32 @@ hipError_t launch_flush_gradient(float* gpart, float* gsum, const Layout& L, hip
 hipError_t launch_finish_gradient(const float* gsum, const float* A, float* out, const Layout& L,
                                   double dt, int wrt_vel, hipStream_t s);
 
+// correction network (fd_cnn.hip)
+int cnn_packed_elems(int cin_pad);
+int cnn_wgrad_slots(int D, int H, int W, int zchunk);
+hipError_t launch_cnn_pack(const float* w, int cin, int cout, int cin_pad, int flip,
+                           uint16_t* out, hipStream_t s);
+hipError_t launch_cnn_conv(const uint16_t* x, int cin_pad, int D, int H, int W,
+                           const uint16_t* packed, const float* bias, int mode,
+                           const uint16_t* mask, int cout_store, uint16_t* y, float* yf,
+                           hipStream_t s);
+hipError_t launch_cnn_wgrad(const uint16_t* x, int cx, const uint16_t* dz, int cz, int D, int H,
+                            int W, int zchunk, float* partials, float* out, hipStream_t s);
+hipError_t launch_cnn_loss_grad(const float* out, const float* target, const uint8_t* mask,
+                                int64_t nvox, int cout, int cpad, float inv_n, uint16_t* dz,
+                                float* loss, hipStream_t s);
+hipError_t launch_cnn_adam(float* p, const float* g, float* m, float* v, int64_t n, int t,
+                           float lr, float b1, float b2, float eps, hipStream_t s);
+hipError_t launch_cnn_features(const float* uc, const float* up, const float* A, const Layout& L,
+                               float inv_dt_vref, uint32_t* bits, uint16_t* xo, hipStream_t s);
+hipError_t launch_cnn_correct(float* uc, float* up, const Layout& L, const float* d,
+                              const uint32_t* bits, hipStream_t s);
+hipError_t launch_cnn_residual(const float* ref_cur, const float* ref_prev, const float* uc,
+                               const float* up, const Layout& L, const uint32_t* bits, float* t,
+                               hipStream_t s);
+hipError_t launch_restrict(const float* u, const Layout& L, int stride, float* out,
+                           hipStream_t s);
+
 // stencils
 hipError_t launch_acoustic(const AcousticStep& p, int ndim, int radius, int variant, int tile_cfg,
                            int shots_per_block, hipStream_t s);

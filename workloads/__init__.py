@@ -35,6 +35,14 @@ upsampled, rescaled, and edge-replicated into the layer):
     points); 10 Hz Ricker at the centre (x, y) and z = 25 m; 800 steps.
   * ``vti_3d``       -- the ``tti_3d`` model without tilt and azimuth (VTI
     pseudo-acoustic), same grid, time steps and source.
+  * ``learned_model`` -- one training/evaluation model of the coarse-grid
+    correction: random layered velocity (2-5 layers between 1.5 and 3.4 km/s,
+    random interface depths) times (1 + p), |p| <= 0.05 (correlation 20 fine
+    points); fine grid h = 10 m (256^3 physical, 40-point layer, space order
+    16, dt = 0.4 CFL at 3675 m/s, 1000 steps), coarse grid h = 20 m (every
+    second fine point, 20-point layer, space order 4, dt doubled, 500
+    steps); 10 Hz Ricker source at a random on-grid (x, y) in the middle half
+    at z = 40 m; receivers every 40 m at z = 20 m.
   * ``fwi_3d``       -- the many-shot survey of a full-waveform inversion:
     256^3 physical, h = 15 m, 40-point layer; true model of four layers
     1.5 / 2.0 / 2.7 / 3.5 km/s times (1 + p), |p| <= 0.05 (correlation 12
@@ -362,3 +370,44 @@ def vti_3d(so: int = 8, phys: int = 384, nbl: int = 40, nt: int = 800, seed: int
     p = tti_3d(so=so, phys=phys, nbl=nbl, nt=nt, seed=seed, receivers=receivers)
     p.name, p.physics, p.theta, p.phi = "vti_3d", "vti", None, None
     return p
+
+
+def learned_model(seed: int, phys_f: int = 256, nbl_f: int = 40, so_f: int = 16, so_c: int = 4,
+                  nt_f: int = 1000, f0: float = 10.0, rec_every: int = 4) -> dict:
+    """Fine / coarse pair of one random layered model (see the module notes).
+    The coarse padded grid is every second point of the fine padded grid, so
+    phys_f and nbl_f must be even."""
+    assert phys_f % 2 == 0 and nbl_f % 2 == 0
+    rng = np.random.default_rng(seed)
+    h_f = 10.0
+    n = phys_f
+    nl = int(rng.integers(2, 6))
+    depths = np.sort(rng.uniform(0.1, 0.9, nl - 1)) * n
+    vels = np.sort(rng.uniform(1500.0, 3400.0, nl))
+    z = np.arange(n)
+    vz = vels[np.searchsorted(depths, z, side="right")]
+    p = 0.05 * smooth_random((n, n, n), 20.0, rng)
+    vel_f = _pad_edge(vz[:, None, None] * (1.0 + p), nbl_f).astype(np.float32)
+    vel_c = np.ascontiguousarray(vel_f[::2, ::2, ::2])
+    nbl_c = nbl_f // 2
+    vmax = VMAX["acoustic_3d"]
+    eta_f = damping_profile(vel_f.shape, nbl_f, (h_f,) * 3, vmax)
+    eta_c = damping_profile(vel_c.shape, nbl_c, (2 * h_f,) * 3, vmax)
+    dt_f = DT[("acoustic_3d", so_f)]
+    dt_c = 2.0 * dt_f
+    nt_c = nt_f // 2
+    cx, cy = (rng.integers(n // 4, 3 * n // 4, 2) // 2) * 2 * h_f   # on the coarse grid
+    src = np.array([[cx, cy, 40.0]])
+    g = np.arange(0, n, rec_every) * h_f
+    gx, gy = np.meshgrid(g, g, indexing="xy")
+    rec = np.stack([gx.ravel(), gy.ravel(), np.full(gx.size, 20.0)], axis=1)
+    return {
+        "shape_f": (n, n, n), "h_f": (h_f,) * 3, "nbl_f": nbl_f, "so_f": so_f, "dt_f": dt_f,
+        "vel_f": vel_f, "eta_f": eta_f,
+        "shape_c": (n // 2,) * 3, "h_c": (2 * h_f,) * 3, "nbl_c": nbl_c, "so_c": so_c,
+        "dt_c": dt_c, "vel_c": vel_c, "eta_c": eta_c,
+        "src": src, "rec": rec, "nt_f": nt_f, "nt_c": nt_c,
+        "wav_f": ricker(f0, dt_f, nt_f)[:, None].astype(np.float32),
+        "wav_c": ricker(f0, dt_c, nt_c)[:, None].astype(np.float32),
+        "seed": seed,
+    }
