@@ -62,9 +62,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-pass", action="store_true")
     ap.add_argument("--workload",
-                    choices=("acoustic", "tti", "vti", "gradient", "shots", "cost"),
+                    choices=("acoustic", "tti", "vti", "gradient", "shots", "cost", "learned"),
                     default="acoustic")
     ap.add_argument("--interval", type=int, default=0)
+    ap.add_argument("--models", type=int, default=24)
+    ap.add_argument("--iters", type=int, default=1500)
     return ap.parse_args()
 
 
@@ -420,6 +422,105 @@ def cost_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def learned_bench(args):
+    """Learned coarse-grid correction at the configuration of its design: fine
+    space order 16 on 256^3 + 40-point layer (h = 10 m, 1000 steps), coarse
+    space order 4 on every second point (128^3 + 20, h = 20 m, 500 steps),
+    correction every 8 coarse steps after the source has radiated.  Trains on
+    --models random layered models (solver-generated pairs) with libfd's
+    kernels, then times and scores on 3 held-out models: the fine solve (the
+    judge), the plain coarse solve, the corrected coarse solve, the coarse
+    solve corrected by the exact residual (the scheme's best case), and plain
+    coarse solves of space order 8 and 16.  Errors are relative L2 of the
+    receiver traces against the fine solve, over all receivers and samples
+    ("err") and over receivers outside the source ball after the first
+    correction ("late").  The headline compares the learned solve's time with
+    the cheapest plain solve whose error is no larger."""
+    import torch
+
+    from paper_1608_03984_amd import learned as Lm
+    from paper_1608_03984_amd.solver import Solver
+    from workloads import learned_model
+
+    K = 8
+    say = lambda m: print(m, file=sys.stderr, flush=True)
+    m0 = learned_model(100)
+    start = Lm.correction_start(m0)
+    nt_f, nt_c = m0["nt_f"], m0["nt_c"]
+    shape_c = tuple(s + 2 * m0["nbl_c"] for s in m0["shape_c"])
+    times = list(range(start + K, nt_c + 1, 8))
+    t0 = time.perf_counter()
+    samples = []
+    for i in range(args.models):
+        pair = Lm.make_pair(learned_model(100 + i))
+        samples += Lm.training_pairs(pair, times, K)
+        pair.close()
+        say(f"# training model {i + 1}/{args.models}: {len(samples)} samples")
+    t_data = time.perf_counter() - t0
+    net = Lm.CorrectionNet(seed=1, out_scale=0.01)
+    none_loss = Lm.sample_loss(None, samples, shape_c)
+    (hist, t_train) = Lm.timed(lambda: Lm.train(net, samples, shape_c, args.iters, lr=1e-3,
+                                                lr_end=1e-4))
+    train_loss = Lm.sample_loss(net, samples, shape_c)
+    say(f"# trained {args.iters} iterations in {t_train:.1f} s: window loss {none_loss:.3e} "
+        f"-> {train_loss:.3e}")
+    del samples
+    rows = []
+    for seed in (900, 901, 902):
+        m = learned_model(seed)
+        pair = Lm.make_pair(m)
+        far = Lm.far_receivers(pair, 6 * m["h_c"][0])
+        held = Lm.training_pairs(pair, times, K)
+        win = (Lm.sample_loss(None, held, shape_c), Lm.sample_loss(net, held, shape_c))
+        del held
+        Lm.solve_fine(pair, 20)                                   # warm-up
+        tf, t_fine = Lm.timed(lambda: Lm.solve_fine(pair, nt_f).clone())
+        runs = {"plain_so4": Lm.timed(lambda: Lm.solve_coarse(pair, nt_c).clone()),
+                "learned_so4": Lm.timed(lambda: Lm.solve_coarse(pair, nt_c, K, net,
+                                                                start=start).clone()),
+                "exact_so4": Lm.timed(lambda: Lm.solve_coarse_exact(pair, nt_c, K,
+                                                                    start=start).clone())}
+        for so in (8, 16):
+            s = Solver(3, m["shape_c"], m["h_c"], m["nbl_c"], so, m["dt_c"], m["vel_c"],
+                       m["eta_c"], max_points=1 + len(m["rec"]))
+            alt = Lm.PairSetup(pair.fine, s, m["src"], m["rec"], m["wav_f"], m["wav_c"], nt_c)
+            runs[f"plain_so{so}"] = Lm.timed(lambda: Lm.solve_coarse(alt, nt_c).clone())
+            s.close()
+        pair.close()
+        row = {"seed": seed, "fine_s": round(t_fine, 4),
+               "window_loss_none": win[0], "window_loss_learned": win[1]}
+        for k, (tr, t) in runs.items():
+            row[f"{k}_s"] = round(t, 4)
+            row[f"err_{k}"] = round(Lm.trace_error(tr, tf), 5)
+            row[f"late_{k}"] = round(Lm.trace_error(tr, tf, far, start), 5)
+        plain = [(row["fine_s"], 0.0)] + [(row[f"plain_so{so}_s"], row[f"err_plain_so{so}"])
+                                          for so in (4, 8, 16)]
+        row["plain_at_equal_error_s"] = min(t for t, e in plain if e <= row["err_learned_so4"])
+        rows.append(row)
+        say(f"# held-out {seed}: {row}")
+    mean = lambda k: float(np.mean([r[k] for r in rows]))
+    t_learn = mean("learned_so4_s")
+    line = {
+        "metric": "learned vs plain s at equal L2 error (3D acoustic coarse-grid correction)",
+        "value": round(t_learn, 4), "unit": "s", "n_gpus": 1, "steps": nt_c,
+        "warmup": 1, "ms_per_step": round(t_learn / nt_c * 1e3, 4),
+        "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "fine so16 256^3+40 (h 10 m, 1000 steps) judged; coarse so4 "
+                               "128^3+20 (h 20 m, 500 steps) corrected every 8 steps by a "
+                               "3-layer 3x3x3 conv net (16 channels, BF16, FP32 accumulation)",
+                   "train_models": args.models, "train_iters": args.iters,
+                   "data_s": round(t_data, 1), "train_s": round(t_train, 2),
+                   "window_loss_train": [none_loss, train_loss]},
+        "plain_at_equal_error_s": round(mean("plain_at_equal_error_s"), 4),
+        "speedup_vs_plain_at_equal_error": round(mean("plain_at_equal_error_s") / t_learn, 3),
+        "speedup_vs_fine": round(mean("fine_s") / t_learn, 3),
+        "mean": {k: float(f"{mean(k):.5g}") for k in rows[0] if k != "seed"},
+        "rows": rows,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -440,6 +541,9 @@ def main():
         return
     if args.workload == "cost":
         cost_bench(args)
+        return
+    if args.workload == "learned":
+        learned_bench(args)
         return
     import torch
 

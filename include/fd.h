@@ -280,8 +280,10 @@ int32_t fd_adjoint(fd_ctx* ctx, int32_t nt, const fd_points* adj, const fd_point
  * conv(x, w)[p][co] = sum_tap sum_ci x[p + off(tap)][ci] w[tap][ci][co] (zero
  * padding, tap = 9 (dz+1) + 3 (dy+1) + (dx+1)), run on the BF16 matrix cores
  * with FP32 accumulation.  Its input x has 8 channels (s u^n, s u^{n-1},
- * v / vref - 1, zeros), s = 1 / max|u^n|, and its 2 output channels d are the
- * corrections of u^n and u^{n-1} in the same units.
+ * s u^n nu, s u^{n-1} nu, zeros), s = 1 / max|u^n|, nu = v / vref - 1, and its
+ * 2 output channels d are the corrections of u^n and u^{n-1} in the same
+ * units.  Every input channel is linear in the wavefield; trained without
+ * biases, the network then maps a quiet region to no correction.
  *
  * Layouts: activations are channels-last BF16 (uint16_t bit patterns)
  * [nz][ny][nx][c] with c = 8 or 16 over the padded grid, 16-byte aligned.
@@ -295,6 +297,8 @@ int32_t fd_adjoint(fd_ctx* ctx, int32_t nt, const fd_points* adj, const fd_point
 #define FD_CNN_RELU 0   /* y = bf16(relu(conv + b)), 16 channels */
 #define FD_CNN_LINEAR 1 /* yf = conv + b in FP32, first cout_store channels */
 #define FD_CNN_MASKED 2 /* y = bf16(conv * (mask > 0)), 16 channels, no bias (backward data) */
+#define FD_CNN_IDENTITY 3 /* y = bf16(conv + b), 16 channels (a layer without activation) */
+#define FD_CNN_UNMASKED 4 /* y = bf16(conv), 16 channels, no bias (its backward data) */
 
 /* Elements (uint16_t) of a packed layer operand for cin_pad = 8 or 16. */
 int32_t fd_cnn_packed_elems(int32_t cin_pad, int64_t* elems);
@@ -337,13 +341,18 @@ int32_t fd_cnn_adam(float* param, const float* grad, float* m, float* v, int64_t
                     float lr, float beta1, float beta2, float eps, void* stream);
 
 /* Network input from a single-shot acoustic context's current state: x
- * (BF16 [padded shape][8]); *scale_bits receives max|u^n| (FP32 bits). */
-int32_t fd_cnn_features(fd_ctx* ctx, float vref, uint32_t* scale_bits, uint16_t* x,
-                        void* stream);
+ * (BF16 [padded shape][8]); *scale_bits receives max|u^n| (FP32 bits) over
+ * the points where mask (uint8 [padded shape], NULL = all points) is set.
+ * The mask keeps the grid-dependent near field of a point source out of the
+ * scale and, in fd_cnn_correct, out of the correction. */
+int32_t fd_cnn_features(fd_ctx* ctx, float vref, const uint8_t* mask, uint32_t* scale_bits,
+                        uint16_t* x, void* stream);
 
-/* Apply the network output d (FP32 [padded shape][2]): u^n += d0 max|u^n|,
- * u^{n-1} += d1 max|u^n| with the scale of the matching fd_cnn_features. */
-int32_t fd_cnn_correct(fd_ctx* ctx, const float* d, const uint32_t* scale_bits, void* stream);
+/* Apply the network output d (FP32 [padded shape][2]) where mask is set (NULL
+ * = everywhere): u^n += d0 max, u^{n-1} += d1 max with the scale of the
+ * matching fd_cnn_features. */
+int32_t fd_cnn_correct(fd_ctx* ctx, const float* d, const uint8_t* mask,
+                       const uint32_t* scale_bits, void* stream);
 
 /* Training target: t = (ref_cur - u^n, ref_prev - u^{n-1}) / max|u^n| (FP32
  * [padded shape][2]) for dense reference fields of the context's padded

@@ -43,6 +43,8 @@ FD_CNN_LAYER_FLOATS = 27 * 256 + 16
 FD_CNN_RELU = 0
 FD_CNN_LINEAR = 1
 FD_CNN_MASKED = 2
+FD_CNN_IDENTITY = 3
+FD_CNN_UNMASKED = 4
 
 EXPORTS = (
     "fd_workspace_bytes", "fd_setup", "fd_forward", "fd_get_field", "fd_set_field",
@@ -137,8 +139,8 @@ def lib() -> ctypes.CDLL:
                                        vp, vp]),
             "fd_cnn_adam": (i32, [vp, vp, vp, vp, ctypes.c_int64, i32, ctypes.c_float,
                                   ctypes.c_float, ctypes.c_float, ctypes.c_float, vp]),
-            "fd_cnn_features": (i32, [vp, ctypes.c_float, vp, vp, vp]),
-            "fd_cnn_correct": (i32, [vp, vp, vp, vp]),
+            "fd_cnn_features": (i32, [vp, ctypes.c_float, vp, vp, vp, vp]),
+            "fd_cnn_correct": (i32, [vp, vp, vp, vp, vp]),
             "fd_cnn_residual": (i32, [vp, vp, vp, vp, vp, vp]),
             "fd_restrict": (i32, [vp, i32, i32, vp, vp]),
         }
@@ -395,14 +397,14 @@ def fd_cnn_adam(p_ptr, g_ptr, m_ptr, v_ptr, n, t, lr, beta1, beta2, eps, stream)
            "fd_cnn_adam")
 
 
-def fd_cnn_features(ctx, vref, bits_ptr, x_ptr, stream):
-    _check(lib().fd_cnn_features(ctx, float(vref), _vp(bits_ptr), _vp(x_ptr), _vp(stream)),
-           "fd_cnn_features", ctx)
+def fd_cnn_features(ctx, vref, mask_ptr, bits_ptr, x_ptr, stream):
+    _check(lib().fd_cnn_features(ctx, float(vref), _vp(mask_ptr), _vp(bits_ptr), _vp(x_ptr),
+                                 _vp(stream)), "fd_cnn_features", ctx)
 
 
-def fd_cnn_correct(ctx, d_ptr, bits_ptr, stream):
-    _check(lib().fd_cnn_correct(ctx, _vp(d_ptr), _vp(bits_ptr), _vp(stream)), "fd_cnn_correct",
-           ctx)
+def fd_cnn_correct(ctx, d_ptr, mask_ptr, bits_ptr, stream):
+    _check(lib().fd_cnn_correct(ctx, _vp(d_ptr), _vp(mask_ptr), _vp(bits_ptr), _vp(stream)),
+           "fd_cnn_correct", ctx)
 
 
 def fd_cnn_residual(ctx, ref_cur_ptr, ref_prev_ptr, bits_ptr, target_ptr, stream):

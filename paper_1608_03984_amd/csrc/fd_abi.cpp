@@ -1185,8 +1185,9 @@ int32_t fd_cnn_conv(const uint16_t* x, int32_t cin_pad, const int64_t* shape,
     if (mode == FD_CNN_LINEAR && (!bias || !yf || cout_store < 1 || cout_store > 16))
         return FD_ERR_INVALID_ARG;
     if (mode == FD_CNN_MASKED && (!mask || !aligned16(y))) return FD_ERR_INVALID_ARG;
-    if (mode != FD_CNN_RELU && mode != FD_CNN_LINEAR && mode != FD_CNN_MASKED)
-        return FD_ERR_INVALID_ARG;
+    if (mode == FD_CNN_IDENTITY && (!bias || !aligned16(y))) return FD_ERR_INVALID_ARG;
+    if (mode == FD_CNN_UNMASKED && !aligned16(y)) return FD_ERR_INVALID_ARG;
+    if (mode < FD_CNN_RELU || mode > FD_CNN_UNMASKED) return FD_ERR_INVALID_ARG;
     const hipError_t e = fd::launch_cnn_conv(x, cin_pad, (int)shape[0], (int)shape[1],
                                              (int)shape[2], packed, bias, mode, mask, cout_store,
                                              y, yf, static_cast<hipStream_t>(stream));
@@ -1244,24 +1245,26 @@ static int32_t cnn_ctx_ok(fd_ctx* ctx) {
     return FD_OK;
 }
 
-int32_t fd_cnn_features(fd_ctx* ctx, float vref, uint32_t* scale_bits, uint16_t* x,
-                        void* stream) {
+int32_t fd_cnn_features(fd_ctx* ctx, float vref, const uint8_t* mask, uint32_t* scale_bits,
+                        uint16_t* x, void* stream) {
     int32_t rc = cnn_ctx_ok(ctx);
     if (rc != FD_OK) return rc;
     if (!scale_bits || !aligned16(x) || !(vref > 0.f))
         return fail(ctx, FD_ERR_INVALID_ARG, "features: bad pointer or vref");
     const hipError_t e = fd::launch_cnn_features(ctx->u[ctx->cur], ctx->u[1 - ctx->cur], ctx->A,
-                                                 ctx->L, (float)(1.0 / (ctx->g.dt * vref)),
+                                                 ctx->L, (float)(1.0 / (ctx->g.dt * vref)), mask,
                                                  scale_bits, x, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? FD_OK : hip_fail(ctx, e, "features");
 }
 
-int32_t fd_cnn_correct(fd_ctx* ctx, const float* d, const uint32_t* scale_bits, void* stream) {
+int32_t fd_cnn_correct(fd_ctx* ctx, const float* d, const uint8_t* mask,
+                       const uint32_t* scale_bits, void* stream) {
     int32_t rc = cnn_ctx_ok(ctx);
     if (rc != FD_OK) return rc;
     if (!d || !scale_bits) return fail(ctx, FD_ERR_INVALID_ARG, "correct: bad pointer");
     const hipError_t e = fd::launch_cnn_correct(ctx->u[ctx->cur], ctx->u[1 - ctx->cur], ctx->L, d,
-                                                scale_bits, static_cast<hipStream_t>(stream));
+                                                mask, scale_bits,
+                                                static_cast<hipStream_t>(stream));
     return e == hipSuccess ? FD_OK : hip_fail(ctx, e, "correct");
 }
 

@@ -73,6 +73,8 @@ __global__ void pack_kernel(const float* __restrict__ w, int cin, int cout, int 
 //   MODE 1: yf = z + b in FP32, the first cout_store channels
 //   MODE 2: y = bf16(z * (mask > 0)), 16 channels (no bias; mask is the
 //           activation of the layer whose input gradient this is)
+//   MODE 3: y = bf16(z + b), 16 channels (a linear layer)
+//   MODE 4: y = bf16(z), 16 channels (backward data of a linear layer)
 template <int CIN, int MODE>
 __global__ __launch_bounds__(256) void conv_kernel(const uint16_t* __restrict__ x, int D, int H,
                                                    int W, const uint4* __restrict__ wp,
@@ -139,6 +141,7 @@ __global__ __launch_bounds__(256) void conv_kernel(const uint16_t* __restrict__ 
                 float v = acc[t][i];
                 if (MODE == 0) v = fmaxf(v + bias[co], 0.f);
                 if (MODE == 2) v = from_bf16(mask[vox * 16 + co]) > 0.f ? v : 0.f;
+                if (MODE == 3) v = v + bias[co];
                 o[i] = to_bf16(v);
             }
             uint2 packed;
@@ -274,9 +277,11 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// max |u| over the interior into *bits (float bits of a non-negative value;
-// integer order equals float order), for the input scale of the network.
+// max |u| over the interior points where mask is set (all of them without a
+// mask) into *bits (float bits of a non-negative value; integer order equals
+// float order), for the input scale of the network.
 __global__ __launch_bounds__(256) void maxabs_kernel(const float* __restrict__ u, Layout L,
+                                                     const uint8_t* __restrict__ mask,
                                                      uint32_t* __restrict__ bits) {
     __shared__ float part[4];
     float m = 0.f;
@@ -286,6 +291,7 @@ __global__ __launch_bounds__(256) void maxabs_kernel(const float* __restrict__ u
         const int x = (int)(i % L.nx);
         const int64_t r = i / L.nx;
         const int y = (int)(r % L.ny), z = (int)(r / L.ny);
+        if (mask && !mask[i]) continue;
         m = fmaxf(m, fabsf(u[L.origin + (int64_t)z * L.plane + (int64_t)y * L.pitch + x]));
     }
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
@@ -296,8 +302,10 @@ __global__ __launch_bounds__(256) void maxabs_kernel(const float* __restrict__ u
 }
 
 // Network input from the solver state: channels (s u^n, s u^{n-1},
-// v / vref - 1, 0 ...) with s = 1 / max|u^n| (read from *bits), v from
-// A = (dt v)^2.  8 channels, dense over the padded grid.
+// s u^n nu, s u^{n-1} nu, 0 ...) with s = 1 / max|u^n| (read from *bits) and
+// nu = v / vref - 1, v from A = (dt v)^2: every channel is linear in the
+// wavefield, so a network without biases maps a quiet region to a zero
+// correction.  8 channels, dense over the padded grid.
 __global__ __launch_bounds__(256) void features_kernel(const float* __restrict__ uc,
                                                        const float* __restrict__ up,
                                                        const float* __restrict__ A, Layout L,
@@ -313,21 +321,23 @@ __global__ __launch_bounds__(256) void features_kernel(const float* __restrict__
         const int64_t r = i / L.nx;
         const int y = (int)(r % L.ny), z = (int)(r / L.ny);
         const int64_t k = L.origin + (int64_t)z * L.plane + (int64_t)y * L.pitch + x;
-        const uint16_t c0 = to_bf16(s * uc[k]), c1 = to_bf16(s * up[k]);
-        const uint16_t c2 = to_bf16(sqrtf(A[k]) * inv_dt_vref - 1.f);
+        const float a = s * uc[k], b = s * up[k];
+        const float nu = sqrtf(A[k]) * inv_dt_vref - 1.f;
         uint4 o;
-        o.x = (uint32_t)c0 | ((uint32_t)c1 << 16);
-        o.y = (uint32_t)c2;
+        o.x = (uint32_t)to_bf16(a) | ((uint32_t)to_bf16(b) << 16);
+        o.y = (uint32_t)to_bf16(a * nu) | ((uint32_t)to_bf16(b * nu) << 16);
         o.z = 0u;
         o.w = 0u;
         *reinterpret_cast<uint4*>(xo + i * 8) = o;
     }
 }
 
-// Apply the network's output: u^n += d0 / s, u^{n-1} += d1 / s.
+// Apply the network's output: u^n += d0 / s, u^{n-1} += d1 / s where mask is
+// set (everywhere without a mask).
 __global__ __launch_bounds__(256) void correct_kernel(float* __restrict__ uc,
                                                       float* __restrict__ up, Layout L,
                                                       const float* __restrict__ d,
+                                                      const uint8_t* __restrict__ mask,
                                                       const uint32_t* __restrict__ bits) {
     const float mx = __uint_as_float(*bits);
     const int64_t n = (int64_t)L.nx * L.ny * L.nz;
@@ -337,6 +347,7 @@ __global__ __launch_bounds__(256) void correct_kernel(float* __restrict__ uc,
         const int64_t r = i / L.nx;
         const int y = (int)(r % L.ny), z = (int)(r / L.ny);
         const int64_t k = L.origin + (int64_t)z * L.plane + (int64_t)y * L.pitch + x;
+        if (mask && !mask[i]) continue;
         uc[k] += d[2 * i] * mx;
         up[k] += d[2 * i + 1] * mx;
     }
@@ -410,9 +421,13 @@ hipError_t launch_cnn_conv(const uint16_t* x, int cin_pad, int D, int H, int W,
     if (cin_pad == 8 && mode == 0) FD_CONV(8, 0);
     else if (cin_pad == 8 && mode == 1) FD_CONV(8, 1);
     else if (cin_pad == 8 && mode == 2) FD_CONV(8, 2);
+    else if (cin_pad == 8 && mode == 3) FD_CONV(8, 3);
+    else if (cin_pad == 8 && mode == 4) FD_CONV(8, 4);
     else if (cin_pad == 16 && mode == 0) FD_CONV(16, 0);
     else if (cin_pad == 16 && mode == 1) FD_CONV(16, 1);
     else if (cin_pad == 16 && mode == 2) FD_CONV(16, 2);
+    else if (cin_pad == 16 && mode == 3) FD_CONV(16, 3);
+    else if (cin_pad == 16 && mode == 4) FD_CONV(16, 4);
     else return hipErrorInvalidValue;
 #undef FD_CONV
     return hipGetLastError();
@@ -462,19 +477,20 @@ hipError_t launch_cnn_adam(float* p, const float* g, float* m, float* v, int64_t
 }
 
 hipError_t launch_cnn_features(const float* uc, const float* up, const float* A, const Layout& L,
-                               float inv_dt_vref, uint32_t* bits, uint16_t* xo, hipStream_t s) {
+                               float inv_dt_vref, const uint8_t* mask, uint32_t* bits,
+                               uint16_t* xo, hipStream_t s) {
     const int64_t n = (int64_t)L.nx * L.ny * L.nz;
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, bits);
-    hipLaunchKernelGGL(maxabs_kernel, dim3(grid1(n)), dim3(256), 0, s, uc, L, bits);
+    hipLaunchKernelGGL(maxabs_kernel, dim3(grid1(n)), dim3(256), 0, s, uc, L, mask, bits);
     hipLaunchKernelGGL(features_kernel, dim3(grid1(n)), dim3(256), 0, s, uc, up, A, L, inv_dt_vref,
                        bits, xo);
     return hipGetLastError();
 }
 
 hipError_t launch_cnn_correct(float* uc, float* up, const Layout& L, const float* d,
-                              const uint32_t* bits, hipStream_t s) {
+                              const uint8_t* mask, const uint32_t* bits, hipStream_t s) {
     const int64_t n = (int64_t)L.nx * L.ny * L.nz;
-    hipLaunchKernelGGL(correct_kernel, dim3(grid1(n)), dim3(256), 0, s, uc, up, L, d, bits);
+    hipLaunchKernelGGL(correct_kernel, dim3(grid1(n)), dim3(256), 0, s, uc, up, L, d, mask, bits);
     return hipGetLastError();
 }
 

@@ -164,9 +164,10 @@ hipError_t launch_cnn_loss_grad(const float* out, const float* target, const uin
 hipError_t launch_cnn_adam(float* p, const float* g, float* m, float* v, int64_t n, int t,
                            float lr, float b1, float b2, float eps, hipStream_t s);
 hipError_t launch_cnn_features(const float* uc, const float* up, const float* A, const Layout& L,
-                               float inv_dt_vref, uint32_t* bits, uint16_t* xo, hipStream_t s);
+                               float inv_dt_vref, const uint8_t* mask, uint32_t* bits,
+                               uint16_t* xo, hipStream_t s);
 hipError_t launch_cnn_correct(float* uc, float* up, const Layout& L, const float* d,
-                              const uint32_t* bits, hipStream_t s);
+                              const uint8_t* mask, const uint32_t* bits, hipStream_t s);
 hipError_t launch_cnn_residual(const float* ref_cur, const float* ref_prev, const float* uc,
                                const float* up, const Layout& L, const uint32_t* bits, float* t,
                                hipStream_t s);

@@ -151,8 +151,11 @@ def test_network_gradient_and_adam_vs_oracle():
     shape = (6, 10, 40)
     V = int(np.prod(shape))
     net = CorrectionNet(seed=4, out_scale=1.0)
+    # non-zero biases here, to check their gradients too
+    net.params[:, 27 * 256:] = torch.from_numpy(
+        rng.standard_normal((3, 16)).astype(np.float32) * 0.1).cuda()
     x = np.zeros(shape + (8,), np.float32)
-    x[..., :3] = rng.standard_normal(shape + (3,))
+    x[..., :4] = rng.standard_normal(shape + (4,))
     xb, xv = bf16_bits(x)
     target = rng.standard_normal(shape + (2,)).astype(np.float32)
     mask = np.zeros(shape, np.uint8)
@@ -189,12 +192,14 @@ def test_network_gradient_and_adam_vs_oracle():
         say(f"  grad {k} rel L2 {e:.2e}")
         assert e < 3e-2, k
     # one Adam step on the GPU against the oracle's, from the GPU gradient
+    # (weights only: the biases are not trained)
     net.adam(1e-3)
     torch.cuda.synchronize()
     p1 = net.params.cpu().numpy()
     ref, _, _ = C.adam_step(p0.astype(np.float64), grads.astype(np.float64), np.zeros(p0.shape),
                             np.zeros(p0.shape), 1, 1e-3)
-    assert np.max(np.abs(p1 - ref)) < 1e-6
+    assert np.max(np.abs(p1[:, :27 * 256] - ref[:, :27 * 256])) < 1e-6
+    assert np.array_equal(p1[:, 27 * 256:], p0[:, 27 * 256:])
 
 
 def test_restrict_features_correct_roundtrip():
@@ -218,7 +223,7 @@ def test_restrict_features_correct_roundtrip():
     up = c.get_field(P.FD_FIELD_PREV).cpu().numpy()
     bits = torch.zeros(1, dtype=torch.int32, device="cuda")
     x0 = torch.empty(V * 8, dtype=torch.int16, device="cuda")
-    P.fd_cnn_features(c.ctx, VREF, bits.data_ptr(), x0.data_ptr(), st())
+    P.fd_cnn_features(c.ctx, VREF, 0, bits.data_ptr(), x0.data_ptr(), st())
     torch.cuda.synchronize()
     mx = np.abs(uc).max()
     assert np.frombuffer(bits.cpu().numpy().tobytes(), np.float32)[0] == np.float32(mx)
@@ -227,14 +232,15 @@ def test_restrict_features_correct_roundtrip():
     np.testing.assert_allclose(feats[..., 0], uc / mx, rtol=2.0 ** -7, atol=1e-30)
     np.testing.assert_allclose(feats[..., 1], up / mx, rtol=2.0 ** -7, atol=1e-30)
     vn = m["vel_c"].astype(np.float64) / VREF - 1
-    assert np.max(np.abs(feats[..., 2] - vn)) < 2e-2
-    assert np.all(feats[..., 3:] == 0)
+    np.testing.assert_allclose(feats[..., 2], uc / mx * vn, rtol=2.0 ** -6, atol=1e-7)
+    np.testing.assert_allclose(feats[..., 3], up / mx * vn, rtol=2.0 ** -6, atol=1e-7)
+    assert np.all(feats[..., 4:] == 0)
     # residual to a reference, applied as a correction, gives the reference
     ref_cur, ref_prev = dev(uc * 1.5 + 1e-3), dev(up * 0.5)
     t = torch.empty(V * 2, dtype=torch.float32, device="cuda")
     P.fd_cnn_residual(c.ctx, ref_cur.data_ptr(), ref_prev.data_ptr(), bits.data_ptr(),
                       t.data_ptr(), st())
-    P.fd_cnn_correct(c.ctx, t.data_ptr(), bits.data_ptr(), st())
+    P.fd_cnn_correct(c.ctx, t.data_ptr(), 0, bits.data_ptr(), st())
     torch.cuda.synchronize()
     a = c.get_field(P.FD_FIELD_CUR).cpu().numpy()
     b = c.get_field(P.FD_FIELD_PREV).cpu().numpy()
