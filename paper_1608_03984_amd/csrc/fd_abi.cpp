@@ -1194,7 +1194,7 @@ int32_t fd_cnn_conv(const uint16_t* x, int32_t cin_pad, const int64_t* shape,
     return e == hipSuccess ? FD_OK : FD_ERR_DEVICE;
 }
 
-static const int kWgradZChunk = 8;
+static const int kWgradZChunk = 32;
 
 int32_t fd_cnn_wgrad_scratch(const int64_t* shape, int64_t* floats) {
     if (!cnn_shape_ok(shape) || !floats) return FD_ERR_INVALID_ARG;

@@ -156,79 +156,158 @@ __global__ __launch_bounds__(256) void conv_kernel(const uint16_t* __restrict__ 
 // db[co] = sum_p dz[p][co], as one MFMA per tap and 32 voxels with A = dz^T
 // (rows co) and B = the shifted x (columns ci), K running over voxels.  Block:
 // 4 waves over a 32 x 4 tile of each plane of a z chunk; wave w owns row
-// y0 + w.  Per plane, dz^T and x^T are staged in LDS transposed (channel-
-// major, x contiguous); x^T is kept in three copies pre-shifted by dx = -1,
-// 0, 1 so that every operand read is an aligned 16-byte row segment.  The
-// bias gradient is the MFMA with B = ones.  Each wave writes its partial sums
-// [27][16][16] + [16] to `partials`, summed by reduce_kernel.
+// y0 + w.  x^T (channel-major, x contiguous) is kept in LDS for the three
+// planes z-1 .. z+1 as a ring, in three copies pre-shifted by dx = -1, 0, 1
+// so that every operand read is an aligned 16-byte row segment; each step
+// loads only the new plane z+1, one 16-byte vector (8 channels of a voxel)
+// per load, and transposes it into the three copies.  dz^T of plane z is
+// staged the same way.  The bias gradient is the MFMA with B = ones.  At the
+// end the four waves' sums are added in LDS and the block writes one partial
+// [27][16][16] + [16] to `partials`, summed by the reduce kernels.
 template <int CX, int CZ>
 __global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__ x,
                                                     const uint16_t* __restrict__ dz, int D, int H,
                                                     int W, int zchunk,
                                                     float* __restrict__ partials) {
     constexpr int LY = kTY + 2;
+    constexpr int XW = kWX + 2;  // loaded voxels along x, with the halo
+    constexpr int LEN = 27 * 256 + 16;
     __shared__ __attribute__((aligned(16))) uint16_t zt[16][kTY][kWX];  // dz^T: [co][y][x]
-    // x^T shifted by dx: [dx+1][ci][z][y][x]
+    // x^T shifted by dx: [dx+1][ci][z ring slot][y][x]
     __shared__ __attribute__((aligned(16))) uint16_t xt[3][16][3][LY][kWX];
+    static_assert(sizeof(xt) >= LEN * sizeof(float), "block reduction reuses x^T");
     const int x0 = blockIdx.x * kWX, y0 = blockIdx.y * kTY;
     const int zb = blockIdx.z * zchunk, ze = min(zb + zchunk, D);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, c = lane & 15;
+
+    // channels past CX / CZ stay zero for the whole block
+    if (CX < 16)
+        for (int i = tid; i < 3 * (16 - CX) * 3 * LY * kWX; i += 256) {
+            const int r = i % (3 * LY * kWX), ci = CX + (i / (3 * LY * kWX)) % (16 - CX),
+                      sh = i / (3 * LY * kWX * (16 - CX));
+            (&xt[sh][ci][0][0][0])[r] = 0;
+        }
+    if (CZ < 16)
+        for (int i = tid; i < (16 - CZ) * kTY * kWX; i += 256)
+            (&zt[CZ][0][0])[i] = 0;
+
+    // plane gz of x (zero outside the volume) into ring slot (gz + 3) % 3
+    auto load_x = [&](int gz) {
+        const int slot = (gz + 3) % 3;
+        constexpr int C8 = CX / 8;
+        for (int i = tid; i < LY * XW * C8; i += 256) {
+            const int c8 = i % C8, xx = (i / C8) % XW, yy = i / (C8 * XW);
+            const int gx = x0 - 1 + xx, gy = y0 - 1 + yy;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D)
+                v = *reinterpret_cast<const uint4*>(x + (((int64_t)gz * H + gy) * W + gx) * CX +
+                                                    8 * c8);
+            const uint16_t e[8] = {(uint16_t)v.x, (uint16_t)(v.x >> 16), (uint16_t)v.y,
+                                   (uint16_t)(v.y >> 16), (uint16_t)v.z, (uint16_t)(v.z >> 16),
+                                   (uint16_t)v.w, (uint16_t)(v.w >> 16)};
+#pragma unroll
+            for (int sh = 0; sh < 3; ++sh) {
+                const int xl = xx - sh;  // copy sh holds x0 + xl + sh - 1
+                if (xl < 0 || xl >= kWX) continue;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) xt[sh][8 * c8 + k][slot][yy][xl] = e[k];
+            }
+        }
+    };
+
     f4 acc[28];
 #pragma unroll
     for (int t = 0; t < 28; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
     bf16x8 ones;
 #pragma unroll
     for (int i = 0; i < 8; ++i) ones[i] = (__bf16)1.0f;
+    load_x(zb - 1);
+    load_x(zb);
     for (int z = zb; z < ze; ++z) {
         __syncthreads();  // the previous plane's operands are consumed
-        // dz^T of plane z
-        for (int i = threadIdx.x; i < 16 * kTY * kWX; i += 256) {
-            const int xx = i % kWX, yy = (i / kWX) % kTY, co = i / (kWX * kTY);
-            const int gx = x0 + xx, gy = y0 + yy;
-            uint16_t v = 0;
-            if (co < CZ && gx < W && gy < H) v = dz[(((int64_t)z * H + gy) * W + gx) * CZ + co];
-            zt[co][yy][xx] = v;
-        }
-        // x^T of planes z-1 .. z+1 with the y halo, three x shifts
-        for (int i = threadIdx.x; i < 3 * 16 * 3 * LY * kWX; i += 256) {
-            const int xx = i % kWX, yy = (i / kWX) % LY, zz = (i / (kWX * LY)) % 3;
-            const int ci = (i / (kWX * LY * 3)) % 16, sh = i / (kWX * LY * 3 * 16);
-            const int gx = x0 + xx + sh - 1, gy = y0 - 1 + yy, gz = z - 1 + zz;
-            uint16_t v = 0;
-            if (ci < CX && gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D)
-                v = x[(((int64_t)gz * H + gy) * W + gx) * CX + ci];
-            xt[sh][ci][zz][yy][xx] = v;
+        load_x(z + 1);
+        {
+            constexpr int C8 = CZ / 8;
+            for (int i = tid; i < kTY * kWX * C8; i += 256) {
+                const int c8 = i % C8, xx = (i / C8) % kWX, yy = i / (C8 * kWX);
+                const int gx = x0 + xx, gy = y0 + yy;
+                uint4 v = {0u, 0u, 0u, 0u};
+                if (gx < W && gy < H)
+                    v = *reinterpret_cast<const uint4*>(dz + (((int64_t)z * H + gy) * W + gx) * CZ +
+                                                        8 * c8);
+                const uint16_t e[8] = {(uint16_t)v.x, (uint16_t)(v.x >> 16), (uint16_t)v.y,
+                                       (uint16_t)(v.y >> 16), (uint16_t)v.z, (uint16_t)(v.z >> 16),
+                                       (uint16_t)v.w, (uint16_t)(v.w >> 16)};
+#pragma unroll
+                for (int k = 0; k < 8; ++k) zt[8 * c8 + k][yy][xx] = e[k];
+            }
         }
         __syncthreads();
         const bf16x8 av = as_bf16x8(*reinterpret_cast<const uint4*>(&zt[c][wave][8 * g]));
 #pragma unroll
-        for (int tap = 0; tap < 27; ++tap) {
-            const int ddz = tap / 9, ddy = (tap / 3) % 3, ddx = tap % 3;
-            const bf16x8 bv =
-                as_bf16x8(*reinterpret_cast<const uint4*>(&xt[ddx][c][ddz][wave + ddy][8 * g]));
-            acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[tap], 0, 0, 0);
+        for (int ddz = 0; ddz < 3; ++ddz) {
+            const int slot = (z - 1 + ddz + 3) % 3;
+#pragma unroll
+            for (int ddy = 0; ddy < 3; ++ddy)
+#pragma unroll
+                for (int ddx = 0; ddx < 3; ++ddx) {
+                    const int tap = 9 * ddz + 3 * ddy + ddx;
+                    const bf16x8 bv = as_bf16x8(
+                        *reinterpret_cast<const uint4*>(&xt[ddx][c][slot][wave + ddy][8 * g]));
+                    acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[tap], 0, 0, 0);
+                }
         }
         acc[27] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, ones, acc[27], 0, 0, 0);
     }
-    // this wave's partial sums: [tap][ci][co] and the bias gradient [co]
+    // the block's sum of the four waves in LDS ([tap][ci][co] and the bias
+    // gradient [co]), then one coalesced partial per block
+    float* red = reinterpret_cast<float*>(&xt[0][0][0][0][0]);
+    for (int wv = 0; wv < 4; ++wv) {
+        __syncthreads();
+        if (wave == wv) {
+#pragma unroll
+            for (int tap = 0; tap < 27; ++tap)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int j = tap * 256 + c * 16 + 4 * g + i;
+                    red[j] = (wv == 0 ? 0.f : red[j]) + acc[tap][i];
+                }
+            if (c == 0)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int j = 27 * 256 + 4 * g + i;
+                    red[j] = (wv == 0 ? 0.f : red[j]) + acc[27][i];
+                }
+        }
+    }
+    __syncthreads();
     const int b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    float* out = partials + ((int64_t)b * 4 + wave) * (27 * 256 + 16);
-#pragma unroll
-    for (int tap = 0; tap < 27; ++tap)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) out[tap * 256 + c * 16 + 4 * g + i] = acc[tap][i];
-    if (c == 0)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) out[27 * 256 + 4 * g + i] = acc[27][i];
+    float* out = partials + (int64_t)b * LEN;
+    for (int j = tid; j < LEN; j += 256) out[j] = red[j];
 }
 
-__global__ void reduce_kernel(const float* __restrict__ partials, int nblocks, int len,
-                              float* __restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// Sum of the per-block partials in two deterministic passes.  Pass 1: block
+// (jb, c) sums slots [c per, (c+1) per) of elements j in its range and writes
+// the sum over slot c per (read only by this block); pass 2 sums the chunk
+// heads.  Slot s holds elements [s len, (s+1) len).
+__global__ __launch_bounds__(256) void reduce_chunks_kernel(float* __restrict__ partials,
+                                                            int nslots, int per, int len) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const int s0 = blockIdx.y * per, s1 = min(s0 + per, nslots);
+    if (j >= len || s0 >= nslots) return;
+    float s = 0.f;
+    for (int b = s0; b < s1; ++b) s += partials[(int64_t)b * len + j];
+    partials[(int64_t)s0 * len + j] = s;
+}
+
+__global__ __launch_bounds__(256) void reduce_heads_kernel(const float* __restrict__ partials,
+                                                           int nslots, int per, int len,
+                                                           float* __restrict__ out) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= len) return;
     float s = 0.f;
-    for (int b = 0; b < nblocks; ++b) s += partials[(int64_t)b * len + j];
+    for (int b = 0; b < nslots; b += per) s += partials[(int64_t)b * len + j];
     out[j] = s;
 }
 
@@ -433,9 +512,9 @@ hipError_t launch_cnn_conv(const uint16_t* x, int cin_pad, int D, int H, int W,
     return hipGetLastError();
 }
 
-// Partial-sum slots (one per wave) the weight-gradient pass writes.
+// Partial-sum slots (one per block) the weight-gradient pass writes.
 int cnn_wgrad_slots(int D, int H, int W, int zchunk) {
-    return 4 * ((W + kWX - 1) / kWX) * ((H + kTY - 1) / kTY) * ((D + zchunk - 1) / zchunk);
+    return ((W + kWX - 1) / kWX) * ((H + kTY - 1) / kTY) * ((D + zchunk - 1) / zchunk);
 }
 
 hipError_t launch_cnn_wgrad(const uint16_t* x, int cx, const uint16_t* dz, int cz, int D, int H,
@@ -455,15 +534,23 @@ hipError_t launch_cnn_wgrad(const uint16_t* x, int cx, const uint16_t* dz, int c
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int len = 27 * 256 + 16;
-    hipLaunchKernelGGL(reduce_kernel, dim3((len + 255) / 256), dim3(256), 0, s, partials,
-                       (int)(4 * grid.x * grid.y * grid.z), len, out);
+    const int nslots = (int)(grid.x * grid.y * grid.z);
+    const int chunks = nslots < 64 ? nslots : 64;
+    const int per = (nslots + chunks - 1) / chunks;
+    const int nj = (len + 255) / 256;
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3(nj, chunks), dim3(256), 0, s, partials, nslots,
+                       per, len);
+    hipLaunchKernelGGL(reduce_heads_kernel, dim3(nj), dim3(256), 0, s, partials, nslots, per, len,
+                       out);
     return hipGetLastError();
 }
 
 hipError_t launch_cnn_loss_grad(const float* out, const float* target, const uint8_t* mask,
                                 int64_t nvox, int cout, int cpad, float inv_n, uint16_t* dz,
                                 float* loss, hipStream_t s) {
-    hipLaunchKernelGGL(loss_grad_kernel, dim3(grid1(nvox)), dim3(256), 0, s, out, target, mask,
+    // few blocks: each block ends in one atomic on the loss
+    const int gmax = grid1(nvox) < 1024 ? grid1(nvox) : 1024;
+    hipLaunchKernelGGL(loss_grad_kernel, dim3(gmax), dim3(256), 0, s, out, target, mask,
                        nvox, cout, cpad, inv_n, dz, loss);
     return hipGetLastError();
 }
@@ -481,7 +568,9 @@ hipError_t launch_cnn_features(const float* uc, const float* up, const float* A,
                                uint16_t* xo, hipStream_t s) {
     const int64_t n = (int64_t)L.nx * L.ny * L.nz;
     hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(1), 0, s, bits);
-    hipLaunchKernelGGL(maxabs_kernel, dim3(grid1(n)), dim3(256), 0, s, uc, L, mask, bits);
+    // few blocks: each block ends in one atomic on the same word
+    const int gmax = grid1(n) < 1024 ? grid1(n) : 1024;
+    hipLaunchKernelGGL(maxabs_kernel, dim3(gmax), dim3(256), 0, s, uc, L, mask, bits);
     hipLaunchKernelGGL(features_kernel, dim3(grid1(n)), dim3(256), 0, s, uc, up, A, L, inv_dt_vref,
                        bits, xo);
     return hipGetLastError();
