@@ -40,7 +40,8 @@ sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 TRAFFIC_SUMMARY = ROOT / "profiles" / "acoustic3d_tiled_592cubed_traffic.md"
-KERNEL_SOURCE = ROOT / "paper_1608_03984_amd" / "csrc" / "fd_acoustic.hip"
+KERNEL_SOURCES = [ROOT / "paper_1608_03984_amd" / "csrc" / f
+                  for f in ("fd_acoustic_tiled.h", "fd_acoustic.hip", "fd_acoustic_hi.hip")]
 BYTES_PER_POINT = 16           # read u^n, u^{n-1}, dt^2 v^2; write u^{n+1}
 ORDERS = (4, 8, 12, 16)
 
@@ -70,6 +71,11 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_hash() -> str:
+    """sha256[:16] of the acoustic kernel's sources, concatenated in order."""
+    return hashlib.sha256(b"".join(f.read_bytes() for f in KERNEL_SOURCES)).hexdigest()[:16]
+
+
 def committed_traffic(phys: int):
     """Per-order HBM bytes per launch from the committed counter summary, or
     None when the summary is missing, for another size, or older than the
@@ -80,7 +86,7 @@ def committed_traffic(phys: int):
     if not m:
         return None
     data = json.loads(m.group(1))
-    if data["source_sha256_16"] != hashlib.sha256(KERNEL_SOURCE.read_bytes()).hexdigest()[:16]:
+    if data["source_sha256_16"] != kernel_source_hash():
         return None
     return {int(k): v["traffic_bytes"] for k, v in data["per_order"].items()}
 

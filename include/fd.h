@@ -372,11 +372,20 @@ int32_t fd_restrict(fd_ctx* ctx, int32_t which, int32_t stride, float* dst, void
  *   threads, 1 = 64x16 with 256, 2 = 64x8 with 512, 3 = 64x16 with 512,
  *   -1 = the default for the space order (and shot count).
  * FD_OPT_SHOTS_PER_BLOCK: shots a block of the tiled 3D acoustic kernel
- *   advances together (1, 2 or 4; 0 = default; 2 and 4 need tile 0 or 2). */
+ *   advances together (1, 2 or 4; 0 = default; 2 and 4 need tile 0 or 2).
+ * FD_OPT_DAMPING_PROFILE: 1 (default) = when fd_setup found the 3D damping
+ *   field to be a sum of per-axis profiles (sigma(x, y, z) = (s_x + s_y) + s_z
+ *   with the profiles taken along the lines through the centre point,
+ *   agreeing everywhere to within 2^-20 of the field's maximum, as for the
+ *   usual absorbing layer), the tiled 3D acoustic kernel evaluates that sum
+ *   instead of reading the field (4 bytes per damped point less traffic);
+ *   0 = always read the field.  Other fields, the 2D and the direct kernels
+ *   always read the field. */
 #define FD_OPT_KERNEL 1
 #define FD_OPT_ZCHUNK 2
 #define FD_OPT_TILE 3
 #define FD_OPT_SHOTS_PER_BLOCK 4
+#define FD_OPT_DAMPING_PROFILE 5
 int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value);
 
 /* Frees the host context (not the workspace). NULL is accepted. */

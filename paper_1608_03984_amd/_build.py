@@ -14,8 +14,8 @@ INCLUDE = ROOT / "include"
 OBJDIR = ROOT / "_build"
 LIB = PKG / "libfd.so"
 
-SOURCES = ["fd_abi.cpp", "fd_common.hip", "fd_acoustic.hip", "fd_tti.hip", "fd_vti.hip",
-           "fd_adjoint.hip", "fd_cnn.hip", "fd_probe.hip"]
+SOURCES = ["fd_acoustic_hi.hip", "fd_acoustic.hip", "fd_tti.hip", "fd_vti.hip", "fd_abi.cpp",
+           "fd_common.hip", "fd_adjoint.hip", "fd_cnn.hip", "fd_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

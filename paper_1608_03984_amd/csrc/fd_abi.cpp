@@ -39,6 +39,9 @@ struct fd_ctx {
     float* u[2];  // acoustic u / TTI p: two levels (shot k at + k * L.volume)
     float* r[2];  // TTI r: two levels
     int32_t* dflag;
+    float* prof;      // damping profiles sx[nx], sy[ny], sz[nz] (3D)
+    bool sep_ok;      // the damping field is (sx + sy) + sz to within 2^-20 of its maximum
+    bool sep_use;     // FD_OPT_DAMPING_PROFILE
     SparsePoint* pts;
     int cur;  // index of the level holding u^n in u[]/r[]
     // derived stencil coefficients (float, already divided by h or h^2)
@@ -216,6 +219,7 @@ uint64_t plan_workspace(const fd_grid* g, const Layout& L, int32_t nshots, int32
     const int64_t ntx = (L.nx + fd::kTileX - 1) / fd::kTileX;
     const int64_t nty = (L.ny + min_tile_y() - 1) / min_tile_y();
     const uint64_t o_flag = cv.take((uint64_t)(ntx * nty * L.nz) * sizeof(int32_t));
+    const uint64_t o_prof = cv.take((uint64_t)(L.nx + L.ny + L.nz) * sizeof(float));
     const uint64_t o_pts = cv.take((uint64_t)(max_points > 0 ? max_points : 1) * sizeof(SparsePoint));
     if (ctx && base) {
         ctx->reduce = reinterpret_cast<uint32_t*>(base + o_red);
@@ -229,6 +233,7 @@ uint64_t plan_workspace(const fd_grid* g, const Layout& L, int32_t nshots, int32
         ctx->r[0] = aniso ? reinterpret_cast<float*>(base + o_r[0]) : nullptr;
         ctx->r[1] = aniso ? reinterpret_cast<float*>(base + o_r[1]) : nullptr;
         ctx->dflag = reinterpret_cast<int32_t*>(base + o_flag);
+        ctx->prof = reinterpret_cast<float*>(base + o_prof);
         ctx->pts = reinterpret_cast<SparsePoint*>(base + o_pts);
     }
     return cv.off;
@@ -393,6 +398,11 @@ fd::AcousticStep acoustic_params(const fd_ctx* ctx) {
     p.A = ctx->A;
     p.sig = ctx->damping ? ctx->sig : nullptr;
     p.dflag = ctx->g.ndim == 3 ? ctx->dflag : nullptr;  // all zero without damping
+    if (ctx->damping && ctx->sep_ok && ctx->sep_use) {
+        p.sx = ctx->prof;
+        p.sy = ctx->prof + ctx->L.nx;
+        p.sz = ctx->prof + ctx->L.nx + ctx->L.ny;
+    }
     p.L = ctx->L;
     double c0 = 0.0;
     for (int a = 0; a < 3; ++a) c0 += ctx->w2[a][0];
@@ -568,6 +578,8 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
     ctx->ck_store = nullptr;
     ctx->ck_nt = ctx->ck_interval = 0;
     ctx->ck_last_acc = false;
+    ctx->sep_ok = false;
+    ctx->sep_use = true;
     plan_workspace(grid, L, nshots, max_points, ctx, static_cast<char*>(workspace));
     hipStream_t s = static_cast<hipStream_t>(stream);
 
@@ -597,7 +609,11 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
     sa.L = L;
     he = fd::launch_setup(sa, s);
     if (he == hipSuccess) he = refresh_flags(ctx, s);
-    uint32_t red[4] = {0, 0, 0, 0};
+    const bool try_sep = ctx->damping && grid->ndim == 3;
+    if (he == hipSuccess && try_sep)
+        he = fd::launch_damping_profiles(ctx->sig, L, ctx->prof, ctx->prof + L.nx,
+                                         ctx->prof + L.nx + L.ny, ctx->reduce + 4, s);
+    uint32_t red[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (he == hipSuccess) he = hipMemcpyAsync(red, ctx->reduce, sizeof(red), hipMemcpyDeviceToHost, s);
     if (he == hipSuccess) he = hipStreamSynchronize(s);
     if (he != hipSuccess) {
@@ -612,6 +628,12 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
     if (red[2]) {
         delete ctx;
         return FD_ERR_INVALID_ARG;  // delta > epsilon: unstable pseudo-acoustic mode
+    }
+    if (try_sep) {
+        float dmax, smax;
+        std::memcpy(&dmax, &red[4], sizeof(float));
+        std::memcpy(&smax, &red[5], sizeof(float));
+        ctx->sep_ok = smax > 0.f && dmax <= std::ldexp(smax, -20);
     }
     float vmax;
     std::memcpy(&vmax, &red[0], sizeof(float));
@@ -665,6 +687,11 @@ int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value) {
             ctx->flags_stale = true;  // rebuilt on the caller's stream by fd_forward
             return FD_OK;
         }
+        case FD_OPT_DAMPING_PROFILE:
+            if (value != 0 && value != 1)
+                return fail(ctx, FD_ERR_INVALID_ARG, "damping profile option 0 or 1");
+            ctx->sep_use = value == 1;
+            return FD_OK;
         case FD_OPT_SHOTS_PER_BLOCK: {
             const int v = value <= 0 ? default_shots_per_block(ctx->radius, ctx->nshots)
                                      : (int)value;

@@ -116,6 +116,62 @@ __global__ __launch_bounds__(kBlock) void setup_kernel(SetupArgs a) {
     if (dgt) atomicOr(&a.reduce[2], 1u);
 }
 
+// Damping profiles through the centre point (xc, yc, zc): sx[x] = sig(x, yc,
+// zc), sy[y] = sig(xc, y, zc), sz[z] = sig(xc, yc, z).  For a field that is a
+// sum of per-axis profiles vanishing at the centre (the usual absorbing
+// layer), (sx[x] + sy[y]) + sz[z] reproduces it.
+__global__ __launch_bounds__(kBlock) void damping_profile_kernel(const float* __restrict__ sig,
+                                                                 Layout L, float* sx, float* sy,
+                                                                 float* sz) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int xc = L.nx / 2, yc = L.ny / 2, zc = L.nz / 2;
+    if (i < L.nx) sx[i] = sig[vol_index(L, i, yc, zc)];
+    if (i < L.ny) sy[i] = sig[vol_index(L, xc, i, zc)];
+    if (i < L.nz) sz[i] = sig[vol_index(L, xc, yc, i)];
+}
+
+// red[0] = max |sig - ((sx + sy) + sz)|, red[1] = max sig (float bits; both
+// non-negative, so integer order is float order).
+__global__ __launch_bounds__(kBlock) void damping_check_kernel(const float* __restrict__ sig,
+                                                               Layout L,
+                                                               const float* __restrict__ sx,
+                                                               const float* __restrict__ sy,
+                                                               const float* __restrict__ sz,
+                                                               uint32_t* red) {
+    __shared__ float sd[kBlock / 64], sm[kBlock / 64];
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    float dmax = 0.f, smx = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int x = (int)(i % L.nx);
+        const int64_t r = i / L.nx;
+        const int y = (int)(r % L.ny);
+        const int z = (int)(r / L.ny);
+        const float v = sig[vol_index(L, x, y, z)];
+        const float sep = (sx[x] + sy[y]) + sz[z];
+        dmax = fmaxf(dmax, fabsf(v - sep));
+        smx = fmaxf(smx, fabsf(v));
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        dmax = fmaxf(dmax, __shfl_xor(dmax, off));
+        smx = fmaxf(smx, __shfl_xor(smx, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sd[threadIdx.x >> 6] = dmax;
+        sm[threadIdx.x >> 6] = smx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float d = sd[0], m = sm[0];
+        for (int i = 1; i < kBlock / 64; ++i) {
+            d = fmaxf(d, sd[i]);
+            m = fmaxf(m, sm[i]);
+        }
+        atomicMax(&red[0], __float_as_uint(d));
+        atomicMax(&red[1], __float_as_uint(m));
+    }
+}
+
 // flags[(z * nty + ty) * ntx + tx] = 1 when any damping coefficient in the
 // 64 x tile_y tile (tx, ty) of plane z is non-zero.
 __global__ __launch_bounds__(kBlock) void damping_flags_kernel(const float* __restrict__ sig,
@@ -210,6 +266,19 @@ hipError_t launch_unpack(const float* dense, float* vol, const Layout& L, hipStr
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(setup_kernel, dim3(grid_for((int64_t)a.L.nx * a.L.ny * a.L.nz)),
                        dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_damping_profiles(const float* sig, const Layout& L, float* sx, float* sy,
+                                   float* sz, uint32_t* red, hipStream_t s) {
+    const int nmax = L.nx > L.ny ? (L.nx > L.nz ? L.nx : L.nz) : (L.ny > L.nz ? L.ny : L.nz);
+    hipLaunchKernelGGL(damping_profile_kernel, dim3((nmax + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       s, sig, L, sx, sy, sz);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t g = grid_for((int64_t)L.nx * L.ny * L.nz);
+    hipLaunchKernelGGL(damping_check_kernel, dim3(g < 1024 ? g : 1024), dim3(kBlock), 0, s, sig,
+                       L, sx, sy, sz, red);
     return hipGetLastError();
 }
 

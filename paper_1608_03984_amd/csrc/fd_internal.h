@@ -49,6 +49,12 @@ struct AcousticStep {
     const float* __restrict__ A;   // dt^2 v^2
     const float* __restrict__ sig; // eta dt / 2, or nullptr
     const int32_t* __restrict__ dflag; // per (z, tile): 1 if the tile-plane holds damping
+    // Separable damping: when set, sig[x][y][z] equals (sx[x] + sy[y]) + sz[z]
+    // (checked at setup) and the tiled kernel evaluates that sum instead of
+    // reading sig.
+    const float* __restrict__ sx;
+    const float* __restrict__ sy;
+    const float* __restrict__ sz;
     float c0;
     float cx[kMaxRadius + 1], cy[kMaxRadius + 1], cz[kMaxRadius + 1];
     Layout L;
@@ -126,6 +132,11 @@ struct SetupArgs {
     Layout L;
 };
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
+// Per-axis damping profiles along the lines through the centre point, then
+// the largest |sig - ((sx + sy) + sz)| and the largest sig over the volume into
+// red[0] and red[1] (float bits).
+hipError_t launch_damping_profiles(const float* sig, const Layout& L, float* sx, float* sy,
+                                   float* sz, uint32_t* red, hipStream_t s);
 hipError_t launch_damping_flags(const float* sig, int32_t* flags, const Layout& L, int tile_y,
                                 int ntx, int nty, hipStream_t s);
 
@@ -177,6 +188,9 @@ hipError_t launch_restrict(const float* u, const Layout& L, int stride, float* o
 // stencils
 hipError_t launch_acoustic(const AcousticStep& p, int ndim, int radius, int variant, int tile_cfg,
                            int shots_per_block, hipStream_t s);
+// The tiled 3D kernel for radius 5-8 (a translation unit of its own).
+hipError_t launch_acoustic_tiled_hi(const AcousticStep& p, int radius, int cfg,
+                                    int shots_per_block, hipStream_t s);
 hipError_t launch_tti(const TTIStep& p, int radius, int variant, hipStream_t s);
 hipError_t launch_vti(const VTIStep& p, int ndim, int radius, int variant, hipStream_t s);
 

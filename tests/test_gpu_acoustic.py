@@ -23,10 +23,12 @@ pytestmark = pytest.mark.gpu
 ORDERS = [2, 4, 6, 8, 10, 12, 14, 16]
 
 
-def gpu_run(p, variant=0, tile=None, zchunk=0):
+def gpu_run(p, variant=0, tile=None, zchunk=0, damping_profile=None):
     s = from_problem(p)
     if variant:
         s.set_option(P.FD_OPT_KERNEL, variant)
+    if damping_profile is not None:
+        s.set_option(P.FD_OPT_DAMPING_PROFILE, damping_profile)
     if tile is not None:
         s.set_option(P.FD_OPT_TILE, tile)
     if zchunk:
@@ -135,6 +137,30 @@ def test_acoustic_full_size_one_step_sampled(full_size_inputs, so):
     say(f"  sampled ({pts.size} pts) one-step rel L2 {e:.2e}")
     assert e < 1e-5
     assert np.all(np.isfinite(got[pts]))
+
+
+@pytest.mark.parametrize("so", [4, 16])
+def test_damping_profiles(so):
+    """The tiled kernel's per-axis damping profiles: for the usual layer (a
+    sum of per-axis profiles) the run matches the one that reads the field
+    and the oracle; for a field that is not such a sum the field is read
+    either way (bitwise equal runs) and the oracle still matches."""
+    import dataclasses
+    p = acoustic_problem(3, (150, 37, 41), 8, so, 120, seed=40 + so)
+    say(f"case: damping profiles {p.padded} so{so}")
+    on, off = gpu_run(p), gpu_run(p, damping_profile=0)
+    say(f"  separable layer: profiles vs field traces {rel(on[0], off[0]):.2e} "
+        f"field {rel(on[1], off[1]):.2e}")
+    assert rel(on[0], off[0]) < 1e-6 and rel(on[1], off[1]) < 1e-6
+    rng = np.random.default_rng(so)
+    eta = p.eta * (1.0 + 0.2 * rng.random(p.eta.shape)).astype(np.float32)
+    q = dataclasses.replace(p, eta=eta.astype(np.float32))
+    on, off = gpu_run(q), gpu_run(q, damping_profile=0)
+    assert np.array_equal(on[0], off[0]) and np.array_equal(on[1], off[1])
+    tref, st, peak = oracle_run_with_peak(q, chunk=40)
+    et, eu = rel(on[0], tref), float(np.linalg.norm(on[1] - st[1]) / peak)
+    say(f"  non-separable field vs oracle: traces {et:.2e} field/peak {eu:.2e}")
+    assert et < 1e-4 and eu < 1e-4
 
 
 def test_acoustic_deterministic():
