@@ -281,10 +281,12 @@ bool locate(const fd_ctx* ctx, const double* c, SparsePoint* P) {
     return true;
 }
 
-// Tile shape of the tiled acoustic kernel (measured on the 592^3 workload):
-// 64 x 16 with 512 threads up to radius 4, 64 x 8 with 256 threads above,
-// where the wider register queue leaves room for fewer rows per block.
-int default_tile(int radius) { return radius <= 4 ? 3 : 0; }
+// Tile shape of the tiled acoustic kernel (measured on the 592^3 workload
+// with the damping layer evaluated from its profiles): 64 x 8 with 256
+// threads at every radius.  With the automatic z chunk every block then owns
+// a whole column (740 blocks at 592^3, all resident at once), so neighbouring
+// tiles march through z together and share their halo rows in L2.
+int default_tile(int) { return 0; }
 
 // Several shots (measured with 16 shots on the 336^3 survey grid): 4 shots
 // per block up to radius 2, 2 up to radius 6, one above, where the register
