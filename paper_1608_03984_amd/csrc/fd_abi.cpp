@@ -288,11 +288,11 @@ bool locate(const fd_ctx* ctx, const double* c, SparsePoint* P) {
 // tiles march through z together and share their halo rows in L2.
 int default_tile(int) { return 0; }
 
-// Several shots (measured with 16 shots on the 336^3 survey grid): 4 shots
-// per block up to radius 2, 2 up to radius 6, one above, where the register
-// queues of several shots cost more occupancy than the shared model reads
-// save; 64 x 8 tiles of 512 threads (configuration 2), 64 x 8 of 256 above
-// radius 6.
+// Several shots (measured with 16 shots on the 336^3 survey grid, three z
+// chunks): 4 shots per block up to radius 2, 2 up to radius 6, one above,
+// where the register queues of several shots cost more occupancy than the
+// shared model reads save; 64 x 8 tiles of 512 threads (configuration 2),
+// 64 x 8 of 256 above radius 6.
 int default_shots_per_block(int radius, int nshots) {
     if (nshots <= 1) return 1;
     const int sb = radius <= 2 ? 4 : (radius <= 6 ? 2 : 1);
@@ -307,12 +307,24 @@ void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, int ng
     const int nty = (L.ny + tile_y - 1) / tile_y;
     int zc = zchunk_opt;
     if (zc <= 0) {
-        // Split z so the grid holds about 768 blocks (three 256-thread blocks
-        // per CU): every z chunk re-reads 2R planes and runs R pipeline-fill
-        // steps, so high orders round the chunk count down.  Groups of shots
-        // multiply the blocks of one z chunk.
+        // One wavefield: one chunk per column when the x-y tiles already give
+        // the chip about 6 waves per CU (1600 waves) -- neighbouring tiles
+        // then march through z together from the first plane, sharing halo
+        // rows in L2, and no chunk re-reads 2R planes or refills the pipeline
+        // (measured best for the acoustic kernel at 592^3 and VTI and TTI at
+        // 464^3); otherwise z is split for about 768 blocks, high orders
+        // rounding the count down.  Several shots (many more blocks than the
+        // chip holds at once): three chunks per column, 4-10 % faster than
+        // whole columns for 16 shots at 336^3.
+        const int waves = (ctx->tti || ctx->vti) ? 8 : (ctx->tile_cfg <= 1 ? 4 : 8);
         const int64_t xy = (int64_t)ntx * nty * ngroups;
-        int64_t nzc = radius <= 4 ? (768 + xy / 2) / xy : 768 / xy;
+        int64_t nzc;
+        if (ctx->nshots > 1)
+            nzc = 3;
+        else if (xy * waves >= 1600)
+            nzc = 1;
+        else
+            nzc = radius <= 4 ? (768 + xy / 2) / xy : 768 / xy;
         if (nzc < 1) nzc = 1;
         zc = (int)((L.nz + nzc - 1) / nzc);
         if (zc < 4 * radius) zc = 4 * radius;
@@ -754,6 +766,11 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
         p.dflag = nd == 3 ? ctx->dflag : nullptr;
         p.e = ctx->e;
         p.d = ctx->d;
+        if (nd == 3 && ctx->damping && ctx->sep_ok && ctx->sep_use) {
+            p.sx = ctx->prof;
+            p.sy = ctx->prof + ctx->L.nx;
+            p.sz = ctx->prof + ctx->L.nx + ctx->L.ny;
+        }
         p.L = ctx->L;
         p.c0h = (float)((double)ctx->w2[0][0] + (nd == 3 ? (double)ctx->w2[1][0] : 0.0));
         p.c0z = ctx->w2[2][0];

@@ -99,6 +99,10 @@ struct VTIStep {
     const int32_t* __restrict__ dflag;
     const float* __restrict__ e;  // 1 + 2 eps
     const float* __restrict__ d;  // sqrt(1 + 2 delta)
+    // separable damping (as in AcousticStep): sig = (sx[x] + sy[y]) + sz[z]
+    const float* __restrict__ sx;
+    const float* __restrict__ sy;
+    const float* __restrict__ sz;
     float c0h, c0z;
     float cx[kMaxRadius + 1], cy[kMaxRadius + 1], cz[kMaxRadius + 1];
     Layout L;

@@ -87,13 +87,15 @@ __global__ __launch_bounds__(256) void vti_direct(VTIStep p) {
 // loaded two steps ahead into one of two register slots, the z loop is
 // unrolled by the queue period 2R+2, loads and stores are raw buffer
 // accesses with 32-bit offsets (ghost points read 0, their stores drop), the
-// damping coefficient is read only in tile-planes flagged as damped, and
-// block numbers are mapped so each XCD streams a contiguous run of tiles.
+// damping coefficient is read only in tile-planes flagged as damped (and
+// not at all when it is a sum of per-axis profiles: SEP adds the three
+// profile values), and block numbers are mapped so each XCD streams a
+// contiguous run of tiles.
 // ---------------------------------------------------------------------------
 typedef const __attribute__((address_space(4))) int32_t cflag_t;
 constexpr uint32_t kOOB = 0x80000000u;
 
-template <int R, int NW, int VY>
+template <int R, int NW, int VY, bool SEP>
 struct TiledVTI {
     static constexpr int TY = NW * VY;
     static constexpr int LW = kTileX + 2 * R;
@@ -118,6 +120,8 @@ struct TiledVTI {
     float rh[2][VY], pcn[2][VY], hy[2][NYH], hx[2][NXH];
     float ppv[2][VY], rpv[2][VY], aa[2][VY], ee[2][VY], dd[2][VY], sg[2][VY];
     int damp[2];
+    float sxl, syv[VY], ezs[2];  // SEP: profile values (x per lane, y per row, z per step)
+    const __attribute__((address_space(4))) float* szc;
 
     __device__ TiledVTI(const VTIStep& ps, float* l) : p(ps), lds(l) {}
 
@@ -159,9 +163,13 @@ struct TiledVTI {
         const int dm = (out && flagbuf != 0) ? 1 : 0;
         flagbuf = flag_of(zc + 1);
         damp[S] = dm;
-        const auto rs = rsrc(dm ? sb + zo : zpl);
+        if constexpr (SEP) {
+            ezs[S] = dm ? szc[zc] : 0.f;
+        } else {
+            const auto rs = rsrc(dm ? sb + zo : zpl);
 #pragma unroll
-        for (int v = 0; v < VY; ++v) sg[S][v] = bload(rs, oc[v]);
+            for (int v = 0; v < VY; ++v) sg[S][v] = bload(rs, oc[v]);
+        }
     }
 
     template <int K>
@@ -201,7 +209,8 @@ struct TiledVTI {
             const float dh = fmaf(p.c0h, pcn[S][v], lx + ly);
             const float dzz = fmaf(p.c0z, q[C][v], lz);
             vti_update(pcn[S][v], ppv[S][v], q[C][v], rpv[S][v], aa[S][v], ee[S][v], dd[S][v],
-                       damp[S] ? sg[S][v] : 0.f, dh, dzz, pn[v], rn[v]);
+                       damp[S] ? (SEP ? (sxl + syv[v]) + ezs[S] : sg[S][v]) : 0.f, dh, dzz,
+                       pn[v], rn[v]);
         }
 #pragma unroll
         for (int v = 0; v < VY; ++v) {
@@ -248,6 +257,17 @@ struct TiledVTI {
         sb = (p.sig ? p.sig : p.A) + org;
         zpl = p.A + org - (int64_t)kGhostYZ * plane;
         flags = (cflag_t*)p.dflag;
+        sxl = 0.f;
+#pragma unroll
+        for (int v = 0; v < VY; ++v) syv[v] = 0.f;
+        if constexpr (SEP) {
+            // the same sum, in the same order, as the setup's check; lanes and
+            // rows past the interior read the last value (their stores drop)
+            szc = (const __attribute__((address_space(4))) float*)p.sz;
+            sxl = p.sx[min(x0 + lane, nx - 1)];
+#pragma unroll
+            for (int v = 0; v < VY; ++v) syv[v] = p.sy[min(y0 + w * VY + v, ny - 1)];
+        }
         auto off = [&](int r, int c) -> uint32_t {
             const int y = y0 - R + r, x = x0 - R + c;
             return (x >= 0 && x < nx && y >= 0 && y < ny) ? (uint32_t)((r * pitch + c) * 4)
@@ -293,10 +313,10 @@ struct TiledVTI {
     }
 };
 
-template <int R, int NW, int VY>
+template <int R, int NW, int VY, bool SEP>
 __global__ __launch_bounds__(64 * NW) void vti3d_tiled(VTIStep p) {
-    __shared__ float lds[2 * TiledVTI<R, NW, VY>::LDS_FLOATS];
-    TiledVTI<R, NW, VY> k(p, lds);
+    __shared__ float lds[2 * TiledVTI<R, NW, VY, SEP>::LDS_FLOATS];
+    TiledVTI<R, NW, VY, SEP> k(p, lds);
     k.run();
 }
 
@@ -313,7 +333,10 @@ hipError_t launch_direct(const VTIStep& p, int ndim, hipStream_t s) {
 
 template <int R>
 hipError_t launch_tiled(const VTIStep& p, hipStream_t s) {
-    hipLaunchKernelGGL((vti3d_tiled<R, 8, 2>), dim3(p.nblocks), dim3(512), 0, s, p);
+    if (p.sx)
+        hipLaunchKernelGGL((vti3d_tiled<R, 8, 2, true>), dim3(p.nblocks), dim3(512), 0, s, p);
+    else
+        hipLaunchKernelGGL((vti3d_tiled<R, 8, 2, false>), dim3(p.nblocks), dim3(512), 0, s, p);
     return hipGetLastError();
 }
 
