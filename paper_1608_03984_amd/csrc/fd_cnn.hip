@@ -27,6 +27,7 @@ typedef __attribute__((ext_vector_type(4))) float f4;
 constexpr int kTX = 64;  // forward output tile: 64 x 4 voxels of one plane
 constexpr int kTY = 4;
 constexpr int kWX = 32;  // weight-gradient tile: 32 x 4 voxels per plane
+constexpr int kZC = 16;  // z planes per block of the convolution
 
 __device__ __forceinline__ uint16_t to_bf16(float f) {
     return __builtin_bit_cast(uint16_t, (__bf16)f);
@@ -66,9 +67,15 @@ __global__ void pack_kernel(const float* __restrict__ w, int cin, int cout, int 
 }
 
 // Forward (and backward-data) convolution.  Block: 4 waves, one 64 x 4 tile
-// of one z plane; wave w computes row y0 + w as 4 groups of 16 voxels.  The
-// input region with its one-voxel halo is staged in LDS; each MFMA reads its B
-// operand (8 channels of one voxel, 16 bytes) from there.
+// of (x, y) marching over kZC planes of z; wave w computes row y0 + w as 4
+// groups of 16 voxels.  The input planes z-1 .. z+1 with their one-voxel
+// halo sit in a ring of four LDS slots; each step loads plane z+2 into
+// registers while the matrix cores work on plane z and stores it into the
+// free slot at the start of the next step, so every input plane is loaded
+// once per block and one barrier per step suffices (a wave can run at most
+// one step ahead, and the slot it fills is the one no step in flight reads).
+// The packed weights stay in registers for the whole block.  Each MFMA reads
+// its B operand (8 channels of one voxel, 16 bytes) from the ring.
 //   MODE 0: y = bf16(relu(z + b)), 16 channels
 //   MODE 1: yf = z + b in FP32, the first cout_store channels
 //   MODE 2: y = bf16(z * (mask > 0)), 16 channels (no bias; mask is the
@@ -84,70 +91,102 @@ __global__ __launch_bounds__(256) void conv_kernel(const uint16_t* __restrict__ 
                                                    float* __restrict__ yf) {
     constexpr int NST = nsteps<CIN>();
     constexpr int C8 = CIN / 8;
-    constexpr int LX = kTX + 2, LY = kTY + 2, LZ = 3;
-    __shared__ uint4 tile[LZ * LY * LX * C8];
-    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z;
-    for (int i = threadIdx.x; i < LZ * LY * LX * C8; i += 256) {
-        const int c8 = i % C8, v = i / C8;
-        const int lx = v % LX, ly = (v / LX) % LY, lz = v / (LX * LY);
-        const int gx = x0 - 1 + lx, gy = y0 - 1 + ly, gz = z0 - 1 + lz;
-        uint4 val = {0u, 0u, 0u, 0u};
-        if (gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D)
-            val = *reinterpret_cast<const uint4*>(x + (((int64_t)gz * H + gy) * W + gx) * CIN +
-                                                  8 * c8);
-        tile[i] = val;
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int LX = kTX + 2, LY = kTY + 2;
+    constexpr int PL = LY * LX * C8;         // 16-byte vectors per staged plane
+    constexpr int NLD = (PL + 255) / 256;    // of them per thread
+    __shared__ uint4 ring[4 * PL];
+    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY;
+    const int zb = blockIdx.z * kZC, ze = min(zb + kZC, D);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, n = lane & 15;
+
+    // plane gz of the input (zero outside the volume) into registers, and
+    // from there into ring slot (gz + 4) & 3 (gz >= -1)
+    uint4 st[NLD];
+    auto load = [&](int gz) {
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int i = tid + 256 * k;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (i < PL) {
+                const int c8 = i % C8, vv = i / C8;
+                const int gx = x0 - 1 + vv % LX, gy = y0 - 1 + vv / LX;
+                if (gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D)
+                    v = *reinterpret_cast<const uint4*>(
+                        x + (((int64_t)gz * H + gy) * W + gx) * CIN + 8 * c8);
+            }
+            st[k] = v;
+        }
+    };
+    auto store = [&](int gz) {
+        uint4* sl = ring + ((gz + 4) & 3) * PL;
+#pragma unroll
+        for (int k = 0; k < NLD; ++k) {
+            const int i = tid + 256 * k;
+            if (i < PL) sl[i] = st[k];
+        }
+    };
+
     bf16x8 a[NST];
 #pragma unroll
     for (int s = 0; s < NST; ++s) a[s] = as_bf16x8(wp[s * 64 + lane]);
-    __syncthreads();
-    f4 acc[4];
+    load(zb - 1);
+    store(zb - 1);
+    load(zb);
+    store(zb);
+    load(zb + 1);
+    const int gy = y0 + wave;
+    for (int z = zb; z < ze; ++z) {
+        store(z + 1);
+        __syncthreads();
+        load(z + 2);  // in flight while the matrix cores work on plane z
+        f4 acc[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < 4; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < NST; ++s) {
-        const int k0 = 32 * s + 8 * g;
-        const bool ok = k0 / CIN < 27;
-        const int tap = ok ? k0 / CIN : 13;  // padding steps read the centre, then use 0
-        const int c8 = (k0 % CIN) / 8;
-        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-        const int base = (((1 + dz) * LY + (1 + wave + dy)) * LX + (1 + n + dx)) * C8 + c8;
+        for (int s = 0; s < NST; ++s) {
+            const int k0 = 32 * s + 8 * g;
+            const bool ok = k0 / CIN < 27;
+            const int tap = ok ? k0 / CIN : 13;  // padding steps read the centre, then use 0
+            const int c8 = (k0 % CIN) / 8;
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const uint4* pl = ring + ((z + dz + 4) & 3) * PL;
+            const int base = ((1 + wave + dy) * LX + (1 + n + dx)) * C8 + c8;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint4 bv = ok ? pl[base + 16 * t * C8] : uint4{0u, 0u, 0u, 0u};
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[s], as_bf16x8(bv), acc[t], 0, 0,
+                                                                0);
+            }
+        }
+        if (gy >= H) continue;  // rows past the volume store nothing (no barrier skipped)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const uint4 bv = ok ? tile[base + 16 * t * C8] : uint4{0u, 0u, 0u, 0u};
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[s], as_bf16x8(bv), acc[t], 0, 0, 0);
-        }
-    }
-    const int gy = y0 + wave, gz = z0;
-    if (gy >= H) return;
+            const int gx = x0 + 16 * t + n;
+            if (gx >= W) continue;
+            const int64_t vox = ((int64_t)z * H + gy) * W + gx;
+            if (MODE == 1) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int gx = x0 + 16 * t + n;
-        if (gx >= W) continue;
-        const int64_t vox = ((int64_t)gz * H + gy) * W + gx;
-        if (MODE == 1) {
+                for (int i = 0; i < 4; ++i) {
+                    const int co = 4 * g + i;
+                    if (co < cout_store) yf[vox * cout_store + co] = acc[t][i] + bias[co];
+                }
+            } else {
+                uint16_t o[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int co = 4 * g + i;
-                if (co < cout_store) yf[vox * cout_store + co] = acc[t][i] + bias[co];
+                for (int i = 0; i < 4; ++i) {
+                    const int co = 4 * g + i;
+                    float v = acc[t][i];
+                    if (MODE == 0) v = fmaxf(v + bias[co], 0.f);
+                    if (MODE == 2) v = from_bf16(mask[vox * 16 + co]) > 0.f ? v : 0.f;
+                    if (MODE == 3) v = v + bias[co];
+                    o[i] = to_bf16(v);
+                }
+                uint2 packed;
+                packed.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
+                packed.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
+                *reinterpret_cast<uint2*>(y + vox * 16 + 4 * g) = packed;
             }
-        } else {
-            uint16_t o[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int co = 4 * g + i;
-                float v = acc[t][i];
-                if (MODE == 0) v = fmaxf(v + bias[co], 0.f);
-                if (MODE == 2) v = from_bf16(mask[vox * 16 + co]) > 0.f ? v : 0.f;
-                if (MODE == 3) v = v + bias[co];
-                o[i] = to_bf16(v);
-            }
-            uint2 packed;
-            packed.x = (uint32_t)o[0] | ((uint32_t)o[1] << 16);
-            packed.y = (uint32_t)o[2] | ((uint32_t)o[3] << 16);
-            *reinterpret_cast<uint2*>(y + vox * 16 + 4 * g) = packed;
         }
     }
 }
@@ -492,7 +531,7 @@ hipError_t launch_cnn_conv(const uint16_t* x, int cin_pad, int D, int H, int W,
                            const uint16_t* packed, const float* bias, int mode,
                            const uint16_t* mask, int cout_store, uint16_t* y, float* yf,
                            hipStream_t s) {
-    const dim3 grid((W + kTX - 1) / kTX, (H + kTY - 1) / kTY, D);
+    const dim3 grid((W + kTX - 1) / kTX, (H + kTY - 1) / kTY, (D + kZC - 1) / kZC);
     const uint4* wp = reinterpret_cast<const uint4*>(packed);
 #define FD_CONV(CI, MO)                                                                      \
     hipLaunchKernelGGL((conv_kernel<CI, MO>), grid, dim3(256), 0, s, x, D, H, W, wp, bias, mask, \

@@ -53,7 +53,7 @@ def st():
     return torch.cuda.current_stream().cuda_stream
 
 
-SHAPES = [(3, 5, 70), (4, 9, 33), (2, 4, 130)]
+SHAPES = [(3, 5, 70), (4, 9, 33), (2, 4, 130), (37, 6, 70)]
 
 
 @pytest.mark.parametrize("cin,mode", [(8, 0), (8, 1), (16, 0), (16, 1), (8, 2), (16, 2)])
