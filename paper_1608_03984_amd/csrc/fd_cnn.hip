@@ -231,28 +231,73 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__
         for (int i = tid; i < (16 - CZ) * kTY * kWX; i += 256)
             (&zt[CZ][0][0])[i] = 0;
 
-    // plane gz of x (zero outside the volume) into ring slot (gz + 3) % 3
-    auto load_x = [&](int gz) {
+    // 16-byte vectors (8 channels of a voxel): plane gz of x with its halo
+    // (LY x XW voxels, NLX vectors per thread) and plane gz of dz (kTY x kWX
+    // voxels, one vector per thread).  Loads go to registers first (issued a
+    // step ahead), then are transposed into LDS.
+    constexpr int NX = LY * XW * (CX / 8), NZ = kTY * kWX * (CZ / 8);
+    constexpr int NLX = (NX + 255) / 256;
+    static_assert(NZ <= 256, "one dz vector per thread per plane");
+    auto load_x = [&](int gz, uint4 (&v)[NLX]) {
+#pragma unroll
+        for (int k = 0; k < NLX; ++k) {
+            const int i = tid + 256 * k;
+            v[k] = uint4{0u, 0u, 0u, 0u};
+            if (i < NX) {
+                constexpr int C8 = CX / 8;
+                const int c8 = i % C8, xx = (i / C8) % XW, yy = i / (C8 * XW);
+                const int gx = x0 - 1 + xx, gy = y0 - 1 + yy;
+                if (gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D)
+                    v[k] = *reinterpret_cast<const uint4*>(
+                        x + (((int64_t)gz * H + gy) * W + gx) * CX + 8 * c8);
+            }
+        }
+    };
+    // x^T of plane gz into ring slot (gz + 3) % 3, three x-shifted copies
+    auto put_x = [&](int gz, const uint4 (&v)[NLX]) {
         const int slot = (gz + 3) % 3;
-        constexpr int C8 = CX / 8;
-        for (int i = tid; i < LY * XW * C8; i += 256) {
+#pragma unroll
+        for (int k = 0; k < NLX; ++k) {
+            const int i = tid + 256 * k;
+            if (i >= NX) continue;
+            constexpr int C8 = CX / 8;
             const int c8 = i % C8, xx = (i / C8) % XW, yy = i / (C8 * XW);
-            const int gx = x0 - 1 + xx, gy = y0 - 1 + yy;
-            uint4 v = {0u, 0u, 0u, 0u};
-            if (gx >= 0 && gx < W && gy >= 0 && gy < H && gz >= 0 && gz < D)
-                v = *reinterpret_cast<const uint4*>(x + (((int64_t)gz * H + gy) * W + gx) * CX +
-                                                    8 * c8);
-            const uint16_t e[8] = {(uint16_t)v.x, (uint16_t)(v.x >> 16), (uint16_t)v.y,
-                                   (uint16_t)(v.y >> 16), (uint16_t)v.z, (uint16_t)(v.z >> 16),
-                                   (uint16_t)v.w, (uint16_t)(v.w >> 16)};
+            const uint4 w = v[k];
+            const uint16_t e[8] = {(uint16_t)w.x, (uint16_t)(w.x >> 16), (uint16_t)w.y,
+                                   (uint16_t)(w.y >> 16), (uint16_t)w.z, (uint16_t)(w.z >> 16),
+                                   (uint16_t)w.w, (uint16_t)(w.w >> 16)};
 #pragma unroll
             for (int sh = 0; sh < 3; ++sh) {
                 const int xl = xx - sh;  // copy sh holds x0 + xl + sh - 1
                 if (xl < 0 || xl >= kWX) continue;
 #pragma unroll
-                for (int k = 0; k < 8; ++k) xt[sh][8 * c8 + k][slot][yy][xl] = e[k];
+                for (int j = 0; j < 8; ++j) xt[sh][8 * c8 + j][slot][yy][xl] = e[j];
             }
         }
+    };
+    auto load_dz = [&](int gz) -> uint4 {
+        uint4 v = {0u, 0u, 0u, 0u};
+        const int i = tid;
+        if (i < NZ) {
+            constexpr int C8 = CZ / 8;
+            const int c8 = i % C8, xx = (i / C8) % kWX, yy = i / (C8 * kWX);
+            const int gx = x0 + xx, gy = y0 + yy;
+            if (gx < W && gy < H && gz < D)
+                v = *reinterpret_cast<const uint4*>(dz + (((int64_t)gz * H + gy) * W + gx) * CZ +
+                                                    8 * c8);
+        }
+        return v;
+    };
+    auto put_dz = [&](uint4 v) {
+        const int i = tid;
+        if (i >= NZ) return;
+        constexpr int C8 = CZ / 8;
+        const int c8 = i % C8, xx = (i / C8) % kWX, yy = i / (C8 * kWX);
+        const uint16_t e[8] = {(uint16_t)v.x, (uint16_t)(v.x >> 16), (uint16_t)v.y,
+                               (uint16_t)(v.y >> 16), (uint16_t)v.z, (uint16_t)(v.z >> 16),
+                               (uint16_t)v.w, (uint16_t)(v.w >> 16)};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) zt[8 * c8 + k][yy][xx] = e[k];
     };
 
     f4 acc[28];
@@ -261,28 +306,20 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const uint16_t* __restrict__
     bf16x8 ones;
 #pragma unroll
     for (int i = 0; i < 8; ++i) ones[i] = (__bf16)1.0f;
-    load_x(zb - 1);
-    load_x(zb);
+    uint4 rx[NLX];
+    load_x(zb - 1, rx);
+    put_x(zb - 1, rx);
+    load_x(zb, rx);
+    put_x(zb, rx);
+    load_x(zb + 1, rx);
+    uint4 rz = load_dz(zb);
     for (int z = zb; z < ze; ++z) {
         __syncthreads();  // the previous plane's operands are consumed
-        load_x(z + 1);
-        {
-            constexpr int C8 = CZ / 8;
-            for (int i = tid; i < kTY * kWX * C8; i += 256) {
-                const int c8 = i % C8, xx = (i / C8) % kWX, yy = i / (C8 * kWX);
-                const int gx = x0 + xx, gy = y0 + yy;
-                uint4 v = {0u, 0u, 0u, 0u};
-                if (gx < W && gy < H)
-                    v = *reinterpret_cast<const uint4*>(dz + (((int64_t)z * H + gy) * W + gx) * CZ +
-                                                        8 * c8);
-                const uint16_t e[8] = {(uint16_t)v.x, (uint16_t)(v.x >> 16), (uint16_t)v.y,
-                                       (uint16_t)(v.y >> 16), (uint16_t)v.z, (uint16_t)(v.z >> 16),
-                                       (uint16_t)v.w, (uint16_t)(v.w >> 16)};
-#pragma unroll
-                for (int k = 0; k < 8; ++k) zt[8 * c8 + k][yy][xx] = e[k];
-            }
-        }
+        put_x(z + 1, rx);
+        put_dz(rz);
         __syncthreads();
+        load_x(z + 2, rx);  // in flight while the matrix cores work on plane z
+        rz = load_dz(z + 1);
         const bf16x8 av = as_bf16x8(*reinterpret_cast<const uint4*>(&zt[c][wave][8 * g]));
 #pragma unroll
         for (int ddz = 0; ddz < 3; ++ddz) {
