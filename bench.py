@@ -63,9 +63,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-pass", action="store_true")
     ap.add_argument("--workload",
-                    choices=("acoustic", "tti", "vti", "gradient", "shots", "cost", "learned"),
+                    choices=("acoustic", "tti", "vti", "gradient", "fwi", "shots", "cost",
+                             "learned"),
                     default="acoustic")
     ap.add_argument("--interval", type=int, default=0)
+    ap.add_argument("--fwi-steps", type=int, default=1200)
     ap.add_argument("--models", type=int, default=24)
     ap.add_argument("--iters", type=int, default=1500)
     return ap.parse_args()
@@ -302,6 +304,107 @@ def gradient_bench(args):
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "whole gradient (algorithmic bytes of every pass / wall time)"},
         "finite": r["finite"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+def fwi_bench(args):
+    """FWI gradient of the 16-shot survey (256^3 + 40-point layer = 336^3
+    points, h = 15 m, so 8, 1200 steps, one 8 Hz Ricker per shot on a 4 x 4
+    grid at z = 30 m, 256 x 256 receivers).  Observed data: the true model,
+    all 16 shots advanced in one launch per step.  Timed: for each shot, the
+    checkpointed forward run in the smoothed start model and the gradient of
+    J = 1/2 sum_shots |d - d_obs|^2 with respect to v, summed over the shots
+    into one buffer (FD_GRAD_ACCUMULATE).  Checked: central differences of J
+    (16-shot launches) along the normalised gradient against <g, dir>.
+    Algorithmic bytes per point and step as in the single-shot gradient."""
+    import torch
+
+    from paper_1608_03984_amd.solver import Solver
+    from workloads import fwi_3d
+
+    S, nt = 16, args.fwi_steps
+    p = fwi_3d(so=8, phys=256 if args.phys == 512 else args.phys, nbl=40, nt=nt, nshots=S,
+               receivers="surface")
+    npts = p.npoints
+    dev = torch.device("cuda:0")
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    srcs = [p.src[k:k + 1] for k in range(S)]
+    wav = torch.from_numpy(p.wavelet.astype(np.float32)).to(dev)
+    nrec = p.rec.shape[0]
+    say = lambda m: print(m, file=sys.stderr, flush=True)
+
+    def survey(vel):
+        """Traces of all shots in `vel` (one launch per step for the 16 shots)."""
+        sv = Solver(3, p.shape, p.spacing, p.nbl, p.so, p.dt, vel, p.eta, nshots=S,
+                    max_points=S * (1 + nrec), device=dev)
+        tr = sv.forward_shots(nt, srcs, [wav] * S, [p.rec] * S)
+        torch.cuda.synchronize()
+        sv.close()
+        return tr
+
+    def misfit(tr, dobs):
+        return float(sum(0.5 * torch.sum((a.double() - b.double()) ** 2) for a, b in
+                         zip(tr, dobs)))
+
+    t0 = time.perf_counter()
+    dobs = survey(p.vel)
+    t_obs = time.perf_counter() - t0
+    say(f"# observed data: {S} shots x {nt} steps in {t_obs:.2f} s")
+    vel0 = p.extra["vel_start"]
+    s = Solver(3, p.shape, p.spacing, p.nbl, p.so, p.dt, vel0, p.eta, max_points=1 + nrec,
+               device=dev)
+    g = torch.zeros(s.field_shape, dtype=torch.float32, device=dev)
+    info = {}
+
+    def gradient():
+        g.zero_()
+        for k in range(S):
+            tr = s.forward_checkpointed(nt, srcs[k], wav, p.rec, interval=args.interval)
+            res = tr - dobs[k]
+            s.gradient(res, wrt="vel", wavelet_grad=False, accumulate_into=g)
+            info["interval"] = s.checkpoint_interval
+            info["store_gb"] = s._ck["bytes"] / 1e9
+
+    # warm-up: one shot
+    tr = s.forward_checkpointed(nt, srcs[0], wav, p.rec, interval=args.interval)
+    s.gradient(tr - dobs[0], wrt="vel", wavelet_grad=False)
+    t_grad = timed(gradient, ev)
+    say(f"# gradient of {S} shots in {t_grad:.2f} s")
+    finite = bool(torch.isfinite(g).all().item())
+    s.close()
+    # central differences along the normalised gradient
+    d = (g / g.abs().max()).cpu().numpy()
+    J0 = misfit(survey(vel0), dobs)
+    gd = float(torch.sum(g.double() * torch.from_numpy(d).to(dev).double()))
+    eps = 1e-3 * J0 / abs(gd) if gd != 0 else 1.0
+    Jp = misfit(survey((vel0 + eps * d).astype(np.float32)), dobs)
+    Jm = misfit(survey((vel0 - eps * d).astype(np.float32)), dobs)
+    fd = (Jp - Jm) / (2 * eps)
+    say(f"# J {J0:.6e}, central difference {fd:.6e} vs <g, dir> {gd:.6e} (eps {eps:.3e} m/s)")
+    I = info["interval"]
+    last = nt - (nt - 1) // I * I
+    flushes = (nt + 31) // 32
+    alg = S * npts * (16 * nt + 4 * last + 20 * (nt - last) + 16 * nt + 16 * nt + 16 * flushes)
+    ach = alg / t_grad / 1e9
+    line = {
+        "metric": "FWI gradient Gpt/s (3D acoustic so8, 16-shot survey)",
+        "value": round(S * npts * nt / t_grad / 1e9, 3), "unit": "Gpt/s", "n_gpus": 1,
+        "steps": nt, "warmup": 1, "ms_per_step": round(t_grad / nt * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"FWI gradient of a {S}-shot survey, 3D acoustic {p.shape[0]}^3 + "
+                               f"40-pt layer ({p.padded[0]}^3 points), h=15 m, so 8, {nt} steps, "
+                               f"8 Hz Ricker per shot, {nrec} receivers, true vs smoothed model",
+                   "points": npts, "shots": S, "interval": I,
+                   "store_gb_per_shot": round(info["store_gb"], 1)},
+        "gradient_s": round(t_grad, 3), "observed_data_s": round(t_obs, 3),
+        "misfit": J0, "fd_check": {"central_difference": fd, "gradient_dot_dir": gd,
+                                   "eps_m_per_s": eps, "rel_err": abs(fd - gd) / abs(gd)},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "whole gradient (algorithmic bytes of every pass / wall time)"},
+        "finite": finite,
     }
     print(json.dumps(line), flush=True)
 
@@ -544,6 +647,9 @@ def main():
         return
     if args.workload == "shots":
         shots_bench(args)
+        return
+    if args.workload == "fwi":
+        fwi_bench(args)
         return
     if args.workload == "cost":
         cost_bench(args)

@@ -227,6 +227,9 @@ int32_t fd_set_shot_field(fd_ctx* ctx, int32_t shot, int32_t which, const float*
 /* fd_gradient wrt selectors. */
 #define FD_WRT_M 0   /* gradient with respect to m = 1/v^2 (squared slowness) */
 #define FD_WRT_VEL 1 /* gradient with respect to v */
+/* ORed into wrt: add the gradient into grad instead of overwriting it (the
+ * sum over the shots of a survey, one shot per fd_gradient call). */
+#define FD_GRAD_ACCUMULATE 256
 
 /* Bytes of the caller-owned checkpoint store for nt steps with a checkpoint
  * every `interval` steps (interval <= 0: the memory-minimising choice, about
@@ -248,7 +251,8 @@ int32_t fd_forward_checkpointed(fd_ctx* ctx, int32_t nt, const fd_points* src,
 /* Gradient of J with respect to the model (wrt = FD_WRT_M or FD_WRT_VEL)
  * and the source wavelets, for the trace sensitivities adj->data ([nt][n],
  * device, read; adj->coords are the receiver positions of the forward run).
- * grad: device dense [Nz][Ny][Nx] float32 over the padded array, overwritten.
+ * grad: device dense [Nz][Ny][Nx] float32 over the padded array, overwritten
+ * (or added to, with FD_GRAD_ACCUMULATE in wrt).
  * wavelet_grad: device [nt][nsrc] float32 (dJ/dq), overwritten; NULL skips it.
  * Requires a preceding fd_forward_checkpointed with the same store, nt,
  * interval and sources (FD_ERR_INVALID_ARG otherwise); may be called again on

@@ -39,6 +39,7 @@ FD_OPT_DAMPING_PROFILE = 5
 
 FD_WRT_M = 0
 FD_WRT_VEL = 1
+FD_GRAD_ACCUMULATE = 256
 
 FD_CNN_LAYER_FLOATS = 27 * 256 + 16
 FD_CNN_RELU = 0

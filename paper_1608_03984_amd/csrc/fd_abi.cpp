@@ -998,6 +998,8 @@ int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_poin
         return fail(ctx, FD_ERR_INVALID_ARG, "gradients are single-shot contexts");
     if (ctx->tti || ctx->vti)
         return fail(ctx, FD_ERR_UNSUPPORTED, "gradients are built for acoustic only");
+    const bool accumulate = (wrt & FD_GRAD_ACCUMULATE) != 0;
+    wrt &= ~FD_GRAD_ACCUMULATE;
     if (wrt != FD_WRT_M && wrt != FD_WRT_VEL) return fail(ctx, FD_ERR_INVALID_ARG, "wrt");
     if (!grad) return fail(ctx, FD_ERR_INVALID_ARG, "grad is NULL");
     const int I = resolve_interval(ctx, nt, interval);
@@ -1047,7 +1049,7 @@ int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_poin
     if (he == hipSuccess && pending) he = fd::launch_flush_gradient(st.gpart, st.gsum, ctx->L, s);
     if (he == hipSuccess)
         he = fd::launch_finish_gradient(st.gsum, ctx->A, grad, ctx->L, ctx->g.dt, wrt == FD_WRT_VEL,
-                                        s);
+                                        accumulate ? 1 : 0, s);
     if (he != hipSuccess) return hip_fail(ctx, he, "gradient");
     return FD_OK;
 }

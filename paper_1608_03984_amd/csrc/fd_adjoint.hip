@@ -53,7 +53,8 @@ __global__ __launch_bounds__(256) void flush_kernel(float* __restrict__ gpart,
 __global__ __launch_bounds__(256) void finish_kernel(const float* __restrict__ gsum,
                                                      const float* __restrict__ A,
                                                      float* __restrict__ out, Layout L, int ntx,
-                                                     float dt, float inv_dt2, int wrt_vel) {
+                                                     float dt, float inv_dt2, int wrt_vel,
+                                                     int accumulate) {
     const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
     const int x = tx * kTileX + (threadIdx.x & 63);
     const int y = ty * kRows + (threadIdx.x >> 6);
@@ -64,9 +65,11 @@ __global__ __launch_bounds__(256) void finish_kernel(const float* __restrict__ g
         if (wrt_vel) {
             // dJ/dv = dJ/dm * (-2 / v^3), v = sqrt(A) / dt
             const float a = A[v];
-            out[d] = gsum[d] * (2.f * dt) / (a * sqrtf(a));
+            const float g = gsum[d] * (2.f * dt) / (a * sqrtf(a));
+            out[d] = accumulate ? out[d] + g : g;
         } else {
-            out[d] = -gsum[d] * inv_dt2;
+            const float g = -gsum[d] * inv_dt2;
+            out[d] = accumulate ? out[d] + g : g;
         }
     }
 }
@@ -95,11 +98,11 @@ hipError_t launch_flush_gradient(float* gpart, float* gsum, const Layout& L, hip
 }
 
 hipError_t launch_finish_gradient(const float* gsum, const float* A, float* out, const Layout& L,
-                                  double dt, int wrt_vel, hipStream_t s) {
+                                  double dt, int wrt_vel, int accumulate, hipStream_t s) {
     int ntx;
     const dim3 grid = plane_grid(L, ntx);
     hipLaunchKernelGGL(finish_kernel, grid, dim3(256), 0, s, gsum, A, out, L, ntx, (float)dt,
-                       (float)(1.0 / (dt * dt)), wrt_vel);
+                       (float)(1.0 / (dt * dt)), wrt_vel, accumulate);
     return hipGetLastError();
 }
 

@@ -158,9 +158,10 @@ hipError_t launch_image(const float* mu, const float* acc, float* gpart, const L
                         hipStream_t s);
 // gsum[dense] += gpart[vol]; gpart[vol] = 0 over the interior.
 hipError_t launch_flush_gradient(float* gpart, float* gsum, const Layout& L, hipStream_t s);
-// out[dense] = gsum * -1/dt^2 (wrt m = 1/v^2) or gsum * 2 dt / A^{3/2} (wrt v).
+// out[dense] = gsum * -1/dt^2 (wrt m = 1/v^2) or gsum * 2 dt / A^{3/2} (wrt v);
+// with accumulate, that value is added to out.
 hipError_t launch_finish_gradient(const float* gsum, const float* A, float* out, const Layout& L,
-                                  double dt, int wrt_vel, hipStream_t s);
+                                  double dt, int wrt_vel, int accumulate, hipStream_t s);
 
 // correction network (fd_cnn.hip)
 int cnn_packed_elems(int cin_pad);

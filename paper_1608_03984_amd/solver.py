@@ -105,20 +105,30 @@ class Solver:
     def checkpoint_interval(self):
         return self._ck["interval"] if getattr(self, "_ck", None) else None
 
-    def gradient(self, adj_data, wrt="vel", wavelet_grad=True):
+    def gradient(self, adj_data, wrt="vel", wavelet_grad=True, accumulate_into=None):
         """(dJ/dmodel [padded field shape], dJ/dwavelet [nt][nsrc] or None) for
         the trace sensitivities ``adj_data`` [nt][nrec] of the last
-        ``forward_checkpointed`` run."""
+        ``forward_checkpointed`` run.  With ``accumulate_into`` (a float32
+        tensor of the field shape) the model gradient is added to it (the sum
+        over the shots of a survey) and that tensor is returned."""
         ck = self._ck
         nt, src, rec = ck["nt"], ck["src"], ck["rec"]
         d = _dev(adj_data, self.device).reshape(nt, 0 if rec is None else rec.shape[0])
-        grad = torch.empty(self.field_shape, dtype=torch.float32, device=self.device)
+        if accumulate_into is not None:
+            grad = accumulate_into
+            if tuple(grad.shape) != self.field_shape or grad.dtype != torch.float32 \
+                    or not grad.is_contiguous() or not grad.is_cuda:
+                raise ValueError("accumulate_into: contiguous float32 tensor of the field shape")
+        else:
+            grad = torch.empty(self.field_shape, dtype=torch.float32, device=self.device)
         nsrc = 0 if src is None else src.shape[0]
         qg = torch.empty((nt, nsrc), dtype=torch.float32, device=self.device) \
             if wavelet_grad and nsrc else None
         B.fd_gradient(self.ctx, nt, src, ck["q"].data_ptr() if ck["q"] is not None else 0, rec,
                       d.data_ptr(), ck["interval"], ck["ptr"], ck["bytes"],
-                      B.FD_WRT_VEL if wrt == "vel" else B.FD_WRT_M, grad.data_ptr(),
+                      (B.FD_WRT_VEL if wrt == "vel" else B.FD_WRT_M)
+                      | (B.FD_GRAD_ACCUMULATE if accumulate_into is not None else 0),
+                      grad.data_ptr(),
                       qg.data_ptr() if qg is not None else 0, self.stream)
         self._keep_adj = d
         return grad, qg

@@ -156,6 +156,34 @@ def test_gradient_wrt_velocity_and_repeat():
     assert rel(gv1, gref * (-2.0 / v ** 3)) < 2e-4
 
 
+def test_gradient_accumulates_over_shots():
+    """FD_GRAD_ACCUMULATE: the gradients of two shots (two source positions)
+    summed into one buffer equal the FP32 sum of the separate gradients, and
+    that sum matches the sum of the oracle's gradients."""
+    import dataclasses
+    p = acoustic_problem(3, (70, 24, 30), 5, 8, 60, seed=23)
+    q = dataclasses.replace(p, src=p.src + np.array([[120.0, -30.0, 40.0]]))
+    say("case: gradient accumulated over two shots")
+    s = from_problem(p)
+    gs, refs = [], []
+    acc = torch.zeros(s.field_shape, dtype=torch.float32, device=s.device)
+    for k, shot in enumerate((p, q)):
+        dobs = observed(shot, seed=50 + k)
+        tr = s.forward_checkpointed(shot.nt, shot.src, shot.wavelet, shot.rec, interval=7)
+        res = tr - torch.from_numpy(dobs.astype(np.float32)).to(tr.device)
+        g, _ = s.gradient(res, wrt="vel", wavelet_grad=False)
+        gs.append(g.cpu().numpy())
+        s.gradient(res, wrt="vel", wavelet_grad=False, accumulate_into=acc)
+        refs.append(oracle_gradient(shot, dobs)[0] * (-2.0 / shot.vel.astype(np.float64) ** 3))
+    got = acc.cpu().numpy()
+    torch.cuda.synchronize()
+    s.close()
+    assert np.array_equal(got, (gs[0] + gs[1]).astype(np.float32))
+    e = rel(got, refs[0] + refs[1])
+    say(f"  accumulated vs oracle sum: {e:.2e}")
+    assert e < 2e-4
+
+
 def test_autograd_function():
     """torch.autograd through AcousticModeling: vel.grad and wavelet.grad of
     1/2 |d - dobs|^2 against the oracle."""
