@@ -68,8 +68,9 @@ def parse():
                     default="acoustic")
     ap.add_argument("--interval", type=int, default=0)
     ap.add_argument("--fwi-steps", type=int, default=1200)
-    ap.add_argument("--models", type=int, default=24)
-    ap.add_argument("--iters", type=int, default=1500)
+    ap.add_argument("--models", type=int, default=200)
+    ap.add_argument("--windows", type=int, default=4)
+    ap.add_argument("--iters", type=int, default=3000)
     return ap.parse_args()
 
 
@@ -560,11 +561,16 @@ def learned_bench(args):
     times = list(range(start + K, nt_c + 1, 8))
     t0 = time.perf_counter()
     samples = []
+    # --windows per model (evenly spaced over the run, shifted from model to
+    # model so that together they cover every window time)
+    nw = min(args.windows, len(times)) if args.windows > 0 else len(times)
     for i in range(args.models):
         pair = Lm.make_pair(learned_model(100 + i))
-        samples += Lm.training_pairs(pair, times, K)
+        sel = sorted({times[(i + j * len(times) // nw) % len(times)] for j in range(nw)})
+        samples += Lm.training_pairs(pair, sel, K)
         pair.close()
-        say(f"# training model {i + 1}/{args.models}: {len(samples)} samples")
+        if (i + 1) % 10 == 0 or i + 1 == args.models:
+            say(f"# training model {i + 1}/{args.models}: {len(samples)} samples")
     t_data = time.perf_counter() - t0
     net = Lm.CorrectionNet(seed=1, out_scale=0.01)
     none_loss = Lm.sample_loss(None, samples, shape_c)
@@ -573,6 +579,7 @@ def learned_bench(args):
     train_loss = Lm.sample_loss(net, samples, shape_c)
     say(f"# trained {args.iters} iterations in {t_train:.1f} s: window loss {none_loss:.3e} "
         f"-> {train_loss:.3e}")
+    n_samples = len(samples)
     del samples
     rows = []
     for seed in (900, 901, 902):
@@ -618,7 +625,9 @@ def learned_bench(args):
         "config": {"workload": "fine so16 256^3+40 (h 10 m, 1000 steps) judged; coarse so4 "
                                "128^3+20 (h 20 m, 500 steps) corrected every 8 steps by a "
                                "3-layer 3x3x3 conv net (16 channels, BF16, FP32 accumulation)",
-                   "train_models": args.models, "train_iters": args.iters,
+                   "train_models": args.models, "windows_per_model": nw,
+                   "train_samples": n_samples,
+                   "train_iters": args.iters,
                    "data_s": round(t_data, 1), "train_s": round(t_train, 2),
                    "window_loss_train": [none_loss, train_loss]},
         "plain_at_equal_error_s": round(mean("plain_at_equal_error_s"), 4),
