@@ -539,7 +539,7 @@ def learned_bench(args):
     correction every 8 coarse steps after the source has radiated.  Trains on
     --models random layered models (solver-generated pairs) with libfd's
     kernels, then times and scores on 3 held-out models: the fine solve (the
-    judge), the plain coarse solve, the corrected coarse solve, the coarse
+    reference), the plain coarse solve, the corrected coarse solve, the coarse
     solve corrected by the exact residual (the scheme's best case), and plain
     coarse solves of space order 8 and 16.  Errors are relative L2 of the
     receiver traces against the fine solve, over all receivers and samples
@@ -622,7 +622,7 @@ def learned_bench(args):
         "warmup": 1, "ms_per_step": round(t_learn / nt_c * 1e3, 4),
         "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
-        "config": {"workload": "fine so16 256^3+40 (h 10 m, 1000 steps) judged; coarse so4 "
+        "config": {"workload": "fine so16 256^3+40 (h 10 m, 1000 steps) as reference; coarse so4 "
                                "128^3+20 (h 20 m, 500 steps) corrected every 8 steps by a "
                                "3-layer 3x3x3 conv net (16 channels, BF16, FP32 accumulation)",
                    "train_models": args.models, "windows_per_model": nw,

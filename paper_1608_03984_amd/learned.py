@@ -11,7 +11,7 @@ loops over them, and runs the corrected solver.
 
 The cost study of the paper (section 6) trades space order against grid
 spacing at a fixed physical problem; the plain solvers stay available as the
-fallback and as the judge of the learned solver's error.
+fallback and as the reference for the learned solver's error.
 """
 from __future__ import annotations
 

@@ -1,7 +1,7 @@
 """The learned coarse-grid correction end to end on small grids: training
 pairs from the fine (space order 16, h) and coarse (space order 4, 2h)
 solvers, training by libfd's own forward/backward kernels and Adam, and the
-corrected coarse solver against the plain one, both judged by the fine
+corrected coarse solver against the plain one, both measured against the fine
 solve's receiver traces.
 
 What is asserted:
