@@ -262,6 +262,16 @@ int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_poin
                     int32_t interval, void* store, uint64_t store_bytes, int32_t wrt,
                     float* grad, float* wavelet_grad, void* stream);
 
+/* The least-squares misfit of full-waveform inversion (the objective whose
+ * gradient fd_gradient returns when given res as the trace sensitivities):
+ * res = d - d_obs elementwise (n FP32 values, device; res may alias d) and
+ * *J += 1/2 sum res^2 (J: one device double, accumulated, so the caller
+ * clears it; the sum is taken in FP64 because finite differences of J check
+ * the gradient).  Asynchronous on `stream`.  FD_ERR_INVALID_ARG for n < 0 or
+ * missing pointers. */
+int32_t fd_misfit(const float* d, const float* d_obs, int64_t n, float* res, double* J,
+                  void* stream);
+
 /* The transpose of the zero-state map q -> d: reads adj->data ([nt][nrec],
  * receiver positions adj->coords) and writes out->data ([nt][nsrc], source
  * positions out->coords) = F^T d'.  Uses the context's wavefield levels as the

@@ -52,7 +52,7 @@ EXPORTS = (
     "fd_workspace_bytes", "fd_setup", "fd_forward", "fd_get_field", "fd_set_field",
     "fd_stencil_weights", "fd_cfl_dt", "fd_set_option", "fd_destroy", "fd_strerror",
     "fd_last_error", "fd_triad", "fd_checkpoint_bytes", "fd_forward_checkpointed", "fd_gradient",
-    "fd_adjoint", "fd_workspace_bytes_shots", "fd_setup_shots", "fd_forward_shots",
+    "fd_adjoint", "fd_misfit", "fd_workspace_bytes_shots", "fd_setup_shots", "fd_forward_shots",
     "fd_get_shot_field", "fd_set_shot_field", "fd_cnn_packed_elems", "fd_cnn_pack", "fd_cnn_conv",
     "fd_cnn_wgrad_scratch", "fd_cnn_wgrad", "fd_cnn_loss_grad", "fd_cnn_adam", "fd_cnn_features",
     "fd_cnn_correct", "fd_cnn_residual", "fd_restrict",
@@ -122,6 +122,7 @@ def lib() -> ctypes.CDLL:
             "fd_forward_checkpointed": (i32, [vp, i32, pp, pp, i32, vp, ctypes.c_uint64, vp]),
             "fd_gradient": (i32, [vp, i32, pp, pp, i32, vp, ctypes.c_uint64, i32, vp, vp, vp]),
             "fd_adjoint": (i32, [vp, i32, pp, pp, vp]),
+            "fd_misfit": (i32, [vp, vp, ctypes.c_int64, vp, vp, vp]),
             "fd_workspace_bytes_shots": (i32, [gp, i32, i32, u64p]),
             "fd_setup_shots": (i32, [gp, mp, i32, vp, ctypes.c_uint64, i32, vp,
                                      ctypes.POINTER(vp)]),
@@ -290,6 +291,13 @@ def fd_gradient(ctx, nt: int, src_coords, src_data_ptr, adj_coords, adj_data_ptr
                              ctypes.c_void_p(stream))
     del keep_s, keep_a
     _check(code, "fd_gradient", ctx)
+
+
+def fd_misfit(d_ptr, dobs_ptr, n: int, res_ptr, J_ptr, stream: int):
+    code = lib().fd_misfit(ctypes.c_void_p(d_ptr), ctypes.c_void_p(dobs_ptr), int(n),
+                           ctypes.c_void_p(res_ptr), ctypes.c_void_p(J_ptr),
+                           ctypes.c_void_p(stream))
+    _check(code, "fd_misfit", None)
 
 
 def fd_adjoint(ctx, nt: int, adj_coords, adj_data_ptr, out_coords, out_data_ptr, stream: int):

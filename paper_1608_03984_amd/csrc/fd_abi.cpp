@@ -1054,6 +1054,14 @@ int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_poin
     return FD_OK;
 }
 
+int32_t fd_misfit(const float* d, const float* d_obs, int64_t n, float* res, double* J,
+                  void* stream) {
+    if (n < 0 || (n > 0 && (!d || !d_obs || !res || !J))) return FD_ERR_INVALID_ARG;
+    if (n == 0) return FD_OK;
+    const hipError_t e = fd::launch_misfit(d, d_obs, n, res, J, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FD_OK : FD_ERR_DEVICE;
+}
+
 int32_t fd_adjoint(fd_ctx* ctx, int32_t nt, const fd_points* adj, const fd_points* out,
                    void* stream) {
     if (!ctx) return FD_ERR_INVALID_ARG;

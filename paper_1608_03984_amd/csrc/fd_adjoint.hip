@@ -74,6 +74,25 @@ __global__ __launch_bounds__(256) void finish_kernel(const float* __restrict__ g
     }
 }
 
+// res = d - d_obs and J += 1/2 sum res^2.  The sum is taken in FP64: the
+// misfit is what the finite-difference checks of the gradient difference.
+__global__ __launch_bounds__(256) void misfit_kernel(const float* __restrict__ d,
+                                                     const float* __restrict__ dobs, int64_t n,
+                                                     float* res, double* J) {
+    __shared__ double part[4];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+        const float r = d[i] - dobs[i];
+        res[i] = r;
+        acc += 0.5 * (double)r * (double)r;
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(J, (part[0] + part[1]) + (part[2] + part[3]));
+}
+
 dim3 plane_grid(const Layout& L, int& ntx) {
     ntx = (L.nx + kTileX - 1) / kTileX;
     const int nty = (L.ny + kRows - 1) / kRows;
@@ -103,6 +122,15 @@ hipError_t launch_finish_gradient(const float* gsum, const float* A, float* out,
     const dim3 grid = plane_grid(L, ntx);
     hipLaunchKernelGGL(finish_kernel, grid, dim3(256), 0, s, gsum, A, out, L, ntx, (float)dt,
                        (float)(1.0 / (dt * dt)), wrt_vel, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_misfit(const float* d, const float* dobs, int64_t n, float* res, double* J,
+                         hipStream_t s) {
+    int64_t g = (n + 255) / 256;
+    if (g > 1024) g = 1024;  // few blocks: each ends in one atomic on J
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(misfit_kernel, dim3((unsigned)g), dim3(256), 0, s, d, dobs, n, res, J);
     return hipGetLastError();
 }
 

@@ -154,6 +154,9 @@ hipError_t launch_record(const float* u, const SparsePoint* pts, int n, float* o
 
 // adjoint / gradient (FP32, two-level summation)
 // gpart[vol] += mu[vol] * acc[vol] over the interior.
+// res = d - dobs (n values), *J += 1/2 sum res^2 (summed in FP64).
+hipError_t launch_misfit(const float* d, const float* dobs, int64_t n, float* res, double* J,
+                         hipStream_t s);
 hipError_t launch_image(const float* mu, const float* acc, float* gpart, const Layout& L,
                         hipStream_t s);
 // gsum[dense] += gpart[vol]; gpart[vol] = 0 over the interior.

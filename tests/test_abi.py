@@ -129,3 +129,7 @@ def test_gradient_entry_points_reject_null_context():
     assert lib.fd_gradient(None, 10, None, None, 0, None, 0, P.FD_WRT_M, None, None,
                            None) == P.FD_ERR_INVALID_ARG
     assert lib.fd_adjoint(None, 10, None, None, None) == P.FD_ERR_INVALID_ARG
+    # the misfit: missing buffers and negative sizes are rejected, n = 0 is a no-op
+    assert lib.fd_misfit(None, None, 5, None, None, None) == P.FD_ERR_INVALID_ARG
+    assert lib.fd_misfit(None, None, -1, None, None, None) == P.FD_ERR_INVALID_ARG
+    assert lib.fd_misfit(None, None, 0, None, None, None) == P.FD_OK

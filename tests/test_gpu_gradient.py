@@ -156,6 +156,34 @@ def test_gradient_wrt_velocity_and_repeat():
     assert rel(gv1, gref * (-2.0 / v ** 3)) < 2e-4
 
 
+def test_misfit_vs_oracle():
+    """fd_misfit: the residual is the FP32 difference of the traces and the
+    observed data, and J matches the oracle's misfit of the same run."""
+    p = acoustic_problem(3, (60, 20, 24), 5, 8, 50, seed=29)
+    dobs = observed(p)
+    say("case: misfit")
+    s = from_problem(p)
+    tr = s.forward(p.nt, p.src, p.wavelet, p.rec)
+    do = torch.from_numpy(dobs.astype(np.float32)).to(tr.device)
+    res = torch.empty_like(tr)
+    J = torch.zeros(1, dtype=torch.float64, device=tr.device)
+    st = torch.cuda.current_stream().cuda_stream
+    P.fd_misfit(tr.data_ptr(), do.data_ptr(), tr.numel(), res.data_ptr(), J.data_ptr(), st)
+    P.fd_misfit(tr.data_ptr(), do.data_ptr(), tr.numel(), res.data_ptr(), J.data_ptr(), st)
+    torch.cuda.synchronize()
+    got_res, got_J, d = res.cpu().numpy(), float(J.item()) / 2, tr.cpu().numpy()
+    s.close()
+    assert np.array_equal(got_res, d - dobs.astype(np.float32))
+    oracle.set_threads(THREADS)
+    try:
+        Jref = oracle.acoustic_misfit(p.ndim, p.nbl, p.spacing, p.dt, p.so, p.vel, p.eta, p.src,
+                                      p.wavelet, p.rec, dobs, p.nt)
+    finally:
+        oracle.set_threads(1)
+    say(f"  J {got_J:.6e} oracle {Jref:.6e}")
+    assert abs(got_J - Jref) <= 2e-4 * Jref
+
+
 def test_gradient_accumulates_over_shots():
     """FD_GRAD_ACCUMULATE: the gradients of two shots (two source positions)
     summed into one buffer equal the FP32 sum of the separate gradients, and
