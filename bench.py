@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-pass", action="store_true")
     ap.add_argument("--workload",
-                    choices=("acoustic", "tti", "vti", "gradient", "fwi", "shots", "cost",
+                    choices=("acoustic", "2d", "tti", "vti", "gradient", "fwi", "shots", "cost",
                              "learned"),
                     default="acoustic")
     ap.add_argument("--interval", type=int, default=0)
@@ -241,6 +241,61 @@ def tti_bench(args, physics="tti"):
                      "kernel": f"{name} stencil ({nbytes} B per point update)"},
         "gflops_paper": round(nflops * npts / kernel_s / 1e9, 1),
         "stencil_ms": round(kernel_s * 1e3, 4), "finite": ok,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def acoustic2d_bench(args):
+    """The 2D workload (201 x 201 physical + 20-point layer = 241^2 points, so
+    4, 500 steps, one source, 101 receivers): cache-resident and bound by
+    launches (three per step), so the 500-step loop is also captured once in
+    a HIP graph and replayed; both rates are reported (no roofline: the
+    0.9 MB of a step never leaves the caches)."""
+    import torch
+
+    from paper_1608_03984_amd.solver import Solver
+    from workloads import acoustic_2d
+
+    p = acoustic_2d()
+    nt, nrec = p.nt, p.rec.shape[0]
+    dev = torch.device("cuda:0")
+    s = Solver(2, p.shape, p.spacing, p.nbl, p.so, p.dt, p.vel, p.eta, max_points=1 + nrec,
+               device=dev)
+    q = torch.from_numpy(p.wavelet.astype(np.float32)).to(dev)
+    traces = torch.empty((nt, nrec), dtype=torch.float32, device=dev)
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
+    def run():
+        s.forward(nt, p.src, q, p.rec, traces=traces)
+
+    run()
+    reps = 20
+    t_eager = timed(lambda: [run() for _ in range(reps)], ev) / reps
+    ref = traces.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    g.replay()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(traces, ref))
+    t_graph = timed(lambda: [g.replay() for _ in range(reps)], ev) / reps
+    torch.cuda.synchronize()
+    same = same and bool(torch.equal(traces, ref))
+    s.close()
+    npts = p.npoints
+    line = {
+        "metric": "Gpt/s (2D acoustic so4)", "value": round(npts * nt / t_graph / 1e9, 3),
+        "unit": "Gpt/s", "n_gpus": 1, "steps": nt, "warmup": 1,
+        "ms_per_step": round(t_graph / nt * 1e3, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "2D isotropic acoustic, 201^2 + 20-pt layer (241^2 points), "
+                               "h=10 m, v=1500 m/s, so 4, 500 steps, 15 Hz Ricker, 101 receivers",
+                   "points": npts},
+        "eager_gpts": round(npts * nt / t_eager / 1e9, 3),
+        "graph_gpts": round(npts * nt / t_graph / 1e9, 3),
+        "eager_us_per_step": round(t_eager / nt * 1e6, 2),
+        "graph_us_per_step": round(t_graph / nt * 1e6, 2),
+        "graph_traces_equal_eager": same,
     }
     print(json.dumps(line), flush=True)
 
@@ -675,6 +730,9 @@ def main():
         return
     if args.workload == "fwi":
         fwi_bench(args)
+        return
+    if args.workload == "2d":
+        acoustic2d_bench(args)
         return
     if args.workload == "cost":
         cost_bench(args)

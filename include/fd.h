@@ -134,7 +134,11 @@ int32_t fd_setup(const fd_grid* grid, const fd_model* model, void* workspace,
  * spread over the multilinear corners.  flags & FD_ZERO_STATE starts from
  * zero; otherwise the run continues from the held state (fd_set_field or a
  * previous call).  src or rec may be NULL.  Asynchronous on `stream`, except
- * that new point coordinates are uploaded with one synchronisation. */
+ * that new point coordinates are uploaded with one synchronisation.  A call
+ * whose coordinates equal the previous call's launches kernels only, so it
+ * can be captured in a HIP graph; the index of the level holding u^n is host
+ * state that advances at capture time, so replays agree with it when nt is
+ * even (or every run starts from FD_ZERO_STATE and reads only traces). */
 int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_points* rec,
                    int32_t flags, void* stream);
 

@@ -163,6 +163,31 @@ def test_damping_profiles(so):
     assert et < 1e-4 and eu < 1e-4
 
 
+def test_forward_in_a_hip_graph():
+    """A forward run captured once in a HIP graph: every replay, with eager
+    runs and synchronisations between, gives the eager traces and field."""
+    p = acoustic_problem(2, (67, 1, 33), 5, 8, 40, seed=61)
+    say("case: forward captured in a graph")
+    s = from_problem(p)
+    q = torch.from_numpy(p.wavelet.astype(np.float32)).to(s.device)
+    traces = torch.empty((p.nt, p.rec.shape[0]), dtype=torch.float32, device=s.device)
+    s.forward(p.nt, p.src, q, p.rec, traces=traces)
+    torch.cuda.synchronize()
+    ref, uref = traces.clone(), s.get_field(P.FD_FIELD_CUR).clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        s.forward(p.nt, p.src, q, p.rec, traces=traces)
+    for _ in range(3):
+        traces.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(traces, ref)
+        assert torch.equal(s.get_field(P.FD_FIELD_CUR), uref)
+        s.forward(p.nt, p.src, q, p.rec)   # eager work between replays
+        torch.cuda.synchronize()
+    s.close()
+
+
 def test_acoustic_deterministic():
     p = acoustic_problem(3, (100, 30, 30), 6, 8, 50, seed=3)
     say("case: determinism")
