@@ -184,6 +184,45 @@ def test_misfit_vs_oracle():
     assert abs(got_J - Jref) <= 2e-4 * Jref
 
 
+def test_taylor_remainder_is_second_order():
+    """Taylor test of the GPU gradient: R(e) = |J(v + e d) - J(v) - e <g, d>|
+    falls as e^2 (ratio 4 per halving of e), J from fd_misfit of FP32 runs."""
+    p = acoustic_problem(3, (60, 24, 30), 5, 8, 60, seed=31)
+    dobs = torch.from_numpy(observed(p).astype(np.float32))
+    say("case: Taylor test of the gradient")
+    st = torch.cuda.current_stream().cuda_stream
+
+    def J_of(vel, keep=None):
+        s = Solver(3, p.shape, p.spacing, p.nbl, p.so, p.dt, vel, p.eta,
+                   max_points=1 + p.rec.shape[0])
+        if keep is None:
+            tr = s.forward(p.nt, p.src, p.wavelet, p.rec)
+        else:
+            tr = s.forward_checkpointed(p.nt, p.src, p.wavelet, p.rec)
+        J = torch.zeros(1, dtype=torch.float64, device=tr.device)
+        do = dobs.to(tr.device)
+        P.fd_misfit(tr.data_ptr(), do.data_ptr(), tr.numel(), tr.data_ptr(), J.data_ptr(), st)
+        if keep is not None:
+            g, _ = s.gradient(tr, wrt="vel", wavelet_grad=False)
+            keep.append(g.cpu().numpy().astype(np.float64))
+        torch.cuda.synchronize()
+        s.close()
+        return float(J.item())
+
+    keep = []
+    J0 = J_of(p.vel, keep)
+    g = keep[0]
+    d = smooth_random(p.vel.shape, 4.0, np.random.default_rng(7))
+    d = (d / np.abs(d).max()).astype(np.float64)
+    gd = float(np.sum(g * d))
+    R = []
+    for e in (8.0, 4.0, 2.0):
+        Je = J_of((p.vel + e * d).astype(np.float32))
+        R.append(abs(Je - J0 - e * gd))
+    say(f"  J {J0:.4e}  <g,d> {gd:.4e}  remainders {R[0]:.3e} {R[1]:.3e} {R[2]:.3e}")
+    assert 3.0 < R[0] / R[1] < 5.0 and 3.0 < R[1] / R[2] < 5.0
+
+
 def test_gradient_accumulates_over_shots():
     """FD_GRAD_ACCUMULATE: the gradients of two shots (two source positions)
     summed into one buffer equal the FP32 sum of the separate gradients, and
