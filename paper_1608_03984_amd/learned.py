@@ -201,16 +201,13 @@ def make_pair(model, device="cuda", src_radius=6):
                      region, n)
 
 
-def training_pairs(pair, times, K, device="cuda", noise=0.0, seed=0):
+def training_pairs(pair, times, K, device="cuda"):
     """Training samples of one model: for each coarse time m in `times`
     (m >= K), the coarse state at m - K is set from the fine solution sampled
     at the coarse points, the coarse solver runs K steps, and the sample is
     (network input of the result, target = scaled difference to the sampled
-    fine solution at m).  With noise > 0 the coarse state is perturbed by
-    white noise of that size relative to max|u^n| before the sample is taken
-    (the target then includes removing it), which teaches the network to damp
-    perturbations it would otherwise amplify over a long run.  Returns lists
-    of (x0 int16 [V*8], target f32 [V*2])."""
+    fine solution at m).  Returns a list of (x0 int16 [V*8], target f32
+    [V*2], region mask, mask count)."""
     f, c = pair.fine, pair.coarse
     st = lambda: _stream(torch.device(device))
     shape_c = c.field_shape
@@ -236,14 +233,6 @@ def training_pairs(pair, times, K, device="cuda", noise=0.0, seed=0):
         c.set_field(B.FD_FIELD_PREV, snaps[2 * m0 - 2].view(shape_c))
         c.set_field(B.FD_FIELD_CUR, snaps[2 * m0].view(shape_c))
         c.forward(K, pair.src, pair.wav_c[m0:m], None, zero_state=False)
-        if noise > 0:
-            gen = torch.Generator(device=device).manual_seed(seed * 100003 + m)
-            uc = c.get_field(B.FD_FIELD_CUR)
-            amp = noise * float(uc.abs().max())
-            for which in (B.FD_FIELD_CUR, B.FD_FIELD_PREV):
-                u = c.get_field(which)
-                u += amp * torch.randn(u.shape, generator=gen, device=device)
-                c.set_field(which, u)
         x0 = torch.empty(V * 8, dtype=torch.int16, device=device)
         tgt = torch.empty(V * 2, dtype=torch.float32, device=device)
         B.fd_cnn_features(c.ctx, VREF, pair.region.data_ptr(), bits.data_ptr(), x0.data_ptr(),
@@ -251,58 +240,6 @@ def training_pairs(pair, times, K, device="cuda", noise=0.0, seed=0):
         B.fd_cnn_residual(c.ctx, snaps[2 * m].data_ptr(), snaps[2 * m - 2].data_ptr(),
                           bits.data_ptr(), tgt.data_ptr(), st())
         out.append((x0, tgt, pair.region, pair.n_region))
-    torch.cuda.synchronize()
-    return out
-
-
-def rollout_pairs(pair, K, net=None, keep_every=1, device="cuda", start=0):
-    """Training samples along a coarse run from the zero state: every K
-    steps the sample is (network input of the coarse state, target = scaled
-    difference to the fine solution sampled at the coarse points at the same
-    time), after which the network's own correction is applied when `net`
-    is given (so later samples see the states the corrected solver actually
-    reaches), and nothing otherwise.  Every keep_every-th sample is kept;
-    samples and corrections begin at coarse step `start`."""
-    f, c = pair.fine, pair.coarse
-    st = _stream(torch.device(device))
-    shape_c = c.field_shape
-    V = int(np.prod(shape_c))
-    nt_c = pair.nt_c
-    ref_cur = torch.empty(V, dtype=torch.float32, device=device)
-    ref_prev = torch.empty(V, dtype=torch.float32, device=device)
-    bits = torch.zeros(1, dtype=torch.int32, device=device)
-    xin = torch.empty(V * 8, dtype=torch.int16, device=device)
-    if net is not None:
-        net.pack()
-    out = []
-    f.forward(0, zero_state=True)
-    c.forward(0, zero_state=True)
-    done_f = done_c = 0
-    j = 0
-    while done_c + K <= nt_c:
-        m = done_c + K
-        # fine solution at fine steps 2m - 2 and 2m, sampled at the coarse points
-        f.forward(2 * m - 2 - done_f, pair.src, pair.wav_f[done_f:2 * m - 2], None,
-                  zero_state=False)
-        B.fd_restrict(f.ctx, B.FD_FIELD_CUR, 2, ref_prev.data_ptr(), st)
-        f.forward(2, pair.src, pair.wav_f[2 * m - 2:2 * m], None, zero_state=False)
-        B.fd_restrict(f.ctx, B.FD_FIELD_CUR, 2, ref_cur.data_ptr(), st)
-        done_f = 2 * m
-        c.forward(K, pair.src, pair.wav_c[done_c:m], None, zero_state=False)
-        done_c = m
-        if m < start:
-            continue
-        B.fd_cnn_features(c.ctx, VREF, pair.region.data_ptr(), bits.data_ptr(), xin.data_ptr(),
-                          st)
-        j += 1
-        if j % keep_every == 0:
-            tgt = torch.empty(V * 2, dtype=torch.float32, device=device)
-            B.fd_cnn_residual(c.ctx, ref_cur.data_ptr(), ref_prev.data_ptr(), bits.data_ptr(),
-                              tgt.data_ptr(), st)
-            out.append((xin.clone(), tgt, pair.region, pair.n_region))
-        if net is not None:
-            d = net.forward(xin, shape_c)
-            B.fd_cnn_correct(c.ctx, d.data_ptr(), pair.region.data_ptr(), bits.data_ptr(), st)
     torch.cuda.synchronize()
     return out
 

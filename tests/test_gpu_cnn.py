@@ -56,7 +56,8 @@ def st():
 SHAPES = [(3, 5, 70), (4, 9, 33), (2, 4, 130), (37, 6, 70)]
 
 
-@pytest.mark.parametrize("cin,mode", [(8, 0), (8, 1), (16, 0), (16, 1), (8, 2), (16, 2)])
+@pytest.mark.parametrize("cin,mode", [(8, 0), (8, 1), (16, 0), (16, 1), (8, 2), (16, 2), (16, 3),
+                                      (8, 4), (16, 4)])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_conv_vs_oracle(cin, mode, shape):
     rng = np.random.default_rng(cin * 10 + mode + shape[2])
@@ -65,18 +66,19 @@ def test_conv_vs_oracle(cin, mode, shape):
     x = np.zeros(shape + (cin,), np.float32)
     x[..., :creal] = rng.standard_normal(shape + (creal,))
     xb, xv = bf16_bits(x)
-    if mode == 2:
+    back = mode in (2, 4)
+    if back:
         # backward-data: the layer maps 16 -> cin' channels in the forward
         # direction; its transpose takes cin channels (real ones) to 16
         p = layer_params(rng, 16, creal)
     else:
-        p = layer_params(rng, creal, 16 if mode == 0 else 2)
+        p = layer_params(rng, creal, 2 if mode == 1 else 16)
     w = p[:27 * 256].reshape(27, 16, 16)
     wr = C.bf16_round(w)
     say(f"case: conv cin{cin} mode{mode} {shape}")
     pk = torch.empty(P.fd_cnn_packed_elems(cin), dtype=torch.int16, device="cuda")
     pd = dev(p)
-    P.fd_cnn_pack(pd.data_ptr(), cin, 1 if mode == 2 else 0, pk.data_ptr(), st())
+    P.fd_cnn_pack(pd.data_ptr(), cin, 1 if back else 0, pk.data_ptr(), st())
     V = D * H * W
     xd = dev(xb.reshape(-1))
     mask_np = None
@@ -89,8 +91,10 @@ def test_conv_vs_oracle(cin, mode, shape):
     P.fd_cnn_conv(xd.data_ptr(), cin, shape, pk.data_ptr(), pd.data_ptr() + 4 * 27 * 256, mode,
                   md.data_ptr() if mode == 2 else 0, 2, y.data_ptr(), yf.data_ptr(), st())
     torch.cuda.synchronize()
-    if mode == 0:
-        ref = np.maximum(C.conv3d(xv, wr[:, :cin, :], p[27 * 256:27 * 256 + 16]), 0)
+    if mode in (0, 3):
+        ref = C.conv3d(xv, wr[:, :cin, :], p[27 * 256:27 * 256 + 16])
+        if mode == 0:
+            ref = np.maximum(ref, 0)
         got = from_bits(y.cpu().numpy()).reshape(ref.shape)
     elif mode == 1:
         ref = C.conv3d(xv, wr[:, :cin, :2], p[27 * 256:27 * 256 + 2])
@@ -102,7 +106,9 @@ def test_conv_vs_oracle(cin, mode, shape):
     else:
         # input channels of the transpose are the forward layer's outputs
         ref = C.conv3d_backward_data(xv[..., :creal] if cin == 8 else xv, wr[:, :, :creal]
-                                     if cin == 8 else wr) * (mask_np > 0)
+                                     if cin == 8 else wr)
+        if mode == 2:
+            ref = ref * (mask_np > 0)
         got = from_bits(y.cpu().numpy()).reshape(ref.shape)
     # one BF16 unit and a half, plus FP32 accumulation noise near zero
     tol = 1.5 * 2.0 ** -7 * np.abs(ref) + 1e-5 * np.abs(ref).max()
