@@ -395,10 +395,10 @@ int32_t fd_restrict(fd_ctx* ctx, int32_t which, int32_t stride, float* dst, void
  *   field to be a sum of per-axis profiles (sigma(x, y, z) = (s_x + s_y) + s_z
  *   with the profiles taken along the lines through the centre point,
  *   agreeing everywhere to within 2^-20 of the field's maximum, as for the
- *   usual absorbing layer), the tiled 3D acoustic kernel evaluates that sum
- *   instead of reading the field (4 bytes per damped point less traffic);
- *   0 = always read the field.  Other fields, the 2D and the direct kernels
- *   always read the field. */
+ *   usual absorbing layer), the tiled 3D acoustic, VTI and TTI kernels
+ *   evaluate that sum instead of reading the field (4 bytes per damped point
+ *   less traffic); 0 = always read the field.  Other fields, the 2D and the
+ *   direct kernels always read the field. */
 #define FD_OPT_KERNEL 1
 #define FD_OPT_ZCHUNK 2
 #define FD_OPT_TILE 3

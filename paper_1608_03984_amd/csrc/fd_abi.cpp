@@ -832,6 +832,11 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
         p.e = ctx->e;
         p.d = ctx->d;
         for (int k = 0; k < 6; ++k) p.c[k] = ctx->c[k];
+        if (ctx->damping && ctx->sep_ok && ctx->sep_use) {
+            p.sx = ctx->prof;
+            p.sy = ctx->prof + ctx->L.nx;
+            p.sz = ctx->prof + ctx->L.nx + ctx->L.ny;
+        }
         p.L = ctx->L;
         for (int j = 0; j <= fd::kMaxRadius; ++j) {
             p.w2x[j] = ctx->w2[0][j];

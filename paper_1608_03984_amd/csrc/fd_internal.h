@@ -79,6 +79,10 @@ struct TTIStep {
     const float* __restrict__ e;
     const float* __restrict__ d;
     const float* __restrict__ c[6];
+    // separable damping (as in AcousticStep): sig = (sx[x] + sy[y]) + sz[z]
+    const float* __restrict__ sx;
+    const float* __restrict__ sy;
+    const float* __restrict__ sz;
     float w2x[kMaxRadius + 1], w2y[kMaxRadius + 1], w2z[kMaxRadius + 1];  // 2nd-derivative / h^2
     float w1x[kMaxRadius + 1], w1y[kMaxRadius + 1], w1z[kMaxRadius + 1];  // 1st-derivative / h
     Layout L;

@@ -116,7 +116,8 @@ __global__ __launch_bounds__(256) void tti_direct(TTIStep p) {
 // accesses with out-of-range offsets for ghost points, and the 2R steps
 // before a chunk only fill the pipeline (their stores have a zero record
 // limit).  Two barriers per step: one after staging p and r, one after
-// staging gy.
+// staging gy.  A damping layer that is a sum of per-axis profiles (SEP) is
+// evaluated from the three profile values instead of read.
 // ---------------------------------------------------------------------------
 typedef const __attribute__((address_space(4))) int32_t tflag_t;
 constexpr uint32_t kOOBt = 0x80000000u;
@@ -134,7 +135,7 @@ __device__ __forceinline__ void tstore(__amdgpu_buffer_rsrc_t r, uint32_t off, f
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, kNT);
 }
 
-template <int R, int NW>
+template <int R, int NW, bool SEP>
 struct TiledTTI {
     static constexpr int TY = NW;
     static constexpr int LW = kTileX + 2 * R;
@@ -171,6 +172,9 @@ struct TiledTTI {
     float hp_c[2], hr_c[2], hp_h[2][NH], hr_h[2][NH], c1h[2], c2h[2], c4h[2];
     float opp[2], orp[2], oa[2], oe[2], od[2], oc3[2], oc5[2], oc6[2], osg[2];
     int damp[2];
+    float sxl;  // SEP: this lane's x profile value, its row's y value
+    float syl;
+    const __attribute__((address_space(4))) float* szc;
 
     __device__ TiledTTI(const TTIStep& ps, float* lds) : p(ps) {
         fp_t = lds;
@@ -212,7 +216,10 @@ struct TiledTTI {
         const int d = (out && flagbuf != 0) ? 1 : 0;
         flagbuf = flag_of(zc + 1);
         damp[S] = d;
-        osg[S] = tload(trsrc(d ? sb + zo : zpl), oc);
+        if constexpr (SEP)
+            osg[S] = d ? szc[zc] : 0.f;  // the z value; the sum is formed at use
+        else
+            osg[S] = tload(trsrc(d ? sb + zo : zpl), oc);
     }
 
     template <int K>
@@ -312,7 +319,8 @@ struct TiledTTI {
         float pn = (2.f * pc - opp[S]) + fpv;
         float rn = (2.f * rc - orp[S]) + frv;
         if (damp[S]) {
-            const float sv = osg[S];
+            // the profile sum in the same order as the setup's check
+            const float sv = SEP ? (sxl + syl) + osg[S] : osg[S];
             pn = (2.f * pc - (1.f - sv) * opp[S] + fpv) / (1.f + sv);
             rn = (2.f * rc - (1.f - sv) * orp[S] + frv) / (1.f + sv);
         }
@@ -362,6 +370,14 @@ struct TiledTTI {
         for (int k = 0; k < 6; ++k) cb[k] = p.c[k] + org;
         zpl = p.A + org - (int64_t)kGhostYZ * plane;
         flags = (tflag_t*)p.dflag;
+        sxl = syl = 0.f;
+        if constexpr (SEP) {
+            // lanes and rows past the interior read the last value (their
+            // stores drop)
+            szc = (const __attribute__((address_space(4))) float*)p.sz;
+            sxl = p.sx[min(x0 + lane, nx - 1)];
+            syl = p.sy[min(y0 + w, ny - 1)];
+        }
         auto off = [&](int r, int c) -> uint32_t {
             const int y = y0 - R + r, x = x0 - R + c;
             return (x >= 0 && x < nx && y >= 0 && y < ny) ? (uint32_t)((r * pitch + c) * 4) : kOOBt;
@@ -405,16 +421,19 @@ struct TiledTTI {
     }
 };
 
-template <int R, int NW>
+template <int R, int NW, bool SEP>
 __global__ __launch_bounds__(64 * NW) void tti3d_tiled(TTIStep p) {
-    __shared__ float lds[TiledTTI<R, NW>::LDS_FLOATS];
-    TiledTTI<R, NW> k(p, lds);
+    __shared__ float lds[TiledTTI<R, NW, SEP>::LDS_FLOATS];
+    TiledTTI<R, NW, SEP> k(p, lds);
     k.run();
 }
 
 template <int R>
 hipError_t launch_tiled(const TTIStep& p, hipStream_t s) {
-    hipLaunchKernelGGL((tti3d_tiled<R, 8>), dim3(p.nblocks), dim3(512), 0, s, p);
+    if (p.sx)
+        hipLaunchKernelGGL((tti3d_tiled<R, 8, true>), dim3(p.nblocks), dim3(512), 0, s, p);
+    else
+        hipLaunchKernelGGL((tti3d_tiled<R, 8, false>), dim3(p.nblocks), dim3(512), 0, s, p);
     return hipGetLastError();
 }
 
