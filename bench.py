@@ -300,14 +300,27 @@ def acoustic2d_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def gradient_bytes(nt, I):
+    """Algorithmic bytes per point of a checkpointed forward run plus its
+    gradient (nt steps, checkpoint interval I): forward 16 per step (the last
+    segment also stores its accelerations, 4 more); the other segments
+    recomputed storing the accelerations, 20; adjoint steps 16 with the
+    imaging term fused in, 12 more (acceleration and partial sum read, partial
+    sum written), except one term per segment imaged by the separate kernel,
+    16 (adjoint field read as well); 16 per flush of the partial sums into the
+    total (every 32 terms)."""
+    last = nt - (nt - 1) // I * I           # steps of the last segment (not recomputed)
+    nseg = (nt + I - 1) // I
+    flushes = (nt + 31) // 32
+    return (16 * nt + 4 * last + 20 * (nt - last) + 16 * nt + 12 * (nt - nseg) + 16 * nseg
+            + 16 * flushes)
+
+
 def gradient_bench(args):
     """FWI gradient of the 3D acoustic workload (so 8, 592^3 points, 1 shot):
     checkpointed forward run of ``--steps`` steps, then the adjoint run with
-    segment recomputation and the imaging condition.  Algorithmic bytes per
-    point and step: forward 16, recomputed forward 16 + 4 (acceleration
-    stored), adjoint 16, imaging 16 (adjoint field and acceleration read,
-    FP32 partial sum read and written), plus 16 per point for each flush of
-    the partial sums into the total (every 32 steps)."""
+    segment recomputation and the imaging condition (fused into the adjoint
+    steps).  Algorithmic bytes: gradient_bytes()."""
     import torch
 
     from paper_1608_03984_amd.solver import Solver
@@ -341,9 +354,7 @@ def gradient_bench(args):
     nt = args.steps
     t_all = r["t_fwd"] + r["t_grad"]
     I = r["interval"]
-    last = nt - (nt - 1) // I * I           # steps of the last segment (not recomputed)
-    flushes = (nt + 31) // 32
-    alg = npts * (16 * nt + 4 * last + 20 * (nt - last) + 16 * nt + 16 * nt + 16 * flushes)
+    alg = npts * gradient_bytes(nt, I)
     ach = alg / t_all / 1e9
     s.close()
     line = {
@@ -455,9 +466,7 @@ def fwi_bench(args):
     fd = (Jp - Jm) / (2 * eps)
     say(f"# J {J0:.6e}, central difference {fd:.6e} vs <g, dir> {gd:.6e} (eps {eps:.3e} m/s)")
     I = info["interval"]
-    last = nt - (nt - 1) // I * I
-    flushes = (nt + 31) // 32
-    alg = S * npts * (16 * nt + 4 * last + 20 * (nt - last) + 16 * nt + 16 * nt + 16 * flushes)
+    alg = S * npts * gradient_bytes(nt, I)
     ach = alg / t_grad / 1e9
     line = {
         "metric": "FWI gradient Gpt/s (3D acoustic so8, 16-shot survey)",

@@ -404,6 +404,11 @@ int32_t fd_restrict(fd_ctx* ctx, int32_t which, int32_t stride, float* dst, void
 #define FD_OPT_TILE 3
 #define FD_OPT_SHOTS_PER_BLOCK 4
 #define FD_OPT_DAMPING_PROFILE 5
+/* FD_OPT_FUSED_IMAGING: 1 (default) = fd_gradient adds the imaging term
+ * inside the adjoint stencil launch (tiled 3D kernel with the default 64 x 8
+ * tile: one read of the adjoint field less per point and step); 0 = a
+ * separate imaging launch per step.  Both give the same bits. */
+#define FD_OPT_FUSED_IMAGING 6
 int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value);
 
 /* Frees the host context (not the workspace). NULL is accepted. */

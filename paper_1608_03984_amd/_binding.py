@@ -36,6 +36,7 @@ FD_OPT_ZCHUNK = 2
 FD_OPT_TILE = 3
 FD_OPT_SHOTS_PER_BLOCK = 4
 FD_OPT_DAMPING_PROFILE = 5
+FD_OPT_FUSED_IMAGING = 6
 
 FD_WRT_M = 0
 FD_WRT_VEL = 1

@@ -42,6 +42,7 @@ struct fd_ctx {
     float* prof;      // damping profiles sx[nx], sy[ny], sz[nz] (3D)
     bool sep_ok;      // the damping field is (sx + sy) + sz to within 2^-20 of its maximum
     bool sep_use;     // FD_OPT_DAMPING_PROFILE
+    bool fuse_image;  // FD_OPT_FUSED_IMAGING
     SparsePoint* pts;
     int cur;  // index of the level holding u^n in u[]/r[]
     // derived stencil coefficients (float, already divided by h or h^2)
@@ -594,6 +595,7 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
     ctx->ck_last_acc = false;
     ctx->sep_ok = false;
     ctx->sep_use = true;
+    ctx->fuse_image = true;
     plan_workspace(grid, L, nshots, max_points, ctx, static_cast<char*>(workspace));
     hipStream_t s = static_cast<hipStream_t>(stream);
 
@@ -701,6 +703,11 @@ int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value) {
             ctx->flags_stale = true;  // rebuilt on the caller's stream by fd_forward
             return FD_OK;
         }
+        case FD_OPT_FUSED_IMAGING:
+            if (value != 0 && value != 1)
+                return fail(ctx, FD_ERR_INVALID_ARG, "fused imaging option 0 or 1");
+            ctx->fuse_image = value == 1;
+            return FD_OK;
         case FD_OPT_DAMPING_PROFILE:
             if (value != 0 && value != 1)
                 return fail(ctx, FD_ERR_INVALID_ARG, "damping profile option 0 or 1");
@@ -1029,7 +1036,21 @@ int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_poin
     if (he == hipSuccess) he = fd::launch_fill_zero(st.gpart, ctx->L.volume, s);
     if (he == hipSuccess) he = fd::launch_fill_zero(st.gsum, st.dense, s);
     int pending = 0;  // adjoint steps accumulated in gpart since the last flush
+    auto imaged = [&]() -> hipError_t {  // one more term in gpart: flush every kFlushSteps
+        if (++pending < kFlushSteps) return hipSuccess;
+        pending = 0;
+        return fd::launch_flush_gradient(st.gpart, st.gsum, ctx->L, s);
+    };
     fd::AcousticStep p = acoustic_params(ctx);
+    // The imaging term mu^{k+1} a^{k+1} is fused into the adjoint step that
+    // produces mu^k (its centre field is mu^{k+1}) on the tiled 64 x 8 kernel;
+    // the first step of a segment has no a^{k+1} in the segment, so the
+    // segment's last term, mu^{n0+1} a^{n0+1}, is imaged by the separate
+    // kernel before the next segment's recomputation overwrites the slots.
+    // The terms enter gpart in the same order and with the same fmaf as the
+    // unfused loop, so both give the same bits.
+    const bool fuse = ctx->fuse_image && ctx->g.ndim == 3 && ctx->variant == 0 &&
+                      ctx->tile_cfg == 0;
     int m = 0;  // st.mu[m] holds mu^{k+1}, st.mu[1-m] mu^{k+2}
     for (int j = st.nck - 1; j >= 0 && he == hipSuccess; --j) {
         const int n0 = j * I, n1 = n0 + I < nt ? n0 + I : nt;
@@ -1040,14 +1061,24 @@ int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_poin
                 he = forward_segment(ctx, p, &st, n0, n1, src, nsrc, nullptr, 0, s);
         }
         for (int k = n1; k > n0 && he == hipSuccess; --k) {
+            const bool fused = fuse && k < n1;
+            if (fused) {
+                p.img_a = st.slot(ctx, k - n0);  // a^{k+1}
+                p.img_g = st.gpart;
+            }
             he = adjoint_step(ctx, p, st.mu[m], st.mu[1 - m], k, nsrc, wavelet_grad, adj, nadj, s);
-            if (he == hipSuccess)
+            p.img_a = nullptr;
+            p.img_g = nullptr;
+            if (he == hipSuccess && fused) he = imaged();  // mu^{k+1} a^{k+1}
+            if (he == hipSuccess && !fuse) {
                 he = fd::launch_image(st.mu[1 - m], st.slot(ctx, k - 1 - n0), st.gpart, ctx->L, s);
-            if (he == hipSuccess && ++pending == kFlushSteps) {
-                he = fd::launch_flush_gradient(st.gpart, st.gsum, ctx->L, s);
-                pending = 0;
+                if (he == hipSuccess) he = imaged();
             }
             m = 1 - m;
+        }
+        if (he == hipSuccess && fuse && n1 > n0) {  // mu^{n0+1} a^{n0+1}
+            he = fd::launch_image(st.mu[m], st.slot(ctx, 0), st.gpart, ctx->L, s);
+            if (he == hipSuccess) he = imaged();
         }
     }
     ctx->ck_last_acc = false;  // the segment slots now hold the first segment

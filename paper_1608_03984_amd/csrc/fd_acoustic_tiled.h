@@ -83,9 +83,10 @@ constexpr uint32_t kOOB = 0x80000000u;  // any offset at or past the record limi
 constexpr int kRecords = 0x7fffffff;
 
 
-template <int R, int NW, int VY, int SB, bool ACC, bool SEP>
+template <int R, int NW, int VY, int SB, bool ACC, bool SEP, bool IMG>
 struct TiledAcoustic {
     static_assert(!ACC || SB == 1, "acceleration output is single-shot");
+    static_assert(!IMG || (SB == 1 && !ACC), "fused imaging is a single-shot adjoint step");
     static constexpr int TY = NW * VY;
     static constexpr int LW = kTileX + 2 * R;
     static constexpr int LH = TY + 2 * R + 1;  // last row: sink for idle halo lanes
@@ -102,6 +103,9 @@ struct TiledAcoustic {
     float* pb[SB];        // same for u^{n-1} / u^{n+1}
     int lim[SB];          // store record limit: 0 for the padding shots of a ragged group
     float* cb;            // same for the acceleration output (ACC)
+    const float* iab;     // IMG: the acceleration the output point's u^n images with
+    float* igb;           // IMG: the FP32 partial sum of the imaging condition
+    float ia[2][VY], ig[2][VY];
     const float* ab;      // same for A (shared by the shots)
     const float* sb;      // same for the damping coefficient
     const float* zpl;     // an all-zero plane (ghost plane of A) at the tile origin
@@ -167,6 +171,14 @@ struct TiledAcoustic {
                 prv[S][s][v] = bload<kBufNT>(rp, oc[v]);
             }
             aa[S][v] = bload<kBufNT>(ra, oc[v]);
+        }
+        if constexpr (IMG) {
+            const auto ri = rsrc(out ? iab + zo : zpl), rg = rsrc(out ? igb + zo : zpl);
+#pragma unroll
+            for (int v = 0; v < VY; ++v) {
+                ia[S][v] = bload<kBufNT>(ri, oc[v]);
+                ig[S][v] = bload<kBufNT>(rg, oc[v]);
+            }
         }
         const int d = (out && flagbuf != 0) ? 1 : 0;
         flagbuf = flag_of(zc + 1);
@@ -254,6 +266,14 @@ struct TiledAcoustic {
 #pragma unroll
                 for (int v = 0; v < VY; ++v) bstore_nt(rc, oc[v], av[v]);
             }
+            if constexpr (IMG) {
+                // the same fmaf as the separate imaging kernel
+                const auto rg = __builtin_amdgcn_make_buffer_rsrc(
+                    igb + (int64_t)z * plane, 0, z >= z0 ? kRecords : 0, 0x00020000);
+#pragma unroll
+                for (int v = 0; v < VY; ++v)
+                    bstore_nt(rg, oc[v], fmaf(q[s][C][v], ia[S][v], ig[S][v]));
+            }
         }
         fetch<S>(z + 2);
         return true;
@@ -297,6 +317,8 @@ struct TiledAcoustic {
             lim[s] = shot < p.nshots ? kRecords : 0;
         }
         cb = ACC ? p.acc + org : pb[0];
+        iab = IMG ? p.img_a + org : ab;
+        igb = IMG ? p.img_g + org : pb[0];
         ab = p.A + org;
         sb = (p.sig ? p.sig : p.A) + org;
         zpl = p.A + org - (int64_t)kGhostYZ * plane;
@@ -364,9 +386,9 @@ struct TiledAcoustic {
     }
 };
 
-template <int R, int NW, int VY, int SB, bool ACC, bool SEP>
+template <int R, int NW, int VY, int SB, bool ACC, bool SEP, bool IMG>
 __global__ __launch_bounds__(64 * NW) void acoustic3d_tiled(AcousticStep p) {
-    using T = TiledAcoustic<R, NW, VY, SB, ACC, SEP>;
+    using T = TiledAcoustic<R, NW, VY, SB, ACC, SEP, IMG>;
     __shared__ float lds[T::SMEM_FLOATS];
     T k(p, lds);
     k.run();
@@ -376,12 +398,22 @@ template <int R, int NW, int VY, int SB, bool SEP>
 hipError_t launch_tiled_sep(const AcousticStep& p, hipStream_t s) {
     if constexpr (SB == 1) {
         if (p.acc) {
-            hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, 1, true, SEP>), dim3(p.nblocks),
-                               dim3(64 * NW), 0, s, p);
+            hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, 1, true, SEP, false>),
+                               dim3(p.nblocks), dim3(64 * NW), 0, s, p);
             return hipGetLastError();
         }
+        if (p.img_a) {
+            // built for the default 64 x 8 tile only (the caller checks)
+            if constexpr (NW == 4 && VY == 2) {
+                hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, 1, false, SEP, true>),
+                                   dim3(p.nblocks), dim3(64 * NW), 0, s, p);
+                return hipGetLastError();
+            }
+            return hipErrorInvalidValue;
+        }
     }
-    hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, SB, false, SEP>), dim3(p.nblocks),
+    if (p.img_a) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, SB, false, SEP, false>), dim3(p.nblocks),
                        dim3(64 * NW), 0, s, p);
     return hipGetLastError();
 }

@@ -184,6 +184,27 @@ def test_misfit_vs_oracle():
     assert abs(got_J - Jref) <= 2e-4 * Jref
 
 
+@pytest.mark.parametrize("interval", [0, 7, 1])
+def test_fused_imaging_gives_the_same_bits(interval):
+    """The imaging term fused into the adjoint stencil launch and the separate
+    imaging kernel give bitwise equal gradients (same terms, same order, same
+    fmaf), for several checkpoint intervals (1: every segment one step)."""
+    p = with_sources(acoustic_problem(3, (75, 30, 34), 6, 8, 50, seed=77), nsrc=2)
+    dobs = observed(p)
+    say(f"case: fused imaging, interval {interval}")
+    out = []
+    for fused in (1, 0):
+        s = from_problem(p)
+        s.set_option(P.FD_OPT_FUSED_IMAGING, fused)
+        tr = s.forward_checkpointed(p.nt, p.src, p.wavelet, p.rec, interval=interval)
+        res = tr - torch.from_numpy(dobs.astype(np.float32)).to(tr.device)
+        g, qg = s.gradient(res, wrt="m")
+        out.append((g.cpu().numpy(), qg.cpu().numpy()))
+        torch.cuda.synchronize()
+        s.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
 def test_taylor_remainder_is_second_order():
     """Taylor test of the GPU gradient: R(e) = |J(v + e d) - J(v) - e <g, d>|
     falls as e^2 (ratio 4 per halving of e), J from fd_misfit of FP32 runs."""
