@@ -1,0 +1,117 @@
+"""Invariants of the method checked on the GPU itself (libfd through its C
+ABI), where the expected values come from closed forms or symmetry rather
+than from the oracle's run:
+
+  * an exact discrete plane wave of the scheme stays one, to FP32 rounding,
+    wherever the zero walls have not reached (the dispersion relation of the
+    scheme with the oracle's closed-form weights);
+  * a source on the mirror plane of an x-symmetric model gives bitwise
+    mirror-symmetric traces and fields;
+  * TTI with epsilon = delta = 0 (any tilt) is the acoustic equation: its p
+    traces equal the acoustic kernel's.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+import paper_1608_03984_amd as P  # noqa: E402
+from paper_1608_03984_amd.solver import Solver  # noqa: E402
+from tests._gpu_util import rel, say, tti_problem  # noqa: E402
+from workloads import damping_profile, ricker  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _symbol(w, theta):
+    """W(theta) = w0 + 2 sum_j w_j cos(j theta) of the second-derivative stencil."""
+    return w[0] + 2.0 * sum(w[j] * np.cos(j * theta) for j in range(1, len(w)))
+
+
+@pytest.mark.parametrize("so", [4, 8, 16])
+def test_plane_wave_on_gpu(so):
+    r = so // 2
+    w = oracle.weights_d2(so)
+    v = 2000.0
+    shape = (40, 38, 42)                   # [nz][ny][nx]
+    h = (10.0, 12.0, 8.0)                  # (x, y, z)
+    k = np.array([2 * np.pi / (7.1 * h[0]), 2 * np.pi / (11.3 * h[1]), -2 * np.pi / (8.9 * h[2])])
+    nsteps = max(1, 12 // r)
+    dt = 0.8 * oracle.cfl_dt(3, so, h, v)
+    X2 = sum(-_symbol(w, k[a] * h[a]) / h[a] ** 2 for a in range(3))
+    om = 2.0 / dt * np.arcsin(0.5 * v * dt * np.sqrt(X2))
+    z, y, x = np.meshgrid(np.arange(shape[0]) * h[2], np.arange(shape[1]) * h[1],
+                          np.arange(shape[2]) * h[0], indexing="ij")
+    phase = k[0] * x + k[1] * y + k[2] * z
+    say(f"case: plane wave on the GPU so{so}, {nsteps} steps")
+    s = Solver(3, (shape[2], shape[1], shape[0]), h, 0, so, dt,
+               np.full(shape, v, dtype=np.float32), None, max_points=1)
+    s.set_field(P.FD_FIELD_PREV, torch.from_numpy(np.cos(phase + om * dt).astype(np.float32)))
+    s.set_field(P.FD_FIELD_CUR, torch.from_numpy(np.cos(phase).astype(np.float32)))
+    s.forward(nsteps, zero_state=False)
+    u = s.get_field(P.FD_FIELD_CUR).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    s.close()
+    exact = np.cos(phase - nsteps * om * dt)
+    d = nsteps * r
+    sl = tuple(slice(d, n - d) for n in shape)
+    err = np.max(np.abs(u[sl] - exact[sl]))
+    say(f"  interior max error {err:.2e} (amplitude 1)")
+    assert exact[sl].size > 100 and err < 5e-6
+    assert np.max(np.abs(u - exact)) > 1e-3   # the walls did act outside
+
+
+def test_mirror_symmetry_on_gpu():
+    """x-symmetric layered model with its damping layer, source on the mirror
+    plane, receivers in mirrored pairs."""
+    nx, ny, nz, nbl, so = 101, 33, 41, 8, 8
+    h = (10.0, 10.0, 10.0)
+    pad = (nz + 2 * nbl, ny + 2 * nbl, nx + 2 * nbl)
+    zz = np.arange(pad[0])[:, None, None]
+    yy = np.arange(pad[1])[None, :, None]
+    vel = (1500.0 + 20.0 * zz + 5.0 * np.abs(yy - pad[1] // 2) + 0.0 * np.arange(pad[2])
+           ).astype(np.float32)
+    eta = damping_profile(pad, nbl, h, float(vel.max()))
+    dt = 0.4 * oracle.cfl_dt(3, so, h, float(vel.max()))
+    nt = 90
+    q = ricker(12.0, dt, nt)[:, None].astype(np.float32)
+    xc = (nx - 1) / 2 * h[0]
+    src = np.array([[xc, (ny - 1) / 2 * h[1], 150.0]])
+    offs = np.array([0.0, 30.0, 70.0, 140.0, 310.0])
+    rec = np.array([[xc + sgn * o, 160.0, 20.0] for o in offs for sgn in (1, -1)])
+    say("case: mirror symmetry on the GPU")
+    s = Solver(3, (nx, ny, nz), h, nbl, so, dt, vel, eta, max_points=1 + len(rec))
+    tr = s.forward(nt, src, q, rec).cpu().numpy()
+    u = s.get_field(P.FD_FIELD_CUR).cpu().numpy()
+    torch.cuda.synchronize()
+    s.close()
+    e_tr = rel(tr[:, 0::2], tr[:, 1::2])
+    e_u = rel(u, u[:, :, ::-1])
+    say(f"  mirrored traces {e_tr:.2e}, mirrored field {e_u:.2e} "
+        f"(bitwise: {np.array_equal(u, u[:, :, ::-1])})")
+    # symmetric pairs are summed before they are weighted, so mirrored points
+    # do the same arithmetic on mirrored data: the symmetry is exact
+    assert np.abs(tr).max() > 0
+    assert np.array_equal(tr[:, 0::2], tr[:, 1::2]) and np.array_equal(u, u[:, :, ::-1])
+
+
+def test_tti_reduces_to_acoustic_on_gpu():
+    """epsilon = delta = 0 with tilted axes: the TTI kernel's p equals the
+    acoustic kernel's u (source into p and r, so p = r throughout)."""
+    p = tti_problem((70, 30, 34), 6, 8, 60, seed=811)
+    zeros = np.zeros_like(p.eps)
+    say("case: TTI with epsilon = delta = 0 against acoustic, on the GPU")
+    st = Solver(3, p.shape, p.spacing, p.nbl, p.so, p.dt, p.vel, p.eta, physics="tti",
+                epsilon=zeros, delta=zeros, theta=p.theta, phi=p.phi,
+                max_points=1 + len(p.rec))
+    tt = st.forward(p.nt, p.src, p.wavelet, p.rec).cpu().numpy()
+    st.close()
+    sa = Solver(3, p.shape, p.spacing, p.nbl, p.so, p.dt, p.vel, p.eta,
+                max_points=1 + len(p.rec))
+    ta = sa.forward(p.nt, p.src, p.wavelet, p.rec).cpu().numpy()
+    torch.cuda.synchronize()
+    sa.close()
+    e = rel(tt, ta)
+    say(f"  TTI p traces vs acoustic: {e:.2e}")
+    assert np.abs(ta).max() > 0 and e < 1e-5
