@@ -1,0 +1,31 @@
+"""The benchmark's command line without a GPU: more than one GPU is refused
+with a message and a non-zero status (the solver has no multi-GPU path), and
+the gradient byte count that the gradient benches report against matches its
+terms."""
+import json
+import subprocess
+import sys
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, str(ROOT / "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
+
+
+def test_gradient_bytes_terms():
+    sys.path.insert(0, str(ROOT))
+    import bench
+    # one segment (interval >= nt): forward 16 + 4 (its accelerations), no
+    # recomputation, adjoint 16, one separately imaged term 16 and nt - 1
+    # fused ones 12, flushes 16 every 32 terms
+    nt = 64
+    assert bench.gradient_bytes(nt, nt) == 16 * nt + 4 * nt + 16 * nt + 12 * (nt - 1) + 16 + 16 * 2
+    # interval 1: every step its own segment, none fused; the last segment's
+    # single step is not recomputed
+    assert bench.gradient_bytes(10, 1) == 16 * 10 + 4 + 20 * 9 + 16 * 10 + 16 * 10 + 16
