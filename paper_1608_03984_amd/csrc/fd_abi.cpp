@@ -145,6 +145,14 @@ int32_t validate_grid(const fd_grid* g, std::string& msg) {
         if (g->shape[a] < 1 || g->shape[a] > (1 << 20))
             return msg = "shape out of range", FD_ERR_INVALID_ARG;
     if (g->ndim == 2 && g->shape[1] != 1) return msg = "2D grids need shape[1] == 1", FD_ERR_INVALID_ARG;
+    {
+        // the padded array must stay far from 64-bit byte-count overflow in the
+        // workspace plan (2^40 points, 4 TiB per field, is far beyond one GPU)
+        const double pad = 2.0 * g->nbl;
+        const double pts = (g->shape[0] + pad) * (g->ndim == 3 ? g->shape[1] + pad : 1.0) *
+                           (g->shape[2] + pad);
+        if (pts > 1099511627776.0) return msg = "grid too large", FD_ERR_INVALID_ARG;
+    }
     for (int a = 0; a < 3; ++a) {
         if (g->ndim == 2 && a == 1) continue;
         if (!(g->spacing[a] > 0.0) || !std::isfinite(g->spacing[a]))

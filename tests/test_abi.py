@@ -88,6 +88,11 @@ def test_workspace_validation_codes():
         (P.make_grid(3, (0, 8, 8), (1, 1, 1), 0, 4, 1e-3), P.FD_ERR_INVALID_ARG),
         (P.make_grid(3, (8, 8, 8), (1, 1, 1), -1, 4, 1e-3), P.FD_ERR_INVALID_ARG),
         (P.make_grid(3, (8, 8, 8), (1, 1, 1), 0, 4, 1e-3, 7), P.FD_ERR_INVALID_ARG),
+        # beyond 2^40 padded points (byte counts would approach 64-bit overflow)
+        (P.make_grid(3, (1 << 20, 1 << 20, 1 << 20), (1, 1, 1), 0, 4, 1e-3),
+         P.FD_ERR_INVALID_ARG),
+        (P.make_grid(3, (1 << 14, 1 << 14, 1 << 13), (1, 1, 1), 0, 4, 1e-3),
+         P.FD_ERR_INVALID_ARG),
     ]
     for g, code in bad:
         assert _code(lambda: P.fd_workspace_bytes(g, 1)) == code
