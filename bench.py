@@ -665,7 +665,7 @@ def learned_bench(args):
     for seed in (900, 901, 902):
         m = learned_model(seed)
         pair = Lm.make_pair(m)
-        far = Lm.far_receivers(pair, 6 * m["h_c"][0])
+        far = Lm.far_receivers(pair, Lm.SRC_RADIUS * m["h_c"][0])
         held = Lm.training_pairs(pair, times, K)
         win = (Lm.sample_loss(None, held, shape_c), Lm.sample_loss(net, held, shape_c))
         del held

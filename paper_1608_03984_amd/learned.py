@@ -188,7 +188,10 @@ def region_mask(field_shape, nbl, spacing, src, src_radius, device="cuda"):
     return t, int(m.sum())
 
 
-def make_pair(model, device="cuda", src_radius=6):
+SRC_RADIUS = 4       # coarse points of the source ball left out of the correction
+
+
+def make_pair(model, device="cuda", src_radius=SRC_RADIUS):
     """Solvers for a workloads.learned_model() dictionary."""
     m = model
     fine = Solver(3, m["shape_f"], m["h_f"], m["nbl_f"], m["so_f"], m["dt_f"], m["vel_f"],
@@ -280,7 +283,7 @@ def sample_loss(net, samples, shape_c):
     return tot / max(len(samples), 1)
 
 
-def correction_start(model, src_radius=6, periods=2.0, f0=10.0, vmin=1500.0):
+def correction_start(model, src_radius=SRC_RADIUS, periods=1.0, f0=10.0, vmin=1500.0):
     """First coarse step at which corrections apply: after the source wavelet
     (`periods` / f0) and the travel time out of the excluded source ball."""
     t = periods / f0 + src_radius * model["h_c"][0] / vmin
