@@ -341,10 +341,18 @@ void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, int ng
     if (zc > L.nz) zc = L.nz;
     const int nzc = (L.nz + zc - 1) / zc;
     const int ntiles = ntx * nty * nzc;
-    const int nblocks = (int)round_up((int64_t)ntiles * ngroups, 8);
+    int nblocks = (int)round_up((int64_t)ntiles * ngroups, 8);
+    // Several shot groups give many more blocks than the chip holds: order
+    // them by pass (z chunk, group), every pass spread over the 8 XCDs in
+    // x-y slabs, so that the blocks running together are whole x-y planes of
+    // tiles started at the same time (neighbours share halo rows in L2) and
+    // consecutive groups of one chunk read the same A planes together.
+    const int slab = ngroups > 1 ? (ntx * nty + 7) / 8 : 0;
+    if (slab > 0) nblocks = 8 * slab * nzc * ngroups;
     if (a) {
         a->ntx = ntx; a->nty = nty; a->nzc = nzc; a->zchunk = zc;
         a->ntiles = ntiles; a->nblocks = nblocks; a->ngroups = ngroups;
+        a->slab = slab;
     }
     if (t) {
         t->ntx = ntx; t->nty = nty; t->nzc = nzc; t->zchunk = zc;

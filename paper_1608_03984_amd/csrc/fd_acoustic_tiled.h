@@ -286,9 +286,21 @@ struct TiledAcoustic {
 
     __device__ void run() {
         const int b = blockIdx.x;
-        const int item = (b & 7) * (p.nblocks >> 3) + (b >> 3);
-        if (item >= p.ntiles * p.ngroups) return;
-        const int t = item % p.ntiles, group = item / p.ntiles;
+        int t, group;
+        if (p.slab > 0) {
+            // pass-major: XCD b & 7 takes tiles [(b & 7) slab, (b & 7 + 1) slab)
+            // of pass (b >> 3) / slab; groups vary fastest over the passes
+            const int j = b >> 3, pass = j / p.slab;
+            const int txy = (b & 7) * p.slab + j % p.slab;
+            if (txy >= p.ntx * p.nty) return;
+            group = pass % p.ngroups;
+            t = txy + (pass / p.ngroups) * (p.ntx * p.nty);
+        } else {
+            const int item = (b & 7) * (p.nblocks >> 3) + (b >> 3);
+            if (item >= p.ntiles * p.ngroups) return;
+            t = item % p.ntiles;
+            group = item / p.ntiles;
+        }
         ntx = p.ntx;
         nty = p.nty;
         tx = t % ntx;

@@ -67,6 +67,10 @@ struct AcousticStep {
     int32_t ntx, nty, nzc, zchunk;  // tile grid (tiled kernels)
     int32_t ntiles, nblocks;        // ntx*nty*nzc and the launched (multiple of 8) count
     int32_t nshots, ngroups;        // wavefields advanced together; groups of shots per block
+    // > 0: pass-major block order (several shot groups): a pass is one
+    // (z chunk, shot group) over all x-y tiles, each XCD takes `slab`
+    // consecutive x-y tiles of every pass, and passes run in order
+    int32_t slab;
     int64_t shot_stride;            // floats between the volumes of consecutive shots
 };
 
