@@ -75,8 +75,14 @@ def parse():
 
 
 def kernel_source_hash() -> str:
-    """sha256[:16] of the acoustic kernel's sources, concatenated in order."""
-    return hashlib.sha256(b"".join(f.read_bytes() for f in KERNEL_SOURCES)).hexdigest()[:16]
+    """sha256[:16] of the acoustic kernel's sources, concatenated in order,
+    followed by the per-source compiler flags they are built with (the
+    path-free additions of the build script)."""
+    from paper_1608_03984_amd import _build
+
+    h = hashlib.sha256(b"".join(f.read_bytes() for f in KERNEL_SOURCES))
+    h.update(repr([_build.EXTRA.get(f.name, []) for f in KERNEL_SOURCES]).encode())
+    return h.hexdigest()[:16]
 
 
 def committed_traffic(phys: int):
