@@ -1,7 +1,8 @@
 """The benchmark's command line without a GPU: more than one GPU is refused
-with a message and a non-zero status (the solver has no multi-GPU path), and
-the gradient byte count that the gradient benches report against matches its
-terms."""
+with a message and a non-zero status (the solver has no multi-GPU path), the
+gradient byte count that the gradient benches report against matches its
+terms, and the hash that ties the committed traffic counters to the kernel
+covers the sources and their per-source build flags."""
 import json
 import subprocess
 import sys
@@ -29,3 +30,25 @@ def test_gradient_bytes_terms():
     # interval 1: every step its own segment, none fused; the last segment's
     # single step is not recomputed
     assert bench.gradient_bytes(10, 1) == 16 * 10 + 4 + 20 * 9 + 16 * 10 + 16 * 10 + 16
+
+
+def test_kernel_hash_covers_sources_and_build_flags():
+    sys.path.insert(0, str(ROOT))
+    import bench
+    from paper_1608_03984_amd import _build
+
+    # every per-source flag set names a source the build compiles
+    assert set(_build.EXTRA) <= set(_build.SOURCES)
+    # the hashed sources exist and are compiled by the build
+    names = [f.name for f in bench.KERNEL_SOURCES]
+    assert all(f.exists() for f in bench.KERNEL_SOURCES)
+    assert {n for n in names if n.endswith(".hip")} <= set(_build.SOURCES)
+    h = bench.kernel_source_hash()
+    saved = dict(_build.EXTRA)
+    try:
+        _build.EXTRA["fd_acoustic_hi.hip"] = ["-O2"]
+        assert bench.kernel_source_hash() != h
+    finally:
+        _build.EXTRA.clear()
+        _build.EXTRA.update(saved)
+    assert bench.kernel_source_hash() == h
