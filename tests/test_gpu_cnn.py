@@ -208,6 +208,30 @@ def test_network_gradient_and_adam_vs_oracle():
     assert np.array_equal(p1[:, 27 * 256:], p0[:, 27 * 256:])
 
 
+def test_adam_carried_steps_vs_oracle():
+    """fd_cnn_adam over five consecutive steps with the moments carried on
+    the device (t = 1..5, a fresh gradient each step) against the oracle's
+    Adam run in FP64 from the same FP32 start: parameters and both moments
+    element-wise to 1e-6 (beyond t = 1 the bias corrections 1 - beta^t and
+    the carried moments matter)."""
+    rng = np.random.default_rng(77)
+    n = 3000
+    p0 = rng.standard_normal(n).astype(np.float32)
+    grads = [rng.standard_normal(n).astype(np.float32) for _ in range(5)]
+    say("case: Adam, five carried steps")
+    pd, md, vd = dev(p0.copy()), dev(np.zeros(n, np.float32)), dev(np.zeros(n, np.float32))
+    pr, mr, vr = p0.astype(np.float64), np.zeros(n), np.zeros(n)
+    for t, g in enumerate(grads, start=1):
+        gd = dev(g)
+        P.fd_cnn_adam(pd.data_ptr(), gd.data_ptr(), md.data_ptr(), vd.data_ptr(), n, t, 1e-2,
+                      0.9, 0.999, 1e-8, st())
+        pr, mr, vr = C.adam_step(pr, g.astype(np.float64), mr, vr, t, 1e-2)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(pd.cpu().numpy(), pr, rtol=0, atol=1e-6)
+        np.testing.assert_allclose(md.cpu().numpy(), mr, rtol=1e-6, atol=1e-9)
+        np.testing.assert_allclose(vd.cpu().numpy(), vr, rtol=1e-6, atol=1e-9)
+
+
 def test_restrict_features_correct_roundtrip():
     """fd_restrict samples every second point; features carry s u^n, s u^{n-1}
     and v / vref - 1; a correction by the residual restores the reference."""

@@ -5,8 +5,10 @@
   * backward-data is the adjoint of the convolution (dot-product identity),
     backward-weight its adjoint in the weights;
   * the network gradient equals central differences of the FP64 loss;
-  * Adam's first step has a closed form; bf16 rounding is exact on
-    representable values and rounds half to even.
+  * Adam's first step has a closed form, and so have five steps of a
+    constant and of a sign-alternating gradient (moments carried, bias
+    corrections 1 - beta^t); bf16 rounding is exact on representable values
+    and rounds half to even.
 Planted mistakes in a copy of the module must fail these pins.
 """
 import importlib.util
@@ -68,6 +70,39 @@ def check_net_gradient(M=C):
             flat[i] = old
             fd = (lp - lm) / (2 * h)
             assert abs(fd - g.reshape(-1)[i]) <= 1e-6 * max(1.0, abs(fd)), (k, i, fd, g.reshape(-1)[i])
+
+
+def check_adam_sequence(M=C):
+    """Five carried Adam steps against closed forms written from the
+    recurrences m_t = b1 m + (1-b1) g_t, v_t = b2 v + (1-b2) g_t^2 with zero
+    initial moments:
+      constant g:            m_t = (1 - b1^t) g,  v_t = (1 - b2^t) g^2, so
+                             every bias-corrected step is g / (|g| + eps);
+      g_t = (-1)^(t+1) g:    m_t = (1-b1) g (-1)^(t+1) (1 - (-b1)^t) / (1 + b1),
+                             v_t = (1 - b2^t) g^2."""
+    rng = np.random.default_rng(6)
+    b1, b2, eps, lr, T = 0.9, 0.999, 1e-8, 1e-2, 5
+    g = rng.standard_normal(8) + np.sign(rng.standard_normal(8)) * 0.5
+    p0 = rng.standard_normal(8)
+    for alternating in (False, True):
+        p, m, v = p0.copy(), np.zeros(8), np.zeros(8)
+        ref = p0.copy()
+        for t in range(1, T + 1):
+            gt = g * (-1.0) ** (t + 1) if alternating else g
+            p, m, v = M.adam_step(p, gt, m, v, t, lr, b1, b2, eps)
+            if alternating:
+                mt = (1 - b1) * g * (-1.0) ** (t + 1) * (1 - (-b1) ** t) / (1 + b1)
+            else:
+                mt = (1 - b1 ** t) * g
+            vt = (1 - b2 ** t) * g * g
+            np.testing.assert_allclose(m, mt, rtol=1e-12, atol=1e-15)
+            np.testing.assert_allclose(v, vt, rtol=1e-12, atol=1e-15)
+            ref = ref - lr * (mt / (1 - b1 ** t)) / (np.abs(g) + eps)
+            np.testing.assert_allclose(p, ref, rtol=1e-12, atol=1e-14)
+
+
+def test_adam_sequence_closed_forms():
+    check_adam_sequence()
 
 
 def test_conv_matches_loops():
@@ -140,6 +175,15 @@ MUTANTS = [
     ("tap order", "OFFSETS = [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]",
      "OFFSETS = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]",
      [check_conv_matches_loops]),
+    ("adam bias correction without the power", "vh = v / (1 - beta2 ** t)",
+     "vh = v / (1 - beta2)", [check_adam_sequence]),
+    ("adam first-moment correction without the power", "mh = m / (1 - beta1 ** t)",
+     "mh = m / (1 - beta1)", [check_adam_sequence]),
+    ("adam moments not carried", "return param - lr * mh / (np.sqrt(vh) + eps), m, v",
+     "return param - lr * mh / (np.sqrt(vh) + eps), m * 0, v * 0", [check_adam_sequence]),
+    ("adam second moment of the gradient, not its square",
+     "v = beta2 * v + (1 - beta2) * grad * grad", "v = beta2 * v + (1 - beta2) * np.abs(grad)",
+     [check_adam_sequence]),
 ]
 
 

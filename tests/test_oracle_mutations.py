@@ -14,6 +14,7 @@ import pytest
 import oracle
 from tests import test_oracle_acoustic as ta
 from tests import test_oracle_adjoint as tadj
+from tests import test_oracle_step_points as tsp
 from tests import test_oracle_tti as tt
 from tests import test_oracle_vti as tv
 from tests import test_oracle_weights as tw
@@ -71,6 +72,12 @@ VTI = [
 ADJOINT = [
     lambda: tadj.test_adjoint_equals_dense_transpose(4),
     lambda: tadj.test_adjoint_dot_product(3, 8),
+]
+STEP_POINTS = [
+    lambda: tsp.check_acoustic(3, 4),
+    lambda: tsp.check_acoustic(2, 4),
+    lambda: tsp.check_vti(3, 4),
+    lambda: tsp.check_tti(4),
 ]
 GRADIENT = [
     lambda: tadj.test_gradient_pointwise_central_differences(2),
@@ -139,6 +146,27 @@ MUTANTS = [
      "const double* uk2 = hist + (size_t)k * (size_t)N;", GRADIENT),
     # gradient: damping factor of u^k with the wrong sign
     ("gradient damping", "(1.0 + s) * uk[i]", "(1.0 - s) * uk[i]", GRADIENT),
+    # one-step entries: y and z exchanged in the flat-index decode
+    ("acoustic step decode",
+     "long ix = i % n.nx, iy = (i / n.nx) % n.ny, iz = i / (n.nx * n.ny);\n        out[k] = acoustic_point",
+     "long ix = i % n.nx, iz = (i / n.nx) % n.nz, iy = i / (n.nx * n.nz);\n        out[k] = acoustic_point",
+     STEP_POINTS),
+    # one-step entries: the two time levels exchanged
+    ("acoustic step levels", "fld_t up = {NULL, u_prev}, uc = {NULL, u_cur};",
+     "fld_t up = {NULL, u_cur}, uc = {NULL, u_prev};", STEP_POINTS),
+    # one-step entries: x and y exchanged in the TTI decode
+    ("tti step decode",
+     "long ix = i % n.nx, iy = (i / n.nx) % n.ny, iz = i / (n.nx * n.ny);\n        tti_point",
+     "long ix = i % n.ny, iy = (i / n.ny) % n.nx, iz = i / (n.nx * n.ny);\n        tti_point",
+     STEP_POINTS),
+    # one-step entries: the previous levels of p and r exchanged (TTI)
+    ("tti step fields",
+     "fld_t pp = {NULL, p_prev}, pc = {NULL, p_cur}, rp = {NULL, r_prev}, rc = {NULL, r_cur};",
+     "fld_t pp = {NULL, r_prev}, pc = {NULL, p_cur}, rp = {NULL, p_prev}, rc = {NULL, r_cur};",
+     STEP_POINTS),
+    # one-step entries: the current p passed for r (VTI)
+    ("vti step fields", "iz = i / (n.nx * n.ny);\n        vti_point(pp, pc, rp, rc,",
+     "iz = i / (n.nx * n.ny);\n        vti_point(pp, pc, rp, pc,", STEP_POINTS),
 ]
 
 
