@@ -100,9 +100,15 @@ def committed_traffic(phys: int):
     return {int(k): v["traffic_bytes"] for k, v in data["per_order"].items()}
 
 
+TRIAD_SWEEP = [(u, b, f) for f in (0, 1) for u in (1, 2, 4, 8) for b in (0, 2048, 4096, 8192)]
+
+
 def triad_gbs(torch, P):
-    """STREAM-style triad bandwidth (2^28 floats per array), events on the
-    launch stream."""
+    """STREAM-style triad bandwidth (2^28 floats per array, 3 GiB moved per
+    launch), events on the launch stream: the best of a sweep over the
+    triad's unroll depth, grid and load kind (fd_triad_config).  Returns
+    (GB/s, {"unroll", "blocks", "temporal", "default_gbs"}) or (None, None)
+    when a result is wrong."""
     n = 1 << 28
     dev = torch.device("cuda:0")
     a = torch.empty(n, device=dev)
@@ -110,13 +116,24 @@ def triad_gbs(torch, P):
     c = torch.ones(n, device=dev)
     st = torch.cuda.current_stream().cuda_stream
     ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-    P.fd_triad(a.data_ptr(), b.data_ptr(), c.data_ptr(), 2.0, n, st)
-    t = timed(lambda: [P.fd_triad(a.data_ptr(), b.data_ptr(), c.data_ptr(), 2.0, n, st)
-                       for _ in range(10)], ev) / 10
-    ok = float(a[n - 1].item()) == 3.0
+    ptrs = (a.data_ptr(), b.data_ptr(), c.data_ptr())
+    best, cfg = 0.0, None
+    for u, blocks, flags in TRIAD_SWEEP:
+        P.fd_triad_config(*ptrs, 2.0, n, u, blocks, flags, st)
+        t = timed(lambda: [P.fd_triad_config(*ptrs, 2.0, n, u, blocks, flags, st)
+                           for _ in range(10)], ev) / 10
+        gbs = 12 * n / t / 1e9
+        if gbs > best:
+            best, cfg = gbs, {"unroll": u, "blocks": blocks, "temporal": bool(flags)}
+    P.fd_triad(*ptrs, 2.0, n, st)
+    t = timed(lambda: [P.fd_triad(*ptrs, 2.0, n, st) for _ in range(10)], ev) / 10
+    cfg["default_gbs"] = round(12 * n / t / 1e9, 1)
+    a.zero_()
+    P.fd_triad(*ptrs, 2.0, n, st)
+    ok = bool((a == 3.0).all().item())
     del a, b, c
     torch.cuda.empty_cache()
-    return 12 * n / t / 1e9 if ok else None
+    return (best, cfg) if ok else (None, None)
 
 
 def profile_pass(args):
@@ -244,7 +261,7 @@ def tti_bench(args, physics="tti"):
     ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
     s.forward(args.warmup, p.src, wav[:args.warmup], p.rec, traces=traces[:args.warmup])
     tw = timed(lambda: s.forward(args.steps, p.src, wav[args.warmup:], p.rec, zero_state=False,
-                                 traces=traces[args.warmup:]), ev)
+                                 traces=traces[args.warmup:], keep_points=True), ev)
     s.forward(args.warmup, zero_state=False)
     tk = timed(lambda: s.forward(args.steps, zero_state=False), ev)
     ok = bool(torch.isfinite(traces).all().item())
@@ -805,7 +822,8 @@ def main():
         # warm-up (also uploads the point tables)
         s.forward(args.warmup, prob.src, wav[:args.warmup], rec, traces=traces[:args.warmup])
         tw = timed(lambda: s.forward(args.steps, prob.src, wav[args.warmup:], rec,
-                                     zero_state=False, traces=traces[args.warmup:]), ev)
+                                     zero_state=False, traces=traces[args.warmup:],
+                                     keep_points=True), ev)
         # the stencil kernel alone (no sparse points): its average launch time
         s.forward(args.warmup, zero_state=False)
         tk = timed(lambda: s.forward(args.steps, zero_state=False), ev)
@@ -829,7 +847,7 @@ def main():
         tot_kernel += tk
     value = tot_pts / tot_time / 1e9
     ach = BYTES_PER_POINT * tot_pts / tot_kernel / 1e9
-    tgbs = triad_gbs(torch, P)
+    tgbs, tcfg = triad_gbs(torch, P)
     mean_traffic = (round(sum(traffic[so] for so in orders) / len(orders))
                     if traffic and all(so in traffic for so in orders) else None)
     line = {
@@ -855,6 +873,7 @@ def main():
                      "kernel": "acoustic3d_tiled (sweep aggregate; traffic = mean bytes per "
                                "launch over the orders)"},
         "triad_gbs": round(tgbs, 1) if tgbs else None,
+        "triad_config": tcfg,
         "frac_of_triad": round(ach / tgbs, 4) if tgbs else None,
         "per_order": per,
     }

@@ -70,8 +70,16 @@ extern "C" {
 #define FD_FIELD_R_PREV 2 /* VTI/TTI r^{n-1} */
 #define FD_FIELD_R_CUR 3  /* VTI/TTI r^{n}   */
 
-/* fd_forward flags. */
+/* fd_forward / fd_forward_shots flags. */
 #define FD_ZERO_STATE 1 /* start from the zero state of Eq. (Acou)/(TTI) */
+/* Use the point table of the last upload (the previous stepping call's
+ * sources and receivers, in that call's order and, for fd_forward_shots, with
+ * its per-shot counts) without reading coordinates: src->coords, rec->coords
+ * and the count arrays may be NULL, src->n and rec->n must equal the counts of
+ * that upload (FD_ERR_INVALID_ARG otherwise, or when nothing was uploaded
+ * yet), and the data pointers are used as usual.  The host work of the call
+ * then does not grow with the number of points. */
+#define FD_KEEP_POINTS 2
 
 /* Largest supported space order (radius 8). */
 #define FD_MAX_SPACE_ORDER 16
@@ -135,8 +143,9 @@ int32_t fd_setup(const fd_grid* grid, const fd_model* model, void* workspace,
  * zero; otherwise the run continues from the held state (fd_set_field or a
  * previous call).  src or rec may be NULL.  Asynchronous on `stream`, except
  * that new point coordinates are uploaded with one synchronisation.  A call
- * whose coordinates equal the previous call's launches kernels only, so it
- * can be captured in a HIP graph; the index of the level holding u^n is host
+ * whose coordinates equal the previous call's (compared on the host, in time
+ * proportional to the number of points) or that passes FD_KEEP_POINTS
+ * launches kernels only, so it can be captured in a HIP graph; the index of the level holding u^n is host
  * state that advances at capture time, so replays agree with it when nt is
  * even (or every run starts from FD_ZERO_STATE and reads only traces). */
 int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_points* rec,
@@ -162,6 +171,16 @@ int32_t fd_cfl_dt(const fd_grid* grid, double vmax, double* dt_max);
  * traffic (8 bytes read, 4 written per element) for calibrating hardware
  * byte counters.  Asynchronous on `stream`. */
 int32_t fd_triad(float* a, const float* b, const float* c, float s, int64_t n, void* stream);
+
+/* fd_triad with an explicit launch shape, for sweeping the ceiling: each
+ * thread moves `unroll` (1, 2, 4 or 8) 16-byte vectors of each array per
+ * iteration; blocks = 0 gives every 256-thread block one chunk of 256 unroll
+ * vectors, blocks > 0 launches that many blocks striding over the chunks;
+ * flags = FD_TRIAD_TEMPORAL uses ordinary instead of non-temporal loads and
+ * stores.  Same traffic as fd_triad.  FD_ERR_INVALID_ARG for other values. */
+#define FD_TRIAD_TEMPORAL 1
+int32_t fd_triad_config(float* a, const float* b, const float* c, float s, int64_t n,
+                        int32_t unroll, int32_t blocks, int32_t flags, void* stream);
 
 /* ------------------------------------------------------------------------ */
 /* Several shots on one model (acoustic only)                                */

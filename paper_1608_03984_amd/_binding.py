@@ -29,6 +29,8 @@ FD_FIELD_R_PREV = 2
 FD_FIELD_R_CUR = 3
 
 FD_ZERO_STATE = 1
+FD_KEEP_POINTS = 2
+FD_TRIAD_TEMPORAL = 1
 FD_MAX_SPACE_ORDER = 16
 
 FD_OPT_KERNEL = 1
@@ -56,7 +58,7 @@ EXPORTS = (
     "fd_adjoint", "fd_misfit", "fd_workspace_bytes_shots", "fd_setup_shots", "fd_forward_shots",
     "fd_get_shot_field", "fd_set_shot_field", "fd_cnn_packed_elems", "fd_cnn_pack", "fd_cnn_conv",
     "fd_cnn_wgrad_scratch", "fd_cnn_wgrad", "fd_cnn_loss_grad", "fd_cnn_adam", "fd_cnn_features",
-    "fd_cnn_correct", "fd_cnn_residual", "fd_restrict",
+    "fd_cnn_correct", "fd_cnn_residual", "fd_restrict", "fd_triad_config",
 )
 
 
@@ -119,6 +121,8 @@ def lib() -> ctypes.CDLL:
             "fd_strerror": (ctypes.c_char_p, [i32]),
             "fd_last_error": (ctypes.c_char_p, [vp]),
             "fd_triad": (i32, [vp, vp, vp, ctypes.c_float, ctypes.c_int64, vp]),
+            "fd_triad_config": (i32, [vp, vp, vp, ctypes.c_float, ctypes.c_int64, i32, i32, i32,
+                                      vp]),
             "fd_checkpoint_bytes": (i32, [vp, i32, i32, u64p, ctypes.POINTER(i32)]),
             "fd_forward_checkpointed": (i32, [vp, i32, pp, pp, i32, vp, ctypes.c_uint64, vp]),
             "fd_gradient": (i32, [vp, i32, pp, pp, i32, vp, ctypes.c_uint64, i32, vp, vp, vp]),
@@ -201,8 +205,16 @@ def fd_setup(grid: FdGrid, model: FdModel, workspace_ptr: int, workspace_bytes: 
 
 
 def _points(coords, data_ptr):
+    """fd_points for host coordinates [n][ndim]; an int n instead gives n
+    points with no coordinates (FD_KEEP_POINTS calls)."""
     if coords is None:
         return None, None
+    if isinstance(coords, (int, np.integer)):
+        p = FdPoints()
+        p.n = int(coords)
+        p.coords = None
+        p.data = ctypes.c_void_p(int(data_ptr) if data_ptr else 0)
+        return p, None
     c = np.ascontiguousarray(coords, dtype=np.float64)
     p = FdPoints()
     p.n = int(c.shape[0]) if c.size else 0
@@ -243,6 +255,14 @@ def fd_destroy(ctx):
 def fd_triad(a_ptr: int, b_ptr: int, c_ptr: int, s: float, n: int, stream: int):
     _check(lib().fd_triad(ctypes.c_void_p(a_ptr), ctypes.c_void_p(b_ptr), ctypes.c_void_p(c_ptr),
                           float(s), int(n), ctypes.c_void_p(stream)), "fd_triad")
+
+
+def fd_triad_config(a_ptr: int, b_ptr: int, c_ptr: int, s: float, n: int, unroll: int,
+                    blocks: int, flags: int, stream: int):
+    _check(lib().fd_triad_config(ctypes.c_void_p(a_ptr), ctypes.c_void_p(b_ptr),
+                                 ctypes.c_void_p(c_ptr), float(s), int(n), int(unroll),
+                                 int(blocks), int(flags), ctypes.c_void_p(stream)),
+           "fd_triad_config")
 
 
 def fd_stencil_weights(space_order: int, deriv: int) -> np.ndarray:

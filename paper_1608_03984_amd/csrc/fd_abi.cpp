@@ -360,21 +360,37 @@ void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, int ng
     }
 }
 
+// True when the given points are those of the last upload (compared in
+// place: no copy of the coordinates).
+bool same_points(const fd_ctx* ctx, int n1, const double* c1, int n2, const double* c2,
+                 const int32_t* counts1, const int32_t* counts2) {
+    const size_t nd = (size_t)ctx->g.ndim;
+    if (n1 != ctx->nsrc_dev || n2 != ctx->nrec_dev) return false;
+    if ((size_t)n1 * nd != ctx->src_coords.size() || (size_t)n2 * nd != ctx->rec_coords.size())
+        return false;
+    if (n1 && std::memcmp(c1, ctx->src_coords.data(), (size_t)n1 * nd * sizeof(double))) return false;
+    if (n2 && std::memcmp(c2, ctx->rec_coords.data(), (size_t)n2 * nd * sizeof(double))) return false;
+    const size_t ns = counts1 || counts2 ? (size_t)ctx->nshots : 0;
+    if ((counts1 ? ns : 0) != ctx->src_counts.size() || (counts2 ? ns : 0) != ctx->rec_counts.size())
+        return false;
+    if (counts1 && std::memcmp(counts1, ctx->src_counts.data(), ns * sizeof(int32_t))) return false;
+    if (counts2 && std::memcmp(counts2, ctx->rec_counts.data(), ns * sizeof(int32_t))) return false;
+    return true;
+}
+
 // Upload the sparse-point table [first..., second...] when the coordinates
 // differ from the last upload.
 // counts1 / counts2 give the points per shot (NULL: all in shot 0).
 int32_t sync_points(fd_ctx* ctx, int n1, const double* c1, int n2, const double* c2,
                     const char* what1, const char* what2, hipStream_t s,
                     const int32_t* counts1 = nullptr, const int32_t* counts2 = nullptr) {
+    if (same_points(ctx, n1, c1, n2, c2, counts1, counts2)) return FD_OK;
     const int nd = ctx->g.ndim;
     std::vector<double> a(n1 ? c1 : nullptr, n1 ? c1 + (size_t)n1 * nd : nullptr);
     std::vector<double> b(n2 ? c2 : nullptr, n2 ? c2 + (size_t)n2 * nd : nullptr);
     const int ns = counts1 || counts2 ? ctx->nshots : 0;
     std::vector<int32_t> k1(counts1 ? counts1 : nullptr, counts1 ? counts1 + ns : nullptr);
     std::vector<int32_t> k2(counts2 ? counts2 : nullptr, counts2 ? counts2 + ns : nullptr);
-    if (n1 == ctx->nsrc_dev && n2 == ctx->nrec_dev && a == ctx->src_coords &&
-        b == ctx->rec_coords && k1 == ctx->src_counts && k2 == ctx->rec_counts)
-        return FD_OK;
     std::vector<SparsePoint> host((size_t)n1 + n2);
     for (int i = 0; i < n1; ++i)
         if (!locate(ctx, &a[(size_t)i * nd], &host[i]))
@@ -409,11 +425,23 @@ int32_t sync_points(fd_ctx* ctx, int n1, const double* c1, int n2, const double*
 }
 
 // Argument checks shared by the stepping entry points.
-int32_t check_points_arg(fd_ctx* ctx, int nt, const fd_points* p, const char* what) {
+// keep: the coordinates are those of the last upload (FD_KEEP_POINTS) and
+// may be NULL.
+int32_t check_points_arg(fd_ctx* ctx, int nt, const fd_points* p, const char* what,
+                         bool keep = false) {
     if (!p) return FD_OK;
     if (p->n < 0) return fail(ctx, FD_ERR_INVALID_ARG, std::string("negative ") + what + " count");
-    if (p->n > 0 && (!p->coords || (!p->data && nt > 0)))
+    if (p->n > 0 && ((!p->coords && !keep) || (!p->data && nt > 0)))
         return fail(ctx, FD_ERR_INVALID_ARG, std::string(what) + " coords/data missing");
+    return FD_OK;
+}
+
+// FD_KEEP_POINTS: reuse the point table of the last upload as it stands; the
+// counts must be those of that upload (O(1) host work per call).
+int32_t keep_points(fd_ctx* ctx, int n1, int n2) {
+    if (ctx->nsrc_dev < 0 || n1 != ctx->nsrc_dev || n2 != ctx->nrec_dev)
+        return fail(ctx, FD_ERR_INVALID_ARG,
+                    "FD_KEEP_POINTS: the point counts differ from the last upload");
     return FD_OK;
 }
 
@@ -751,16 +779,18 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
     if (ctx->nshots > 1)
         return fail(ctx, FD_ERR_INVALID_ARG, "a context of several shots steps with fd_forward_shots");
     if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
-    int32_t rc = check_points_arg(ctx, nt, src, "source");
-    if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver");
+    const bool keep = (flags & FD_KEEP_POINTS) != 0;
+    int32_t rc = check_points_arg(ctx, nt, src, "source", keep);
+    if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver", keep);
     if (rc != FD_OK) return rc;
     const int nsrc = src ? src->n : 0, nrec = rec ? rec->n : 0;
     if ((int64_t)nsrc + nrec > ctx->max_points)
         return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int nd = ctx->g.ndim;
-    rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nrec, rec ? rec->coords : nullptr,
-                     "source", "receiver", s);
+    rc = keep ? keep_points(ctx, nsrc, nrec)
+              : sync_points(ctx, nsrc, src ? src->coords : nullptr, nrec,
+                            rec ? rec->coords : nullptr, "source", "receiver", s);
     if (rc != FD_OK) return rc;
 
     hipError_t he = hipSuccess;
@@ -1158,8 +1188,9 @@ int32_t fd_forward_shots(fd_ctx* ctx, int32_t nt, const fd_points* src, const in
     if (ctx->tti || ctx->vti)
         return fail(ctx, FD_ERR_UNSUPPORTED, "several shots are built for acoustic only");
     if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
-    int32_t rc = check_points_arg(ctx, nt, src, "source");
-    if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver");
+    const bool keep = (flags & FD_KEEP_POINTS) != 0;
+    int32_t rc = check_points_arg(ctx, nt, src, "source", keep);
+    if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver", keep);
     if (rc != FD_OK) return rc;
     const int nsrc = src ? src->n : 0, nrec = rec ? rec->n : 0;
     if ((int64_t)nsrc + nrec > ctx->max_points)
@@ -1177,14 +1208,19 @@ int32_t fd_forward_shots(fd_ctx* ctx, int32_t nt, const fd_points* src, const in
             return fail(ctx, FD_ERR_INVALID_ARG, std::string(what) + " counts do not sum to n");
         return FD_OK;
     };
-    rc = check_counts(src_counts, nsrc, "source");
-    if (rc == FD_OK) rc = check_counts(rec_counts, nrec, "receiver");
-    if (rc != FD_OK) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int nd = ctx->g.ndim;
-    rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nrec, rec ? rec->coords : nullptr,
-                     "source", "receiver", s, nsrc ? src_counts : nullptr,
-                     nrec ? rec_counts : nullptr);
+    if (keep) {
+        // the shots of the points are those of the last upload
+        rc = keep_points(ctx, nsrc, nrec);
+    } else {
+        rc = check_counts(src_counts, nsrc, "source");
+        if (rc == FD_OK) rc = check_counts(rec_counts, nrec, "receiver");
+        if (rc == FD_OK)
+            rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nrec,
+                             rec ? rec->coords : nullptr, "source", "receiver", s,
+                             nsrc ? src_counts : nullptr, nrec ? rec_counts : nullptr);
+    }
     if (rc != FD_OK) return rc;
     hipError_t he = hipSuccess;
     if (ctx->flags_stale) {
@@ -1302,12 +1338,10 @@ int32_t fd_cnn_conv(const uint16_t* x, int32_t cin_pad, const int64_t* shape,
     return e == hipSuccess ? FD_OK : FD_ERR_DEVICE;
 }
 
-static const int kWgradZChunk = 32;
-
 int32_t fd_cnn_wgrad_scratch(const int64_t* shape, int64_t* floats) {
     if (!cnn_shape_ok(shape) || !floats) return FD_ERR_INVALID_ARG;
     *floats = (int64_t)fd::cnn_wgrad_slots((int)shape[0], (int)shape[1], (int)shape[2],
-                                           kWgradZChunk) *
+                                           fd::kCnnWgradZChunk) *
               FD_CNN_LAYER_FLOATS;
     return FD_OK;
 }
@@ -1322,7 +1356,7 @@ int32_t fd_cnn_wgrad(const uint16_t* x, int32_t cx, const uint16_t* dz, int32_t 
         return FD_ERR_INVALID_ARG;
     if (scratch_floats < need) return FD_ERR_WORKSPACE;
     const hipError_t e = fd::launch_cnn_wgrad(x, cx, dz, cz, (int)shape[0], (int)shape[1],
-                                              (int)shape[2], kWgradZChunk, scratch, grad,
+                                              (int)shape[2], fd::kCnnWgradZChunk, scratch, grad,
                                               static_cast<hipStream_t>(stream));
     return e == hipSuccess ? FD_OK : FD_ERR_DEVICE;
 }

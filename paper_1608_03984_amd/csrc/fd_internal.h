@@ -181,6 +181,7 @@ hipError_t launch_finish_gradient(const float* gsum, const float* A, float* out,
                                   double dt, int wrt_vel, int accumulate, hipStream_t s);
 
 // correction network (fd_cnn.hip)
+constexpr int kCnnWgradZChunk = 32;  // z planes per block of the weight-gradient pass
 int cnn_packed_elems(int cin_pad);
 int cnn_wgrad_slots(int D, int H, int W, int zchunk);
 hipError_t launch_cnn_pack(const float* w, int cin, int cout, int cin_pad, int flip,

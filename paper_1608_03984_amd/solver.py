@@ -65,8 +65,10 @@ class Solver:
         return torch.cuda.current_stream(self.device).cuda_stream
 
     def forward(self, nt, src_coords=None, wavelet=None, rec_coords=None, zero_state=True,
-                traces=None):
-        """Run nt steps; returns the receiver traces [nt][nrec] (device tensor)."""
+                traces=None, keep_points=False):
+        """Run nt steps; returns the receiver traces [nt][nrec] (device tensor).
+        keep_points: the points are the previous call's (FD_KEEP_POINTS; the
+        coordinates are only counted, not passed)."""
         src = None if src_coords is None else np.asarray(src_coords, np.float64).reshape(-1, self.ndim)
         rec = None if rec_coords is None else np.asarray(rec_coords, np.float64).reshape(-1, self.ndim)
         q = None
@@ -75,9 +77,12 @@ class Solver:
         nrec = 0 if rec is None else rec.shape[0]
         if traces is None and nrec:
             traces = torch.empty((nt, nrec), dtype=torch.float32, device=self.device)
+        flags = (B.FD_ZERO_STATE if zero_state else 0) | (B.FD_KEEP_POINTS if keep_points else 0)
+        if keep_points:
+            src = None if src is None else src.shape[0]
+            rec = None if rec is None else rec.shape[0]
         B.fd_forward(self.ctx, nt, src, q.data_ptr() if q is not None else 0, rec,
-                     traces.data_ptr() if nrec else 0, B.FD_ZERO_STATE if zero_state else 0,
-                     self.stream)
+                     traces.data_ptr() if nrec else 0, flags, self.stream)
         self._keep_q = q  # the wavelet must outlive the asynchronous launches
         return traces
 

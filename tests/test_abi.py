@@ -126,6 +126,16 @@ def test_null_context_and_strings():
     assert P.fd_strerror(99) == "unknown status"
 
 
+def test_triad_config_rejects_bad_shapes():
+    lib = P.lib()
+    a = ctypes.c_void_p(256)  # aligned dummies: rejected before any device work
+    for unroll, blocks, flags in ((3, 0, 0), (0, 0, 0), (16, 0, 0), (4, -1, 0), (4, 0, 2)):
+        assert lib.fd_triad_config(a, a, a, 1.0, 64, unroll, blocks, flags,
+                                   None) == P.FD_ERR_INVALID_ARG
+    assert lib.fd_triad_config(ctypes.c_void_p(4), a, a, 1.0, 64, 1, 0, 0,
+                               None) == P.FD_ERR_INVALID_ARG  # misaligned
+
+
 def test_gradient_entry_points_reject_null_context():
     lib = P.lib()
     u64 = ctypes.c_uint64(0)

@@ -212,6 +212,26 @@ def test_acoustic_continue_equals_single_run():
     assert np.array_equal(u2, u_all)
 
 
+def test_keep_points_equals_passing_the_coordinates():
+    """FD_KEEP_POINTS reuses the last uploaded point table: the same bits as
+    passing the same coordinates again; a different count is rejected."""
+    p = acoustic_problem(3, (80, 20, 20), 4, 8, 30, seed=14)
+    say("case: keep points")
+    s = from_problem(p)
+    t1 = s.forward(10, p.src, p.wavelet[:10], p.rec)
+    t2 = s.forward(20, p.src, p.wavelet[10:], p.rec, zero_state=False, keep_points=True)
+    u_keep = s.get_field().cpu().numpy()
+    keep = np.concatenate([t1.cpu().numpy(), t2.cpu().numpy()])
+    t_all = s.forward(30, p.src, p.wavelet, p.rec).cpu().numpy()
+    u_all = s.get_field().cpu().numpy()
+    with pytest.raises(P.FdError) as e:
+        s.forward(2, p.src, p.wavelet[:2], p.rec[:-1], zero_state=False, keep_points=True)
+    assert e.value.code == P.FD_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    s.close()
+    assert np.array_equal(keep, t_all) and np.array_equal(u_keep, u_all)
+
+
 def test_acoustic_edge_cases():
     say("case: edge cases")
     # a grid smaller than the stencil, no layer, no points, nt = 0
