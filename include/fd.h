@@ -33,8 +33,9 @@
  *   - All device work is enqueued asynchronously on the hipStream_t passed as
  *     `stream` (NULL = default stream); calls return without waiting, except
  *     where stated.  Synchronise on that stream before reading results.
- *   - One context serves one stream at a time and is not thread-safe.  There is
- *     no global mutable state.
+ *   - One context serves one stream at a time and is not thread-safe.  The
+ *     only global state is the per-device scratch array of
+ *     fd_cnn_wgrad_noalloc (and its address table, guarded by a lock).
  *
  * Errors: every entry point returns an int32 status (FD_OK = 0).  No exception
  * crosses the ABI and nothing is printed.  fd_last_error() gives a
@@ -365,6 +366,21 @@ int32_t fd_cnn_wgrad_scratch(const int64_t* shape, int64_t* floats);
 int32_t fd_cnn_wgrad(const uint16_t* x, int32_t cx, const uint16_t* dz, int32_t cz,
                      const int64_t* shape, float* scratch, int64_t scratch_floats, float* grad,
                      void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): fd_cnn_wgrad
+ * without the scratch argument.  The partial sums live in a library-owned
+ * device array of FD_CNN_NOALLOC_SCRATCH_FLOATS floats (48 MiB) that every
+ * device the library runs on holds until the process ends; its address is
+ * looked up on the first call on a device (the current device, which must
+ * own `stream`).  Shapes whose fd_cnn_wgrad_scratch exceeds that size (more
+ * than 1816 blocks of 32 x 4 voxels x 32 planes, e.g. beyond 168^3) return
+ * FD_ERR_WORKSPACE; other arguments and results as fd_cnn_wgrad (the same
+ * kernels, the same bits).  Calls that overlap on one device share the array
+ * and race: serialise them (one stream, or events).  Allocates nothing. */
+#define FD_CNN_NOALLOC_SCRATCH_FLOATS 12582912
+int32_t fd_cnn_wgrad_noalloc(const uint16_t* x, int32_t cx, const uint16_t* dz, int32_t cz,
+                             const int64_t* shape, float* grad, void* stream);
 
 /* Masked mean-square loss L = 1/(2n) sum_mask |out - target|^2 (out, target
  * FP32 [nvox][cout]; mask uint8 [nvox]; inv_n = 1/n): dz = dL/dout as BF16

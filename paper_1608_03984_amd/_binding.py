@@ -50,6 +50,7 @@ FD_CNN_LINEAR = 1
 FD_CNN_MASKED = 2
 FD_CNN_IDENTITY = 3
 FD_CNN_UNMASKED = 4
+FD_CNN_NOALLOC_SCRATCH_FLOATS = 12582912
 
 EXPORTS = (
     "fd_workspace_bytes", "fd_setup", "fd_forward", "fd_get_field", "fd_set_field",
@@ -59,6 +60,7 @@ EXPORTS = (
     "fd_get_shot_field", "fd_set_shot_field", "fd_cnn_packed_elems", "fd_cnn_pack", "fd_cnn_conv",
     "fd_cnn_wgrad_scratch", "fd_cnn_wgrad", "fd_cnn_loss_grad", "fd_cnn_adam", "fd_cnn_features",
     "fd_cnn_correct", "fd_cnn_residual", "fd_restrict", "fd_triad_config",
+    "fd_cnn_wgrad_noalloc",
 )
 
 
@@ -143,6 +145,8 @@ def lib() -> ctypes.CDLL:
                                            ctypes.POINTER(ctypes.c_int64)]),
             "fd_cnn_wgrad": (i32, [vp, i32, vp, i32, ctypes.POINTER(ctypes.c_int64), vp,
                                    ctypes.c_int64, vp, vp]),
+            "fd_cnn_wgrad_noalloc": (i32, [vp, i32, vp, i32, ctypes.POINTER(ctypes.c_int64), vp,
+                                           vp]),
             "fd_cnn_loss_grad": (i32, [vp, vp, vp, ctypes.c_int64, i32, i32, ctypes.c_float, vp,
                                        vp, vp]),
             "fd_cnn_adam": (i32, [vp, vp, vp, vp, ctypes.c_int64, i32, ctypes.c_float,
@@ -413,6 +417,11 @@ def fd_cnn_wgrad(x_ptr, cx, dz_ptr, cz, shape, scratch_ptr, scratch_floats, grad
     _check(lib().fd_cnn_wgrad(_vp(x_ptr), int(cx), _vp(dz_ptr), int(cz), _shape3(shape),
                               _vp(scratch_ptr), int(scratch_floats), _vp(grad_ptr), _vp(stream)),
            "fd_cnn_wgrad")
+
+
+def fd_cnn_wgrad_noalloc(x_ptr, cx, dz_ptr, cz, shape, grad_ptr, stream):
+    _check(lib().fd_cnn_wgrad_noalloc(_vp(x_ptr), int(cx), _vp(dz_ptr), int(cz), _shape3(shape),
+                                      _vp(grad_ptr), _vp(stream)), "fd_cnn_wgrad_noalloc")
 
 
 def fd_cnn_loss_grad(out_ptr, target_ptr, mask_ptr, nvox, cout, cpad, inv_n, dz_ptr, loss_ptr,

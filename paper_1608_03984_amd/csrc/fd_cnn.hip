@@ -15,7 +15,10 @@
 // C[4 (l / 16) + i][l % 16] (i < 4).  The forward pass is O^T = W^T X^T: A
 // rows are output channels, B columns are 16 voxels along x, and the K index
 // runs over (tap, input channel) pairs, 32 per instruction.
+#include "fd.h"
 #include "fd_internal.h"
+
+#include <mutex>
 
 namespace fd {
 
@@ -682,3 +685,58 @@ hipError_t launch_restrict(const float* u, const Layout& L, int stride, float* o
 }
 
 }  // namespace fd
+
+// ---------------------------------------------------------------------------
+// Allocation-free weight gradient: the per-block partial sums go to a
+// file-scope device array instead of a caller buffer.  Each device holds its
+// own copy of the array (until the process ends); its device address is
+// looked up once per device, with that device current, and only that address
+// is handed to kernels.  The weight-gradient pass writes every partial slot
+// it later reads, so nothing has to be cleared between calls; calls that
+// overlap on one device share the array and race.
+// ---------------------------------------------------------------------------
+namespace fd {
+namespace {
+
+__device__ __align__(256) float scratch[FD_CNN_NOALLOC_SCRATCH_FLOATS];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[kMaxDevices];  // device address of `scratch` per device (or null)
+
+hipError_t scratch_address(float** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = static_cast<float*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+}  // namespace fd
+
+extern "C" int32_t fd_cnn_wgrad_noalloc(const uint16_t* x, int32_t cx, const uint16_t* dz,
+                                        int32_t cz, const int64_t* shape, float* grad,
+                                        void* stream) {
+    int64_t need = 0;
+    if (fd_cnn_wgrad_scratch(shape, &need) != FD_OK || !x || !dz || !grad)
+        return FD_ERR_INVALID_ARG;
+    if (!((cx == 8 && cz == 16) || (cx == 16 && cz == 16) || (cx == 16 && cz == 8)))
+        return FD_ERR_INVALID_ARG;
+    if (need > (int64_t)FD_CNN_NOALLOC_SCRATCH_FLOATS) return FD_ERR_WORKSPACE;
+    float* sp = nullptr;
+    if (fd::scratch_address(&sp) != hipSuccess) return FD_ERR_DEVICE;
+    const hipError_t e = fd::launch_cnn_wgrad(x, cx, dz, cz, (int)shape[0], (int)shape[1],
+                                              (int)shape[2], fd::kCnnWgradZChunk, sp, grad,
+                                              static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? FD_OK : FD_ERR_DEVICE;
+}

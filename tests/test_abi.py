@@ -136,6 +136,23 @@ def test_triad_config_rejects_bad_shapes():
                                None) == P.FD_ERR_INVALID_ARG  # misaligned
 
 
+def test_noalloc_wgrad_rejects_before_device_work():
+    """The allocation-free weight gradient checks its arguments and its
+    array's capacity on the host: shapes beyond FD_CNN_NOALLOC_SCRATCH_FLOATS
+    give FD_ERR_WORKSPACE, bad channels or pointers FD_ERR_INVALID_ARG."""
+    lib = P.lib()
+    a = ctypes.c_void_p(256)
+    big = (ctypes.c_int64 * 3)(256, 256, 256)
+    ok = (ctypes.c_int64 * 3)(16, 16, 16)
+    assert P.fd_cnn_wgrad_scratch((256, 256, 256)) > P.FD_CNN_NOALLOC_SCRATCH_FLOATS
+    assert P.fd_cnn_wgrad_scratch((168, 168, 168)) <= P.FD_CNN_NOALLOC_SCRATCH_FLOATS
+    assert lib.fd_cnn_wgrad_noalloc(a, 16, a, 16, big, a, None) == P.FD_ERR_WORKSPACE
+    assert lib.fd_cnn_wgrad_noalloc(a, 8, a, 8, ok, a, None) == P.FD_ERR_INVALID_ARG
+    assert lib.fd_cnn_wgrad_noalloc(None, 16, a, 16, ok, a, None) == P.FD_ERR_INVALID_ARG
+    assert lib.fd_cnn_wgrad_noalloc(a, 16, a, 16, ok, None, None) == P.FD_ERR_INVALID_ARG
+    assert lib.fd_cnn_wgrad_noalloc(a, 16, a, 16, None, a, None) == P.FD_ERR_INVALID_ARG
+
+
 def test_gradient_entry_points_reject_null_context():
     lib = P.lib()
     u64 = ctypes.c_uint64(0)
