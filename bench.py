@@ -41,7 +41,8 @@ sys.path.insert(0, str(ROOT))
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 TRAFFIC_SUMMARY = ROOT / "profiles" / "acoustic3d_tiled_592cubed_traffic.md"
 KERNEL_SOURCES = [ROOT / "paper_1608_03984_amd" / "csrc" / f
-                  for f in ("fd_acoustic_tiled.h", "fd_acoustic.hip", "fd_acoustic_hi.hip")]
+                  for f in ("fd_acoustic_tiled.h", "fd_acoustic.hip", "fd_acoustic_hi.hip",
+                            "fd_acoustic_top.hip")]
 BYTES_PER_POINT = 16           # read u^n, u^{n-1}, dt^2 v^2; write u^{n+1}
 ORDERS = (4, 8, 12, 16)
 
@@ -67,6 +68,7 @@ def parse():
                              "learned"),
                     default="acoustic")
     ap.add_argument("--interval", type=int, default=0)
+    ap.add_argument("--group", type=int, default=4)
     ap.add_argument("--fwi-steps", type=int, default=1200)
     ap.add_argument("--models", type=int, default=200)
     ap.add_argument("--windows", type=int, default=4)
@@ -494,9 +496,45 @@ def fwi_bench(args):
     Jdev.zero_()
     t_grad = timed(gradient, ev)
     J_grad = float(Jdev.item())
-    say(f"# gradient of {S} shots in {t_grad:.2f} s")
+    say(f"# gradient of {S} shots in {t_grad:.2f} s (one shot at a time)")
     finite = bool(torch.isfinite(g).all().item())
     s.close()
+    del s
+    torch.cuda.empty_cache()
+    # the same gradient with G shots per context: each group's checkpointed
+    # forward runs, adjoints and imaging advance G shots in shared launches
+    G = args.group
+    grouped = None
+    if G > 1 and S % G == 0:
+        sg = Solver(3, p.shape, p.spacing, p.nbl, p.so, p.dt, vel0, p.eta, nshots=G,
+                    max_points=G * (1 + nrec), device=dev)
+        g2 = torch.zeros(sg.field_shape, dtype=torch.float32, device=dev)
+        dobs_g = [torch.cat(dobs[k:k + G], dim=1).contiguous() for k in range(0, S, G)]
+
+        def gradient_grouped():
+            g2.zero_()
+            for j, k in enumerate(range(0, S, G)):
+                sg.forward_checkpointed_shots(nt, srcs[k:k + G], [wav] * G, [p.rec] * G,
+                                              interval=args.interval)
+                tr = sg._ck_traces   # [nt][G nrec], shot k's columns k nrec .. (k+1) nrec
+                P.fd_misfit(tr.data_ptr(), dobs_g[j].data_ptr(), tr.numel(), tr.data_ptr(),
+                            Jdev.data_ptr(), st)
+                sg.gradient_shots(tr, wrt="vel", accumulate_into=g2)
+                info["group_store_gb"] = sg._ck["bytes"] / 1e9
+
+        Jdev.zero_()
+        t_g = timed(gradient_grouped, ev)
+        grouped = {"shots_per_context": G, "gradient_s": round(t_g, 3),
+                   "gpts": round(S * npts * nt / t_g / 1e9, 3),
+                   "speedup_vs_one_at_a_time": round(t_grad / t_g, 3),
+                   "store_gb_per_context": round(info["group_store_gb"], 1),
+                   "bitwise_equal_to_one_at_a_time": bool(torch.equal(g, g2)),
+                   "misfit": float(Jdev.item())}
+        say(f"# gradient of {S} shots in {t_g:.2f} s ({G} shots per context), "
+            f"equal bits: {grouped['bitwise_equal_to_one_at_a_time']}")
+        sg.close()
+        del sg, g2, dobs_g
+        torch.cuda.empty_cache()
     # central differences along the normalised gradient
     d = (g / g.abs().max()).cpu().numpy()
     J0 = misfit(survey(vel0), dobs)
@@ -528,6 +566,7 @@ def fwi_bench(args):
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "whole gradient (algorithmic bytes of every pass / wall time)"},
         "finite": finite,
+        "grouped": grouped,
     }
     print(json.dumps(line), flush=True)
 

@@ -95,8 +95,9 @@ typedef struct fd_grid {
     double dt;           /* time step in seconds */
 } fd_grid;
 
-/* Device pointers to float32 fields on the padded shape.  They are read only
- * by fd_setup and may be released once `stream` has passed it. */
+/* Device pointers to float32 fields on the padded shape (dense
+ * [Nz][Ny][Nx]).  They are read only by fd_setup and may be released once it
+ * has returned. */
 typedef struct fd_model {
     const float* vel;     /* P velocity v (m/s), v > 0; m = 1/v^2 */
     const float* eta;     /* damping rate (1/s) of u_tt + eta u_t = v^2 (lap u + q);
@@ -124,13 +125,15 @@ typedef struct fd_ctx fd_ctx;
 int32_t fd_workspace_bytes(const fd_grid* grid, int32_t max_points, uint64_t* bytes);
 
 /* Validates the grid, derives the per-point coefficients the time loop reads
- * (dt^2 v^2, eta dt/2 and, for TTI, the Thomsen and rotation factors) into
- * `workspace` (device, 256-byte aligned, at least fd_workspace_bytes), checks
- * the model (finite, v > 0, TTI: delta <= epsilon) and the CFL bound of
- * Eq. (stability) at the model's fastest speed (for TTI the horizontal P
- * speed v sqrt(1 + 2 epsilon)), and sets the wavefields to zero.  This call
- * synchronises `stream` once to read the model reduction back.  On success
- * *out receives a context; the workspace must stay allocated until
+ * (dt^2 v^2, eta dt/2 and, for VTI and TTI, the Thomsen and rotation factors
+ * of Eq. (TTI) and Eq. (DiffOp)) into `workspace` (device, 256-byte aligned,
+ * at least fd_workspace_bytes), checks the model (finite, v > 0, TTI:
+ * delta <= epsilon) and the CFL bound of Eq. (stability) at the model's
+ * fastest speed (for TTI the horizontal P speed v sqrt(1 + 2 epsilon)), and
+ * sets the wavefields to zero.  The coefficients are computed in FP64 on the
+ * host from the FP32 model (copied there) and rounded once to FP32; the call
+ * therefore synchronises `stream` and returns when the workspace is ready.
+ * On success *out receives a context; the workspace must stay allocated until
  * fd_destroy. */
 int32_t fd_setup(const fd_grid* grid, const fd_model* model, void* workspace,
                  uint64_t workspace_bytes, int32_t max_points, void* stream, fd_ctx** out);
@@ -194,8 +197,10 @@ int32_t fd_triad_config(float* a, const float* b, const float* c, float s, int64
  * tiled 3D kernel reads dt^2 v^2 (and the damping coefficient) once per tile
  * for a group of shots, so the bytes per shot-point fall from 16 towards 12.
  * Fields of shot k are selected with fd_get_shot_field / fd_set_shot_field;
- * fd_forward, the adjoint and the gradient entry points accept only
- * single-shot contexts.
+ * such a context steps with fd_forward_shots and forms the gradient of all
+ * its shots with fd_forward_checkpointed_shots / fd_gradient_shots (below);
+ * fd_forward, fd_adjoint, fd_forward_checkpointed and fd_gradient accept
+ * only single-shot contexts.
  */
 
 /* Workspace bytes for a context of nshots wavefields (1 <= nshots <= 4096)
@@ -245,7 +250,14 @@ int32_t fd_set_shot_field(fd_ctx* ctx, int32_t shot, int32_t which, const float*
  * dense fields plus interval + 2 padded volumes plus one dense FP64 field;
  * compute: at most two forward runs and one adjoint run.
  *
- * TTI contexts return FD_ERR_UNSUPPORTED from these calls.
+ * A context of several shots (fd_setup_shots) runs these steps for all of its
+ * shots in the same launches (fd_forward_checkpointed_shots,
+ * fd_gradient_shots), the tiled kernel advancing up to two shots per block on
+ * shared reads of dt^2 v^2 and the damping coefficient; the store then holds
+ * every shot's checkpoints, accelerations, adjoint levels and imaging sums,
+ * and the gradient is the sum over the shots.
+ *
+ * TTI and VTI contexts return FD_ERR_UNSUPPORTED from these calls.
  */
 
 /* fd_gradient wrt selectors. */
@@ -258,7 +270,8 @@ int32_t fd_set_shot_field(fd_ctx* ctx, int32_t shot, int32_t which, const float*
 /* Bytes of the caller-owned checkpoint store for nt steps with a checkpoint
  * every `interval` steps (interval <= 0: the memory-minimising choice, about
  * sqrt(2 nt) scaled by the padded/dense volume ratio; *interval_out receives
- * the value used and may be NULL).  Host computation only. */
+ * the value used and may be NULL), for all shots of the context (nshots times
+ * the single-shot store, with the same interval).  Host computation only. */
 int32_t fd_checkpoint_bytes(const fd_ctx* ctx, int32_t nt, int32_t interval, uint64_t* bytes,
                             int32_t* interval_out);
 
@@ -285,6 +298,26 @@ int32_t fd_forward_checkpointed(fd_ctx* ctx, int32_t nt, const fd_points* src,
 int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_points* adj,
                     int32_t interval, void* store, uint64_t store_bytes, int32_t wrt,
                     float* grad, float* wavelet_grad, void* stream);
+
+/* fd_forward_checkpointed and fd_gradient for a context of several shots:
+ * the points of all shots one after another with per-shot counts, as in
+ * fd_forward_shots (src->n = sum of src_counts; traces rec->data [nt][rec->n];
+ * sensitivities adj->data [nt][adj->n] with adj_counts per shot; dJ/dq
+ * wavelet_grad [nt][src->n]).  grad receives the sum over the shots of their
+ * gradients, formed shot by shot in shot order (bitwise the result of one
+ * fd_gradient per shot on single-shot contexts, the later ones with
+ * FD_GRAD_ACCUMULATE).  On a single-shot context the counts may be NULL and
+ * these are fd_forward_checkpointed and fd_gradient.  Errors as those, plus
+ * FD_ERR_INVALID_ARG when counts are missing or do not sum to n. */
+int32_t fd_forward_checkpointed_shots(fd_ctx* ctx, int32_t nt, const fd_points* src,
+                                      const int32_t* src_counts, const fd_points* rec,
+                                      const int32_t* rec_counts, int32_t interval, void* store,
+                                      uint64_t store_bytes, void* stream);
+int32_t fd_gradient_shots(fd_ctx* ctx, int32_t nt, const fd_points* src,
+                          const int32_t* src_counts, const fd_points* adj,
+                          const int32_t* adj_counts, int32_t interval, void* store,
+                          uint64_t store_bytes, int32_t wrt, float* grad, float* wavelet_grad,
+                          void* stream);
 
 /* The least-squares misfit of full-waveform inversion (the objective whose
  * gradient fd_gradient returns when given res as the trace sensitivities):
@@ -423,7 +456,9 @@ int32_t fd_restrict(fd_ctx* ctx, int32_t which, int32_t stride, float* dst, void
  * FD_OPT_ZCHUNK: z-planes per thread block of the tiled 3D kernels (0 = auto).
  * FD_OPT_TILE: (x, y) tile of the tiled 3D acoustic kernel: 0 = 64x8 with 256
  *   threads, 1 = 64x16 with 256, 2 = 64x8 with 512, 3 = 64x16 with 512,
- *   -1 = the default for the space order (and shot count).
+ *   -1 = the default for the space order (and shot count); of the tiled TTI
+ *   kernel: 0 = 64x8 with 512 threads (default, also -1), 1 = 64x4 with 256.
+ *   FD_ERR_UNSUPPORTED for VTI (one tile shape).
  * FD_OPT_SHOTS_PER_BLOCK: shots a block of the tiled 3D acoustic kernel
  *   advances together (1, 2 or 4; 0 = default; 2 and 4 need tile 0 or 2).
  * FD_OPT_DAMPING_PROFILE: 1 (default) = when fd_setup found the 3D damping

@@ -60,7 +60,7 @@ EXPORTS = (
     "fd_get_shot_field", "fd_set_shot_field", "fd_cnn_packed_elems", "fd_cnn_pack", "fd_cnn_conv",
     "fd_cnn_wgrad_scratch", "fd_cnn_wgrad", "fd_cnn_loss_grad", "fd_cnn_adam", "fd_cnn_features",
     "fd_cnn_correct", "fd_cnn_residual", "fd_restrict", "fd_triad_config",
-    "fd_cnn_wgrad_noalloc",
+    "fd_cnn_wgrad_noalloc", "fd_forward_checkpointed_shots", "fd_gradient_shots",
 )
 
 
@@ -128,6 +128,11 @@ def lib() -> ctypes.CDLL:
             "fd_checkpoint_bytes": (i32, [vp, i32, i32, u64p, ctypes.POINTER(i32)]),
             "fd_forward_checkpointed": (i32, [vp, i32, pp, pp, i32, vp, ctypes.c_uint64, vp]),
             "fd_gradient": (i32, [vp, i32, pp, pp, i32, vp, ctypes.c_uint64, i32, vp, vp, vp]),
+            "fd_forward_checkpointed_shots": (i32, [vp, i32, pp, ctypes.POINTER(i32), pp,
+                                                    ctypes.POINTER(i32), i32, vp, ctypes.c_uint64,
+                                                    vp]),
+            "fd_gradient_shots": (i32, [vp, i32, pp, ctypes.POINTER(i32), pp, ctypes.POINTER(i32),
+                                        i32, vp, ctypes.c_uint64, i32, vp, vp, vp]),
             "fd_adjoint": (i32, [vp, i32, pp, pp, vp]),
             "fd_misfit": (i32, [vp, vp, ctypes.c_int64, vp, vp, vp]),
             "fd_workspace_bytes_shots": (i32, [gp, i32, i32, u64p]),
@@ -369,6 +374,37 @@ def fd_forward_shots(ctx, nt: int, src_coords, src_counts, src_data_ptr, rec_coo
                                   ctypes.c_void_p(stream))
     del keep_s, keep_r, keep_sc, keep_rc
     _check(code, "fd_forward_shots", ctx)
+
+
+def fd_forward_checkpointed_shots(ctx, nt: int, src_coords, src_counts, src_data_ptr,
+                                  rec_coords, rec_counts, rec_data_ptr, interval: int,
+                                  store_ptr: int, store_bytes: int, stream: int):
+    sp, keep_s = _points(src_coords, src_data_ptr)
+    rp, keep_r = _points(rec_coords, rec_data_ptr)
+    sc, keep_sc = _counts(src_counts)
+    rc, keep_rc = _counts(rec_counts)
+    code = lib().fd_forward_checkpointed_shots(ctx, int(nt), ctypes.byref(sp) if sp else None, sc,
+                                               ctypes.byref(rp) if rp else None, rc,
+                                               int(interval), ctypes.c_void_p(store_ptr),
+                                               int(store_bytes), ctypes.c_void_p(stream))
+    del keep_s, keep_r, keep_sc, keep_rc
+    _check(code, "fd_forward_checkpointed_shots", ctx)
+
+
+def fd_gradient_shots(ctx, nt: int, src_coords, src_counts, src_data_ptr, adj_coords, adj_counts,
+                      adj_data_ptr, interval: int, store_ptr: int, store_bytes: int, wrt: int,
+                      grad_ptr: int, wavelet_grad_ptr: int, stream: int):
+    sp, keep_s = _points(src_coords, src_data_ptr)
+    ap, keep_a = _points(adj_coords, adj_data_ptr)
+    sc, keep_sc = _counts(src_counts)
+    ac, keep_ac = _counts(adj_counts)
+    code = lib().fd_gradient_shots(ctx, int(nt), ctypes.byref(sp) if sp else None, sc,
+                                   ctypes.byref(ap) if ap else None, ac, int(interval),
+                                   ctypes.c_void_p(store_ptr), int(store_bytes), int(wrt),
+                                   ctypes.c_void_p(grad_ptr), ctypes.c_void_p(wavelet_grad_ptr or 0),
+                                   ctypes.c_void_p(stream))
+    del keep_s, keep_a, keep_sc, keep_ac
+    _check(code, "fd_gradient_shots", ctx)
 
 
 def fd_get_shot_field(ctx, shot: int, which: int, dst_ptr: int, stream: int):

@@ -14,8 +14,9 @@ INCLUDE = ROOT / "include"
 OBJDIR = ROOT / "_build"
 LIB = PKG / "libfd.so"
 
-SOURCES = ["fd_acoustic_hi.hip", "fd_acoustic.hip", "fd_tti.hip", "fd_vti.hip", "fd_abi.cpp",
-           "fd_common.hip", "fd_adjoint.hip", "fd_cnn.hip", "fd_probe.hip"]
+SOURCES = ["fd_acoustic_hi.hip", "fd_acoustic_top.hip", "fd_acoustic.hip", "fd_tti.hip",
+           "fd_vti.hip", "fd_abi.cpp", "fd_common.hip", "fd_adjoint.hip", "fd_cnn.hip",
+           "fd_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -35,6 +36,7 @@ FLAGS = [
 # default).
 EXTRA = {
     "fd_acoustic_hi.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
+    "fd_acoustic_top.hip": ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"],
 }
 
 
@@ -51,7 +53,7 @@ def _compile(src: str) -> Path:
 def build(verbose: bool = False) -> Path:
     """Compile every source for gfx950 and link libfd.so next to this file."""
     OBJDIR.mkdir(exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), 10)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB.with_name(LIB.name + ".tmp")
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp),

@@ -8,11 +8,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "fd_internal.h"
@@ -193,7 +195,8 @@ struct Carve {
     }
 };
 
-int min_tile_y() { return 8; }
+// The damping flags are sized for the smallest tile height of any kernel.
+int min_tile_y() { return fd::kMinTileRows; }
 
 constexpr int32_t kMaxShots = 4096;
 
@@ -450,8 +453,20 @@ double cell_volume(const fd_ctx* ctx) {
     return ctx->g.ndim == 3 ? h[0] * h[1] * h[2] : h[0] * h[2];
 }
 
-// Coefficient part of an acoustic launch (fields set per step).
-fd::AcousticStep acoustic_params(const fd_ctx* ctx) {
+// Shots a block of the tiled kernel advances together in plain stepping.
+int ctx_sb(const fd_ctx* ctx) { return ctx->nshots > 1 ? ctx->shots_per_block : 1; }
+
+// Shots per block of the gradient's launches: the context's value, halved
+// until the tiled kernel has an acceleration-output variant for it.
+int grad_sb(const fd_ctx* ctx) {
+    int sb = ctx_sb(ctx);
+    while (sb > 1 && !fd::acc_built(ctx->tile_cfg, sb)) sb /= 2;
+    return sb;
+}
+
+// Coefficient part of an acoustic launch (fields set per step) for sb shots
+// per block.
+fd::AcousticStep acoustic_params(const fd_ctx* ctx, int sb) {
     fd::AcousticStep p;
     std::memset(&p, 0, sizeof(p));
     p.A = ctx->A;
@@ -473,31 +488,34 @@ fd::AcousticStep acoustic_params(const fd_ctx* ctx) {
     }
     p.nshots = ctx->nshots;
     p.shot_stride = ctx->L.volume;
-    const int sb = ctx->nshots > 1 ? ctx->shots_per_block : 1;
     tile_grid(ctx, ctx->tile_y, ctx->zchunk_opt, ctx->radius, (ctx->nshots + sb - 1) / sb, &p,
               nullptr);
     return p;
 }
 
-// One acoustic stencil launch: up <- step(uc, up), optionally storing A L uc.
+// One acoustic stencil launch over every shot: up <- step(uc, up),
+// optionally storing A L uc (volumes of shot k at + k * volume).
 hipError_t acoustic_stencil(const fd_ctx* ctx, fd::AcousticStep& p, const float* uc, float* up,
-                            float* acc, hipStream_t s) {
+                            float* acc, int sb, hipStream_t s) {
     p.uc = uc;
     p.up = up;
     p.acc = acc;
-    return fd::launch_acoustic(p, ctx->g.ndim, ctx->radius, ctx->variant, ctx->tile_cfg,
-                               ctx->nshots > 1 ? ctx->shots_per_block : 1, s);
+    return fd::launch_acoustic(p, ctx->g.ndim, ctx->radius, ctx->variant, ctx->tile_cfg, sb, s);
 }
 
-// Checkpoint store layout (all regions 256-byte aligned):
-//   ck[2 * nck]  dense fields (u^{n-1}, u^n) at n = 0, I, 2I, ...
-//   acc[I]       padded volumes: accelerations of one segment
-//   mu[2]        padded volumes: adjoint levels
-//   gpart        padded volume: partial sum of the imaging condition over at
-//                most kFlushSteps adjoint steps
-//   gsum         dense field: sum of the flushed partial sums
+// Checkpoint store layout for S = nshots wavefields (all regions 256-byte
+// aligned):
+//   ck[S][2 * nck]  dense fields (u^{n-1}, u^n) at n = 0, I, 2I, ... per shot
+//   acc[I][S]       padded volumes: accelerations of one segment, the S
+//                   shots of a step one after another
+//   mu[2][S]        padded volumes: adjoint levels
+//   gpart[S]        padded volumes: partial sums of the imaging condition over
+//                   at most kFlushSteps adjoint steps
+//   gsum[S]         dense fields: sums of the flushed partial sums
+// With S = 1 this is the single-shot store.
 struct Store {
     int nck = 0;
+    int nshots = 1;
     int64_t dense = 0;       // floats per dense field (rounded to 64)
     float* ck = nullptr;
     float* acc = nullptr;
@@ -505,22 +523,27 @@ struct Store {
     float* gpart = nullptr;
     float* gsum = nullptr;
     uint64_t bytes = 0;
-    float* ckf(int k) const { return ck + (int64_t)k * dense; }
-    float* slot(const fd_ctx* ctx, int i) const { return acc + (int64_t)i * ctx->L.volume; }
+    float* ckf(int shot, int k) const { return ck + ((int64_t)shot * 2 * nck + k) * dense; }
+    float* slot(const fd_ctx* ctx, int i) const {
+        return acc + (int64_t)i * nshots * ctx->L.volume;
+    }
 };
 
 Store plan_store(const fd_ctx* ctx, int nt, int interval, char* base) {
     Store st;
     const Layout& L = ctx->L;
+    const uint64_t S = (uint64_t)ctx->nshots;
+    st.nshots = ctx->nshots;
     st.nck = nt > 0 ? (nt + interval - 1) / interval : 0;
     st.dense = round_up((int64_t)L.nx * L.ny * L.nz, 64);
     Carve cv;
-    const uint64_t o_ck = cv.take((uint64_t)(2 * st.nck) * st.dense * sizeof(float));
-    const uint64_t o_acc = cv.take((uint64_t)interval * L.volume * sizeof(float));
-    const uint64_t o_mu0 = cv.take((uint64_t)L.volume * sizeof(float));
-    const uint64_t o_mu1 = cv.take((uint64_t)L.volume * sizeof(float));
-    const uint64_t o_gp = cv.take((uint64_t)L.volume * sizeof(float));
-    const uint64_t o_gs = cv.take((uint64_t)st.dense * sizeof(float));
+    const uint64_t vol = (uint64_t)L.volume * sizeof(float);
+    const uint64_t o_ck = cv.take(S * (uint64_t)(2 * st.nck) * st.dense * sizeof(float));
+    const uint64_t o_acc = cv.take((uint64_t)interval * S * vol);
+    const uint64_t o_mu0 = cv.take(S * vol);
+    const uint64_t o_mu1 = cv.take(S * vol);
+    const uint64_t o_gp = cv.take(S * vol);
+    const uint64_t o_gs = cv.take(S * (uint64_t)st.dense * sizeof(float));
     st.bytes = cv.off;
     if (base) {
         st.ck = reinterpret_cast<float*>(base + o_ck);
@@ -546,10 +569,182 @@ int resolve_interval(const fd_ctx* ctx, int nt, int interval) {
 
 hipError_t refresh_flags(fd_ctx* ctx, hipStream_t s) {
     if (!ctx->damping || ctx->g.ndim != 3) return hipSuccess;
+    if (ctx->tile_y < min_tile_y()) return hipErrorInvalidValue;  // flags sized for min_tile_y
     const Layout& L = ctx->L;
     const int ntx = (L.nx + fd::kTileX - 1) / fd::kTileX;
     const int nty = (L.ny + ctx->tile_y - 1) / ctx->tile_y;
     return fd::launch_damping_flags(ctx->sig, ctx->dflag, L, ctx->tile_y, ntx, nty, s);
+}
+
+// ---------------------------------------------------------------------------
+// Setup on the host: the per-point coefficients are derived in FP64 from the
+// FP32 model and rounded once to FP32 (section 4.1 weights aside, these are
+// the factors of Eq. (Acou) and Eq. (TTI) with Eq. (DiffOp)).
+// ---------------------------------------------------------------------------
+
+// Host threads of the setup passes.
+int host_threads(int64_t n) {
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int nt = (int)std::min<unsigned>(hw ? hw : 1, 32);
+    return n < ((int64_t)1 << 16) ? 1 : nt;
+}
+
+// Runs f(t, i0, i1) for thread t = 0 .. host_threads(n) - 1 over consecutive
+// ranges covering [0, n).
+template <class F>
+void parallel_for(int64_t n, F f) {
+    const int nt = host_threads(n);
+    if (nt <= 1) {
+        f(0, (int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t chunk = (n + nt - 1) / nt;
+    for (int t = 0; t < nt; ++t) {
+        const int64_t a = t * chunk, b = std::min(n, a + chunk);
+        if (a < b) th.emplace_back(f, t, a, b);
+    }
+    for (auto& t : th) t.join();
+}
+
+// Copy one dense FP32 model field (device) to the host.
+hipError_t fetch_field(const float* dev, int64_t n, std::vector<float>& host) {
+    host.resize((size_t)n);
+    return hipMemcpy(host.data(), dev, (size_t)n * sizeof(float), hipMemcpyDeviceToHost);
+}
+
+// Upload a dense host field into the padded volume `vol` through the dense
+// staging area `stage` (stream-ordered; the caller keeps `host` alive until
+// the stream has passed the copy).
+hipError_t upload_field(const std::vector<float>& host, float* stage, float* vol, const Layout& L,
+                        hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(stage, host.data(), host.size() * sizeof(float),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = fd::launch_unpack(stage, vol, L, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // stage is reused by the next field
+    return e;
+}
+
+struct ModelCheck {
+    double vmax = 0.0;  // fastest speed: v, or v sqrt(1 + 2 eps) for VTI and TTI
+    bool bad = false;   // a non-finite or out-of-range value
+    bool dgt = false;   // delta > epsilon somewhere
+};
+
+// Derives A = dt^2 v^2, s = eta dt / 2, e = 1 + 2 eps, d = sqrt(1 + 2 delta)
+// and the six G_zbar_zbar weights
+//   c1 = sin^2(th) cos^2(ph), c2 = sin^2(th) sin^2(ph), c3 = cos^2(th),
+//   c4 = sin(2 ph) sin^2(th), c5 = sin(ph) sin(2 th), c6 = cos(ph) sin(2 th)
+// in FP64 on the host, rounds each once to FP32 and uploads it into its
+// volume.  `stage` is a device area of at least nx ny nz floats.
+hipError_t derive_coefficients(fd_ctx* ctx, const fd_model* m, float* stage, hipStream_t s,
+                               ModelCheck& chk) {
+    const Layout& L = ctx->L;
+    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
+    const double dt = ctx->g.dt;
+    std::vector<float> vel, a, b, out0, out1;
+    hipError_t e = fetch_field(m->vel, n, vel);
+    if (e != hipSuccess) return e;
+    // body(i) returns flag bits for point i; a pass returns their OR
+    auto flag_pass = [&](auto body) {
+        std::vector<unsigned char> part((size_t)host_threads(n), 0);
+        parallel_for(n, [&](int t, int64_t i0, int64_t i1) {
+            unsigned char bd = 0;
+            for (int64_t i = i0; i < i1; ++i) bd |= body(i);
+            part[(size_t)t] = bd;
+        });
+        unsigned char all = 0;
+        for (unsigned char c : part) all |= c;
+        return all;
+    };
+    // A = dt^2 v^2
+    out0.resize((size_t)n);
+    unsigned char fl = flag_pass([&](int64_t i) -> unsigned char {
+        const double v = vel[i];
+        out0[i] = (float)(dt * dt * v * v);
+        return (v > 0.0 && std::isfinite(v)) ? 0 : 1;
+    });
+    chk.bad |= fl != 0;
+    e = upload_field(out0, stage, ctx->A, L, s);
+    if (e != hipSuccess) return e;
+    // the largest finite sp(i)
+    auto max_speed = [&](auto sp) {
+        std::vector<double> part((size_t)host_threads(n), 0.0);
+        parallel_for(n, [&](int t, int64_t i0, int64_t i1) {
+            double mx = 0.0;
+            for (int64_t i = i0; i < i1; ++i) {
+                const double v = sp(i);
+                if (std::isfinite(v) && v > mx) mx = v;
+            }
+            part[(size_t)t] = mx;
+        });
+        double mx = 0.0;
+        for (double v : part) mx = std::max(mx, v);
+        return mx;
+    };
+    if (ctx->e) {  // VTI and TTI: e = 1 + 2 eps, d = sqrt(1 + 2 delta)
+        e = fetch_field(m->epsilon, n, a);
+        if (e == hipSuccess) e = fetch_field(m->delta, n, b);
+        if (e != hipSuccess) return e;
+        out1.resize((size_t)n);
+        fl = flag_pass([&](int64_t i) -> unsigned char {
+            const double ep = a[i], de = b[i];
+            const double ev = 1.0 + 2.0 * ep, d2 = 1.0 + 2.0 * de;
+            out0[i] = (float)ev;
+            out1[i] = (float)std::sqrt(std::max(d2, 0.0));
+            unsigned char r = 0;
+            if (!std::isfinite(ep) || !std::isfinite(de) || !(ev > 0.0) || !(d2 > 0.0)) r |= 1;
+            if (de > ep) r |= 2;
+            return r;
+        });
+        chk.bad |= (fl & 1) != 0;
+        chk.dgt = (fl & 2) != 0;
+        e = upload_field(out0, stage, ctx->e, L, s);
+        if (e == hipSuccess) e = upload_field(out1, stage, ctx->d, L, s);
+        if (e != hipSuccess) return e;
+        chk.vmax = max_speed([&](int64_t i) {
+            return (double)vel[i] * std::sqrt(std::max(1.0 + 2.0 * (double)a[i], 0.0));
+        });
+    } else {
+        chk.vmax = max_speed([&](int64_t i) { return (double)vel[i]; });
+    }
+    vel.clear();
+    vel.shrink_to_fit();
+    if (ctx->damping) {  // s = eta dt / 2
+        e = fetch_field(m->eta, n, a);
+        if (e != hipSuccess) return e;
+        fl = flag_pass([&](int64_t i) -> unsigned char {
+            const double et = a[i];
+            out0[i] = (float)(0.5 * dt * et);
+            return (et >= 0.0 && std::isfinite(et)) ? 0 : 1;
+        });
+        chk.bad |= fl != 0;
+        e = upload_field(out0, stage, ctx->sig, L, s);
+        if (e != hipSuccess) return e;
+    }
+    if (ctx->tti) {  // the weights of Dxx, Dyy, Dzz, Dxy, Dyz, Dxz in G_zbar_zbar
+        e = fetch_field(m->theta, n, a);
+        if (e == hipSuccess) e = fetch_field(m->phi, n, b);
+        if (e != hipSuccess) return e;
+        std::vector<float> c[6];
+        for (auto& v : c) v.resize((size_t)n);
+        fl = flag_pass([&](int64_t i) -> unsigned char {
+            const double th = a[i], ph = b[i];
+            const double st = std::sin(th), ct = std::cos(th), sp = std::sin(ph), cp = std::cos(ph);
+            const double st2 = st * st;
+            c[0][i] = (float)(st2 * cp * cp);
+            c[1][i] = (float)(st2 * sp * sp);
+            c[2][i] = (float)(ct * ct);
+            c[3][i] = (float)(2.0 * sp * cp * st2);
+            c[4][i] = (float)(sp * 2.0 * st * ct);
+            c[5][i] = (float)(cp * 2.0 * st * ct);
+            return (std::isfinite(th) && std::isfinite(ph)) ? 0 : 1;
+        });
+        chk.bad |= fl != 0;
+        for (int k = 0; k < 6 && e == hipSuccess; ++k) e = upload_field(c[k], stage, ctx->c[k], L, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -628,10 +823,11 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
     ctx->max_points = max_points;
     ctx->cur = 1;
     ctx->variant = 0;
-    ctx->tile_cfg = nshots > 1 ? shots_tile(ctx->radius) : default_tile(ctx->radius);
+    ctx->tile_cfg = tti || vti ? 0
+                    : nshots > 1 ? shots_tile(ctx->radius) : default_tile(ctx->radius);
     ctx->zchunk_opt = 0;
-    ctx->tile_y = tti ? fd::tti_tile_y(ctx->radius)
-                      : vti ? fd::vti_tile_y(ctx->radius) : fd::acoustic_tile_y(ctx->tile_cfg);
+    ctx->tile_y = tti ? fd::tti_tile_y(ctx->tile_cfg)
+                      : vti ? fd::vti_tile_y() : fd::acoustic_tile_y(ctx->tile_cfg);
     ctx->nsrc_dev = ctx->nrec_dev = -1;
     ctx->flags_stale = false;
     ctx->ck_store = nullptr;
@@ -651,23 +847,11 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
         delete ctx;
         return FD_ERR_DEVICE;
     }
-    fd::SetupArgs sa;
-    std::memset(&sa, 0, sizeof(sa));
-    sa.vel = model->vel;
-    sa.eta = model->eta;
-    sa.eps = model->epsilon;
-    sa.delta = model->delta;
-    sa.theta = tti ? model->theta : nullptr;
-    sa.phi = tti ? model->phi : nullptr;
-    sa.dt = (float)grid->dt;
-    sa.A = ctx->A;
-    sa.sig = ctx->damping ? ctx->sig : nullptr;
-    sa.e = ctx->e;
-    sa.d = ctx->d;
-    for (int k = 0; k < 6; ++k) sa.c[k] = ctx->c[k];
-    sa.reduce = ctx->reduce;
-    sa.L = L;
-    he = fd::launch_setup(sa, s);
+    // coefficients in FP64 on the host (the first wavefield level is the
+    // staging area of the uploads and is cleared again afterwards)
+    ModelCheck chk;
+    he = derive_coefficients(ctx, model, ctx->u[0], s, chk);
+    if (he == hipSuccess) he = fd::launch_fill_zero(ctx->u[0], L.volume * nshots, s);
     if (he == hipSuccess) he = refresh_flags(ctx, s);
     const bool try_sep = ctx->damping && grid->ndim == 3;
     if (he == hipSuccess && try_sep)
@@ -681,11 +865,11 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
         delete ctx;
         return FD_ERR_DEVICE;
     }
-    if (red[1]) {
+    if (chk.bad) {
         delete ctx;
         return FD_ERR_NONFINITE;
     }
-    if (red[2]) {
+    if (chk.dgt) {
         delete ctx;
         return FD_ERR_INVALID_ARG;  // delta > epsilon: unstable pseudo-acoustic mode
     }
@@ -695,13 +879,12 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
         std::memcpy(&smax, &red[5], sizeof(float));
         ctx->sep_ok = smax > 0.f && dmax <= std::ldexp(smax, -20);
     }
-    float vmax;
-    std::memcpy(&vmax, &red[0], sizeof(float));
-    if (!(vmax > 0.f)) {
+    const double vmax = chk.vmax;
+    if (!(vmax > 0.0)) {
         delete ctx;
         return FD_ERR_NONFINITE;
     }
-    if (grid->dt > cfl_dt(grid, (double)vmax) * (1.0 + 1e-12)) {
+    if (grid->dt > cfl_dt(grid, vmax) * (1.0 + 1e-12)) {
         delete ctx;
         return FD_ERR_UNSTABLE_DT;
     }
@@ -733,8 +916,15 @@ int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value) {
             ctx->zchunk_opt = (int)value;
             return FD_OK;
         case FD_OPT_TILE: {
-            if (ctx->tti || ctx->vti)
-                return fail(ctx, FD_ERR_UNSUPPORTED, "the tile option applies to acoustic");
+            if (ctx->vti) return fail(ctx, FD_ERR_UNSUPPORTED, "the VTI kernel has one tile shape");
+            if (ctx->tti) {
+                const int v = value < 0 ? 0 : (int)value;
+                if (v > 1) return fail(ctx, FD_ERR_INVALID_ARG, "TTI tile configuration is 0..1");
+                ctx->tile_cfg = v;
+                ctx->tile_y = fd::tti_tile_y(v);
+                ctx->flags_stale = true;  // rebuilt on the caller's stream by fd_forward
+                return FD_OK;
+            }
             const int v = value < 0 ? (ctx->nshots > 1 ? shots_tile(ctx->radius)
                                                        : default_tile(ctx->radius))
                                     : (int)value;
@@ -863,10 +1053,10 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
             ctx->cur = 1 - ctx->cur;
         }
     } else if (!ctx->tti) {
-        fd::AcousticStep p = acoustic_params(ctx);
+        fd::AcousticStep p = acoustic_params(ctx, 1);
         for (int n = 0; n < nt; ++n) {
             float* un = ctx->u[1 - ctx->cur];  // holds u^{n-1}, receives u^{n+1}
-            he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, s);
+            he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, 1, s);
             if (he == hipSuccess && nsrc)
                 he = fd::launch_inject(un, ctx->A, sig, spts, nsrc, src->data + (size_t)n * nsrc,
                                        scale, ctx->L, nd, ctx->L.volume, s);
@@ -907,7 +1097,7 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
             p.rc = ctx->r[ctx->cur];
             p.pp = pn;
             p.rp = rn;
-            he = fd::launch_tti(p, ctx->radius, ctx->variant, s);
+            he = fd::launch_tti(p, ctx->radius, ctx->variant, ctx->tile_cfg, s);
             if (he == hipSuccess && nsrc) {
                 const float* q = src->data + (size_t)n * nsrc;
                 he = fd::launch_inject(pn, ctx->A, sig, spts, nsrc, q, scale, ctx->L, 3,
@@ -928,7 +1118,7 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
 
 int32_t fd_checkpoint_bytes(const fd_ctx* ctx, int32_t nt, int32_t interval, uint64_t* bytes,
                             int32_t* interval_out) {
-    if (!ctx || !bytes || nt < 0 || ctx->nshots > 1) return FD_ERR_INVALID_ARG;
+    if (!ctx || !bytes || nt < 0) return FD_ERR_INVALID_ARG;
     if (ctx->tti || ctx->vti) return FD_ERR_UNSUPPORTED;
     const int I = resolve_interval(ctx, nt, interval);
     *bytes = plan_store(ctx, nt, I, nullptr).bytes;
@@ -946,11 +1136,30 @@ int32_t check_store(fd_ctx* ctx, int nt, int I, void* store, uint64_t store_byte
     return FD_OK;
 }
 
-// Forward steps n0 .. n1-1 from the held state, storing the acceleration of
-// step n into slot n - n0 when `slots` is set and sampling receivers when
-// `rec` is set.
-hipError_t forward_segment(fd_ctx* ctx, fd::AcousticStep& p, const Store* slots, int n0, int n1,
-                           const fd_points* src, int nsrc, const fd_points* rec, int nrec,
+// Per-shot point counts of a multi-shot call must cover the points exactly;
+// a single-shot context takes none (all points in its one shot).
+int32_t check_counts(fd_ctx* ctx, const int32_t* k, int n, const char* what) {
+    if (ctx->nshots == 1) {
+        if (k && n != k[0])
+            return fail(ctx, FD_ERR_INVALID_ARG, std::string(what) + " counts do not sum to n");
+        return FD_OK;
+    }
+    if (n == 0) return FD_OK;
+    if (!k) return fail(ctx, FD_ERR_INVALID_ARG, std::string(what) + " counts missing");
+    int64_t t = 0;
+    for (int i = 0; i < ctx->nshots; ++i) {
+        if (k[i] < 0) return fail(ctx, FD_ERR_INVALID_ARG, std::string(what) + " count < 0");
+        t += k[i];
+    }
+    if (t != n) return fail(ctx, FD_ERR_INVALID_ARG, std::string(what) + " counts do not sum to n");
+    return FD_OK;
+}
+
+// Forward steps n0 .. n1-1 of every shot from the held state, storing the
+// accelerations of step n into slot n - n0 when `slots` is set and sampling
+// receivers when `nrec` > 0.
+hipError_t forward_segment(fd_ctx* ctx, fd::AcousticStep& p, int sb, const Store* slots, int n0,
+                           int n1, const fd_points* src, int nsrc, const fd_points* rec, int nrec,
                            hipStream_t s) {
     const int nd = ctx->g.ndim;
     const float scale = (float)(1.0 / cell_volume(ctx));
@@ -959,7 +1168,7 @@ hipError_t forward_segment(fd_ctx* ctx, fd::AcousticStep& p, const Store* slots,
     for (int n = n0; n < n1 && he == hipSuccess; ++n) {
         float* un = ctx->u[1 - ctx->cur];
         float* acc = slots ? slots->slot(ctx, n - n0) : nullptr;
-        he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, acc, s);
+        he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, acc, sb, s);
         if (he == hipSuccess && nsrc) {
             const float* q = src->data + (size_t)n * nsrc;
             he = fd::launch_inject(un, ctx->A, sig, ctx->pts, nsrc, q, scale, ctx->L, nd,
@@ -977,15 +1186,16 @@ hipError_t forward_segment(fd_ctx* ctx, fd::AcousticStep& p, const Store* slots,
     return he;
 }
 
-// One adjoint step in mu = dt^2 v^2 lambda: mu^k from (mu^{k+1}, mu^{k+2}) by
-// the forward stencil, then B R^T d'^{k-1} / (1 + s) injected at the
-// receivers (the forward injection without the 1 / prod(h) source scaling),
-// and dJ/dq^{k-1} = S mu^k / prod(h) sampled at the sources.
-hipError_t adjoint_step(fd_ctx* ctx, fd::AcousticStep& p, const float* mu1, float* mu2, int k,
-                        int nsrc, float* qgrad, const fd_points* adj, int nadj, hipStream_t s) {
+// One adjoint step in mu = dt^2 v^2 lambda for every shot: mu^k from
+// (mu^{k+1}, mu^{k+2}) by the forward stencil, then B R^T d'^{k-1} / (1 + s)
+// injected at the receivers (the forward injection without the 1 / prod(h)
+// source scaling), and dJ/dq^{k-1} = S mu^k / prod(h) sampled at the sources.
+hipError_t adjoint_step(fd_ctx* ctx, fd::AcousticStep& p, int sb, const float* mu1, float* mu2,
+                        int k, int nsrc, float* qgrad, const fd_points* adj, int nadj,
+                        hipStream_t s) {
     const int nd = ctx->g.ndim;
     const float* sig = ctx->damping ? ctx->sig : nullptr;
-    hipError_t he = acoustic_stencil(ctx, p, mu1, mu2, nullptr, s);
+    hipError_t he = acoustic_stencil(ctx, p, mu1, mu2, nullptr, sb, s);
     if (he == hipSuccess && nadj)
         he = fd::launch_inject(mu2, ctx->A, sig, ctx->pts + nsrc, nadj,
                                adj->data + (size_t)(k - 1) * nadj, 1.f, ctx->L, nd, ctx->L.volume,
@@ -996,15 +1206,28 @@ hipError_t adjoint_step(fd_ctx* ctx, fd::AcousticStep& p, const float* mu1, floa
     return he;
 }
 
+// Dense checkpoint k of every shot from / into the held level `f`.
+hipError_t pack_shots(const fd_ctx* ctx, const float* f, const Store& st, int k, hipStream_t s) {
+    hipError_t he = hipSuccess;
+    for (int i = 0; i < ctx->nshots && he == hipSuccess; ++i)
+        he = fd::launch_pack(f + (int64_t)i * ctx->L.volume, st.ckf(i, k), ctx->L, s);
+    return he;
+}
+hipError_t unpack_shots(const fd_ctx* ctx, const Store& st, int k, float* f, hipStream_t s) {
+    hipError_t he = hipSuccess;
+    for (int i = 0; i < ctx->nshots && he == hipSuccess; ++i)
+        he = fd::launch_unpack(st.ckf(i, k), f + (int64_t)i * ctx->L.volume, ctx->L, s);
+    return he;
+}
+
 }  // namespace
 
-int32_t fd_forward_checkpointed(fd_ctx* ctx, int32_t nt, const fd_points* src,
-                                const fd_points* rec, int32_t interval, void* store,
-                                uint64_t store_bytes, void* stream) {
+int32_t fd_forward_checkpointed_shots(fd_ctx* ctx, int32_t nt, const fd_points* src,
+                                      const int32_t* src_counts, const fd_points* rec,
+                                      const int32_t* rec_counts, int32_t interval, void* store,
+                                      uint64_t store_bytes, void* stream) {
     if (!ctx) return FD_ERR_INVALID_ARG;
     ctx->err.clear();
-    if (ctx->nshots > 1)
-        return fail(ctx, FD_ERR_INVALID_ARG, "a context of several shots steps with fd_forward_shots");
     if (ctx->tti || ctx->vti)
         return fail(ctx, FD_ERR_UNSUPPORTED, "gradients are built for acoustic only");
     if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
@@ -1014,12 +1237,17 @@ int32_t fd_forward_checkpointed(fd_ctx* ctx, int32_t nt, const fd_points* src,
     const int nsrc = src ? src->n : 0, nrec = rec ? rec->n : 0;
     if ((int64_t)nsrc + nrec > ctx->max_points)
         return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
+    rc = check_counts(ctx, src_counts, nsrc, "source");
+    if (rc == FD_OK) rc = check_counts(ctx, rec_counts, nrec, "receiver");
+    if (rc != FD_OK) return rc;
     const int I = resolve_interval(ctx, nt, interval);
     rc = check_store(ctx, nt, I, store, store_bytes);
     if (rc != FD_OK) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool multi = ctx->nshots > 1;
     rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nrec, rec ? rec->coords : nullptr,
-                     "source", "receiver", s);
+                     "source", "receiver", s, multi && nsrc ? src_counts : nullptr,
+                     multi && nrec ? rec_counts : nullptr);
     if (rc != FD_OK) return rc;
     ctx->ck_store = nullptr;
     hipError_t he = hipSuccess;
@@ -1028,16 +1256,18 @@ int32_t fd_forward_checkpointed(fd_ctx* ctx, int32_t nt, const fd_points* src,
         if (he != hipSuccess) return hip_fail(ctx, he, "damping flags");
         ctx->flags_stale = false;
     }
-    for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume, s);
+    for (int k = 0; k < 2 && he == hipSuccess; ++k)
+        he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume * ctx->nshots, s);
     const Store st = plan_store(ctx, nt, I, static_cast<char*>(store));
-    fd::AcousticStep p = acoustic_params(ctx);
+    const int sb = grad_sb(ctx);
+    fd::AcousticStep p = acoustic_params(ctx, sb);
     for (int j = 0; j < st.nck && he == hipSuccess; ++j) {
         const int n0 = j * I, n1 = n0 + I < nt ? n0 + I : nt;
-        he = fd::launch_pack(ctx->u[1 - ctx->cur], st.ckf(2 * j), ctx->L, s);
-        if (he == hipSuccess) he = fd::launch_pack(ctx->u[ctx->cur], st.ckf(2 * j + 1), ctx->L, s);
+        he = pack_shots(ctx, ctx->u[1 - ctx->cur], st, 2 * j, s);
+        if (he == hipSuccess) he = pack_shots(ctx, ctx->u[ctx->cur], st, 2 * j + 1, s);
         if (he == hipSuccess)
-            he = forward_segment(ctx, p, j == st.nck - 1 ? &st : nullptr, n0, n1, src, nsrc, rec,
-                                 nrec, s);
+            he = forward_segment(ctx, p, sb, j == st.nck - 1 ? &st : nullptr, n0, n1, src, nsrc,
+                                 rec, nrec, s);
     }
     if (he != hipSuccess) return hip_fail(ctx, he, "checkpointed forward");
     ctx->ck_store = store;
@@ -1047,13 +1277,24 @@ int32_t fd_forward_checkpointed(fd_ctx* ctx, int32_t nt, const fd_points* src,
     return FD_OK;
 }
 
-int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_points* adj,
-                    int32_t interval, void* store, uint64_t store_bytes, int32_t wrt,
-                    float* grad, float* wavelet_grad, void* stream) {
+int32_t fd_forward_checkpointed(fd_ctx* ctx, int32_t nt, const fd_points* src,
+                                const fd_points* rec, int32_t interval, void* store,
+                                uint64_t store_bytes, void* stream) {
+    if (!ctx) return FD_ERR_INVALID_ARG;
+    if (ctx->nshots > 1)
+        return fail(ctx, FD_ERR_INVALID_ARG,
+                    "a context of several shots uses fd_forward_checkpointed_shots");
+    return fd_forward_checkpointed_shots(ctx, nt, src, nullptr, rec, nullptr, interval, store,
+                                         store_bytes, stream);
+}
+
+int32_t fd_gradient_shots(fd_ctx* ctx, int32_t nt, const fd_points* src,
+                          const int32_t* src_counts, const fd_points* adj,
+                          const int32_t* adj_counts, int32_t interval, void* store,
+                          uint64_t store_bytes, int32_t wrt, float* grad, float* wavelet_grad,
+                          void* stream) {
     if (!ctx) return FD_ERR_INVALID_ARG;
     ctx->err.clear();
-    if (ctx->nshots > 1)
-        return fail(ctx, FD_ERR_INVALID_ARG, "gradients are single-shot contexts");
     if (ctx->tti || ctx->vti)
         return fail(ctx, FD_ERR_UNSUPPORTED, "gradients are built for acoustic only");
     const bool accumulate = (wrt & FD_GRAD_ACCUMULATE) != 0;
@@ -1070,41 +1311,59 @@ int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_poin
     const int nsrc = src ? src->n : 0, nadj = adj ? adj->n : 0;
     if ((int64_t)nsrc + nadj > ctx->max_points)
         return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
+    rc = check_counts(ctx, src_counts, nsrc, "source");
+    if (rc == FD_OK) rc = check_counts(ctx, adj_counts, nadj, "adjoint source");
+    if (rc != FD_OK) return rc;
     rc = check_store(ctx, nt, I, store, store_bytes);
     if (rc != FD_OK) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool multi = ctx->nshots > 1;
     rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nadj, adj ? adj->coords : nullptr,
-                     "source", "adjoint source", s);
+                     "source", "adjoint source", s, multi && nsrc ? src_counts : nullptr,
+                     multi && nadj ? adj_counts : nullptr);
     if (rc != FD_OK) return rc;
     const Store st = plan_store(ctx, nt, I, static_cast<char*>(store));
+    const int S = ctx->nshots;
+    const int64_t vol = ctx->L.volume;
     hipError_t he = hipSuccess;
-    for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(st.mu[k], ctx->L.volume, s);
-    if (he == hipSuccess) he = fd::launch_fill_zero(st.gpart, ctx->L.volume, s);
-    if (he == hipSuccess) he = fd::launch_fill_zero(st.gsum, st.dense, s);
+    for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(st.mu[k], vol * S, s);
+    if (he == hipSuccess) he = fd::launch_fill_zero(st.gpart, vol * S, s);
+    if (he == hipSuccess) he = fd::launch_fill_zero(st.gsum, st.dense * S, s);
     int pending = 0;  // adjoint steps accumulated in gpart since the last flush
     auto imaged = [&]() -> hipError_t {  // one more term in gpart: flush every kFlushSteps
         if (++pending < kFlushSteps) return hipSuccess;
         pending = 0;
-        return fd::launch_flush_gradient(st.gpart, st.gsum, ctx->L, s);
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < S && e == hipSuccess; ++i)
+            e = fd::launch_flush_gradient(st.gpart + i * vol, st.gsum + i * st.dense, ctx->L, s);
+        return e;
     };
-    fd::AcousticStep p = acoustic_params(ctx);
+    // the separate imaging kernel, shot by shot: gpart += mu a
+    auto image = [&](const float* mu, const float* acc) -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < S && e == hipSuccess; ++i)
+            e = fd::launch_image(mu + i * vol, acc + i * vol, st.gpart + i * vol, ctx->L, s);
+        return e;
+    };
+    const int sb = grad_sb(ctx);
+    fd::AcousticStep p = acoustic_params(ctx, sb);
     // The imaging term mu^{k+1} a^{k+1} is fused into the adjoint step that
-    // produces mu^k (its centre field is mu^{k+1}) on the tiled 64 x 8 kernel;
-    // the first step of a segment has no a^{k+1} in the segment, so the
-    // segment's last term, mu^{n0+1} a^{n0+1}, is imaged by the separate
-    // kernel before the next segment's recomputation overwrites the slots.
-    // The terms enter gpart in the same order and with the same fmaf as the
-    // unfused loop, so both give the same bits.
+    // produces mu^k (its centre field is mu^{k+1}) where the tiled kernel has
+    // that variant; the first step of a segment has no a^{k+1} in the
+    // segment, so the segment's last term, mu^{n0+1} a^{n0+1}, is imaged by
+    // the separate kernel before the next segment's recomputation overwrites
+    // the slots.  The terms enter gpart in the same order and with the same
+    // fmaf as the unfused loop, so both give the same bits.
     const bool fuse = ctx->fuse_image && ctx->g.ndim == 3 && ctx->variant == 0 &&
-                      ctx->tile_cfg == 0;
+                      fd::img_built(ctx->tile_cfg, sb);
     int m = 0;  // st.mu[m] holds mu^{k+1}, st.mu[1-m] mu^{k+2}
     for (int j = st.nck - 1; j >= 0 && he == hipSuccess; --j) {
         const int n0 = j * I, n1 = n0 + I < nt ? n0 + I : nt;
         if (!(j == st.nck - 1 && ctx->ck_last_acc)) {
-            he = fd::launch_unpack(st.ckf(2 * j), ctx->u[1 - ctx->cur], ctx->L, s);
-            if (he == hipSuccess) he = fd::launch_unpack(st.ckf(2 * j + 1), ctx->u[ctx->cur], ctx->L, s);
+            he = unpack_shots(ctx, st, 2 * j, ctx->u[1 - ctx->cur], s);
+            if (he == hipSuccess) he = unpack_shots(ctx, st, 2 * j + 1, ctx->u[ctx->cur], s);
             if (he == hipSuccess)
-                he = forward_segment(ctx, p, &st, n0, n1, src, nsrc, nullptr, 0, s);
+                he = forward_segment(ctx, p, sb, &st, n0, n1, src, nsrc, nullptr, 0, s);
         }
         for (int k = n1; k > n0 && he == hipSuccess; --k) {
             const bool fused = fuse && k < n1;
@@ -1112,28 +1371,43 @@ int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_poin
                 p.img_a = st.slot(ctx, k - n0);  // a^{k+1}
                 p.img_g = st.gpart;
             }
-            he = adjoint_step(ctx, p, st.mu[m], st.mu[1 - m], k, nsrc, wavelet_grad, adj, nadj, s);
+            he = adjoint_step(ctx, p, sb, st.mu[m], st.mu[1 - m], k, nsrc, wavelet_grad, adj,
+                              nadj, s);
             p.img_a = nullptr;
             p.img_g = nullptr;
             if (he == hipSuccess && fused) he = imaged();  // mu^{k+1} a^{k+1}
             if (he == hipSuccess && !fuse) {
-                he = fd::launch_image(st.mu[1 - m], st.slot(ctx, k - 1 - n0), st.gpart, ctx->L, s);
+                he = image(st.mu[1 - m], st.slot(ctx, k - 1 - n0));
                 if (he == hipSuccess) he = imaged();
             }
             m = 1 - m;
         }
         if (he == hipSuccess && fuse && n1 > n0) {  // mu^{n0+1} a^{n0+1}
-            he = fd::launch_image(st.mu[m], st.slot(ctx, 0), st.gpart, ctx->L, s);
+            he = image(st.mu[m], st.slot(ctx, 0));
             if (he == hipSuccess) he = imaged();
         }
     }
     ctx->ck_last_acc = false;  // the segment slots now hold the first segment
-    if (he == hipSuccess && pending) he = fd::launch_flush_gradient(st.gpart, st.gsum, ctx->L, s);
-    if (he == hipSuccess)
-        he = fd::launch_finish_gradient(st.gsum, ctx->A, grad, ctx->L, ctx->g.dt, wrt == FD_WRT_VEL,
-                                        accumulate ? 1 : 0, s);
+    if (he == hipSuccess && pending)
+        for (int i = 0; i < S && he == hipSuccess; ++i)
+            he = fd::launch_flush_gradient(st.gpart + i * vol, st.gsum + i * st.dense, ctx->L, s);
+    // shot by shot into grad: the bits of one fd_gradient per shot with
+    // FD_GRAD_ACCUMULATE from the second shot on
+    for (int i = 0; i < S && he == hipSuccess; ++i)
+        he = fd::launch_finish_gradient(st.gsum + i * st.dense, ctx->A, grad, ctx->L, ctx->g.dt,
+                                        wrt == FD_WRT_VEL, (accumulate || i > 0) ? 1 : 0, s);
     if (he != hipSuccess) return hip_fail(ctx, he, "gradient");
     return FD_OK;
+}
+
+int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_points* adj,
+                    int32_t interval, void* store, uint64_t store_bytes, int32_t wrt,
+                    float* grad, float* wavelet_grad, void* stream) {
+    if (!ctx) return FD_ERR_INVALID_ARG;
+    if (ctx->nshots > 1)
+        return fail(ctx, FD_ERR_INVALID_ARG, "a context of several shots uses fd_gradient_shots");
+    return fd_gradient_shots(ctx, nt, src, nullptr, adj, nullptr, interval, store, store_bytes,
+                             wrt, grad, wavelet_grad, stream);
 }
 
 int32_t fd_misfit(const float* d, const float* d_obs, int64_t n, float* res, double* J,
@@ -1170,9 +1444,9 @@ int32_t fd_adjoint(fd_ctx* ctx, int32_t nt, const fd_points* adj, const fd_point
         ctx->flags_stale = false;
     }
     for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume, s);
-    fd::AcousticStep p = acoustic_params(ctx);
+    fd::AcousticStep p = acoustic_params(ctx, 1);
     for (int k = nt; k >= 1 && he == hipSuccess; --k) {
-        he = adjoint_step(ctx, p, ctx->u[ctx->cur], ctx->u[1 - ctx->cur], k, nsrc,
+        he = adjoint_step(ctx, p, 1, ctx->u[ctx->cur], ctx->u[1 - ctx->cur], k, nsrc,
                           out ? out->data : nullptr, adj, nadj, s);
         ctx->cur = 1 - ctx->cur;
     }
@@ -1195,27 +1469,14 @@ int32_t fd_forward_shots(fd_ctx* ctx, int32_t nt, const fd_points* src, const in
     const int nsrc = src ? src->n : 0, nrec = rec ? rec->n : 0;
     if ((int64_t)nsrc + nrec > ctx->max_points)
         return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
-    // per-shot counts must cover the points exactly
-    auto check_counts = [&](const int32_t* k, int n, const char* what) -> int32_t {
-        if (n == 0) return FD_OK;
-        if (!k) return fail(ctx, FD_ERR_INVALID_ARG, std::string(what) + " counts missing");
-        int64_t t = 0;
-        for (int i = 0; i < ctx->nshots; ++i) {
-            if (k[i] < 0) return fail(ctx, FD_ERR_INVALID_ARG, std::string(what) + " count < 0");
-            t += k[i];
-        }
-        if (t != n)
-            return fail(ctx, FD_ERR_INVALID_ARG, std::string(what) + " counts do not sum to n");
-        return FD_OK;
-    };
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int nd = ctx->g.ndim;
     if (keep) {
         // the shots of the points are those of the last upload
         rc = keep_points(ctx, nsrc, nrec);
     } else {
-        rc = check_counts(src_counts, nsrc, "source");
-        if (rc == FD_OK) rc = check_counts(rec_counts, nrec, "receiver");
+        rc = check_counts(ctx, src_counts, nsrc, "source");
+        if (rc == FD_OK) rc = check_counts(ctx, rec_counts, nrec, "receiver");
         if (rc == FD_OK)
             rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nrec,
                              rec ? rec->coords : nullptr, "source", "receiver", s,
@@ -1234,10 +1495,11 @@ int32_t fd_forward_shots(fd_ctx* ctx, int32_t nt, const fd_points* src, const in
     if (he != hipSuccess) return hip_fail(ctx, he, "zero state");
     const float scale = (float)(1.0 / cell_volume(ctx));
     const float* sig = ctx->damping ? ctx->sig : nullptr;
-    fd::AcousticStep p = acoustic_params(ctx);
+    const int sb = ctx_sb(ctx);
+    fd::AcousticStep p = acoustic_params(ctx, sb);
     for (int n = 0; n < nt; ++n) {
         float* un = ctx->u[1 - ctx->cur];
-        he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, s);
+        he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, sb, s);
         if (he == hipSuccess && nsrc)
             he = fd::launch_inject(un, ctx->A, sig, ctx->pts, nsrc, src->data + (size_t)n * nsrc,
                                    scale, ctx->L, nd, ctx->L.volume, s);

@@ -1,7 +1,7 @@
 // fd_acoustic.hip -- acoustic leapfrog stencil kernels of libfd (gfx950):
 // the direct kernel (2D, and a plain 3D variant), the launch dispatch, and
-// the tiled 3D kernel of radius 1-4 (radius 5-8 is instantiated in
-// fd_acoustic_hi.hip).  The update and the tiled kernel's design are
+// the tiled 3D kernel of radius 1-4 (radius 5-6 is instantiated in
+// fd_acoustic_hi.hip, 7-8 in fd_acoustic_top.hip).  The update and the tiled kernel's design are
 // described in fd_acoustic_tiled.h.
 #include "fd_acoustic_tiled.h"
 
@@ -48,6 +48,7 @@ hipError_t launch_direct(const AcousticStep& p, int ndim, hipStream_t s) {
         AcousticStep q = p;
         q.uc = p.uc + shot * p.shot_stride;
         q.up = p.up + shot * p.shot_stride;
+        q.acc = p.acc ? p.acc + shot * p.shot_stride : nullptr;
         if (ndim == 2) {
             hipLaunchKernelGGL((acoustic_direct<2, R>), dim3(gx, (p.L.nz + 3) / 4), dim3(64, 4),
                                0, s, q);
@@ -62,14 +63,16 @@ hipError_t launch_direct(const AcousticStep& p, int ndim, hipStream_t s) {
 }  // namespace
 
 int acoustic_tile_y(int cfg) {
-    static const int ty[4] = {8, 16, 8, 16};
-    return cfg >= 0 && cfg < 4 ? ty[cfg] : 8;
+    return cfg >= 0 && cfg < 4 ? kAcousticTiles[cfg].height() : kAcousticTiles[0].height();
 }
 
 hipError_t launch_acoustic(const AcousticStep& p, int ndim, int radius, int variant, int cfg,
                            int shots_per_block, hipStream_t s) {
     const bool tiled = ndim == 3 && variant == 0;
-    if (tiled && radius >= 5) return launch_acoustic_tiled_hi(p, radius, cfg, shots_per_block, s);
+    if (tiled && (radius == 5 || radius == 6))
+        return launch_acoustic_tiled_r56(p, radius, cfg, shots_per_block, s);
+    if (tiled && (radius == 7 || radius == 8))
+        return launch_acoustic_tiled_r78(p, radius, cfg, shots_per_block, s);
     switch (radius) {
         case 1:
             return tiled ? launch_tiled_cfg<1>(p, cfg, shots_per_block, s)

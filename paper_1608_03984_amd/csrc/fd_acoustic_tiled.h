@@ -85,8 +85,7 @@ constexpr int kRecords = 0x7fffffff;
 
 template <int R, int NW, int VY, int SB, bool ACC, bool SEP, bool IMG>
 struct TiledAcoustic {
-    static_assert(!ACC || SB == 1, "acceleration output is single-shot");
-    static_assert(!IMG || (SB == 1 && !ACC), "fused imaging is a single-shot adjoint step");
+    static_assert(!IMG || !ACC, "fused imaging is an adjoint step (no acceleration output)");
     static constexpr int TY = NW * VY;
     static constexpr int LW = kTileX + 2 * R;
     static constexpr int LH = TY + 2 * R + 1;  // last row: sink for idle halo lanes
@@ -102,10 +101,10 @@ struct TiledAcoustic {
     const float* ub[SB];  // tile origin (x0 - R, y0 - R) of u^n, plane 0, per shot
     float* pb[SB];        // same for u^{n-1} / u^{n+1}
     int lim[SB];          // store record limit: 0 for the padding shots of a ragged group
-    float* cb;            // same for the acceleration output (ACC)
-    const float* iab;     // IMG: the acceleration the output point's u^n images with
-    float* igb;           // IMG: the FP32 partial sum of the imaging condition
-    float ia[2][VY], ig[2][VY];
+    float* cb[SB];        // same for the acceleration output (ACC), per shot
+    const float* iab[SB]; // IMG: the acceleration the output point's u^n images with
+    float* igb[SB];       // IMG: the FP32 partial sum of the imaging condition
+    float ia[2][SB][VY], ig[2][SB][VY];
     const float* ab;      // same for A (shared by the shots)
     const float* sb;      // same for the damping coefficient
     const float* zpl;     // an all-zero plane (ghost plane of A) at the tile origin
@@ -173,11 +172,14 @@ struct TiledAcoustic {
             aa[S][v] = bload<kBufNT>(ra, oc[v]);
         }
         if constexpr (IMG) {
-            const auto ri = rsrc(out ? iab + zo : zpl), rg = rsrc(out ? igb + zo : zpl);
 #pragma unroll
-            for (int v = 0; v < VY; ++v) {
-                ia[S][v] = bload<kBufNT>(ri, oc[v]);
-                ig[S][v] = bload<kBufNT>(rg, oc[v]);
+            for (int s = 0; s < SB; ++s) {
+                const auto ri = rsrc(out ? iab[s] + zo : zpl), rg = rsrc(out ? igb[s] + zo : zpl);
+#pragma unroll
+                for (int v = 0; v < VY; ++v) {
+                    ia[S][s][v] = bload<kBufNT>(ri, oc[v]);
+                    ig[S][s][v] = bload<kBufNT>(rg, oc[v]);
+                }
             }
         }
         const int d = (out && flagbuf != 0) ? 1 : 0;
@@ -262,17 +264,17 @@ struct TiledAcoustic {
             for (int v = 0; v < VY; ++v) bstore_nt(ro, oc[v], nv[v]);
             if constexpr (ACC) {
                 const auto rc = __builtin_amdgcn_make_buffer_rsrc(
-                    cb + (int64_t)z * plane, 0, z >= z0 ? kRecords : 0, 0x00020000);
+                    cb[s] + (int64_t)z * plane, 0, z >= z0 ? lim[s] : 0, 0x00020000);
 #pragma unroll
                 for (int v = 0; v < VY; ++v) bstore_nt(rc, oc[v], av[v]);
             }
             if constexpr (IMG) {
                 // the same fmaf as the separate imaging kernel
                 const auto rg = __builtin_amdgcn_make_buffer_rsrc(
-                    igb + (int64_t)z * plane, 0, z >= z0 ? kRecords : 0, 0x00020000);
+                    igb[s] + (int64_t)z * plane, 0, z >= z0 ? lim[s] : 0, 0x00020000);
 #pragma unroll
                 for (int v = 0; v < VY; ++v)
-                    bstore_nt(rg, oc[v], fmaf(q[s][C][v], ia[S][v], ig[S][v]));
+                    bstore_nt(rg, oc[v], fmaf(q[s][C][v], ia[S][s][v], ig[S][s][v]));
             }
         }
         fetch<S>(z + 2);
@@ -328,10 +330,17 @@ struct TiledAcoustic {
             pb[s] = p.up + se * p.shot_stride + org;
             lim[s] = shot < p.nshots ? kRecords : 0;
         }
-        cb = ACC ? p.acc + org : pb[0];
-        iab = IMG ? p.img_a + org : ab;
-        igb = IMG ? p.img_g + org : pb[0];
         ab = p.A + org;
+#pragma unroll
+        for (int s = 0; s < SB; ++s) {
+            // shot s of the acceleration and imaging volumes (the padding
+            // shots of a ragged group re-read the last shot and store nothing)
+            const int shot = group * SB + s;
+            const int64_t so = (int64_t)(shot < p.nshots ? shot : p.nshots - 1) * p.shot_stride;
+            cb[s] = ACC ? p.acc + so + org : pb[s];
+            iab[s] = IMG ? p.img_a + so + org : ab;
+            igb[s] = IMG ? p.img_g + so + org : pb[s];
+        }
         sb = (p.sig ? p.sig : p.A) + org;
         zpl = p.A + org - (int64_t)kGhostYZ * plane;
         flags = (cflag_t*)p.dflag;
@@ -406,55 +415,57 @@ __global__ __launch_bounds__(64 * NW) void acoustic3d_tiled(AcousticStep p) {
     k.run();
 }
 
-template <int R, int NW, int VY, int SB, bool SEP>
+// Configuration CFG of kAcousticTiles with SB shots per block; the
+// acceleration-output and fused-imaging variants exist where acc_built /
+// img_built say so.
+template <int R, int CFG, int SB, bool SEP>
 hipError_t launch_tiled_sep(const AcousticStep& p, hipStream_t s) {
-    if constexpr (SB == 1) {
-        if (p.acc) {
-            hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, 1, true, SEP, false>),
+    constexpr int NW = kAcousticTiles[CFG].waves, VY = kAcousticTiles[CFG].rows;
+    if (p.acc) {
+        if constexpr (acc_built(CFG, SB)) {
+            hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, SB, true, SEP, false>),
                                dim3(p.nblocks), dim3(64 * NW), 0, s, p);
             return hipGetLastError();
         }
-        if (p.img_a) {
-            // built for the default 64 x 8 tile only (the caller checks)
-            if constexpr (NW == 4 && VY == 2) {
-                hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, 1, false, SEP, true>),
-                                   dim3(p.nblocks), dim3(64 * NW), 0, s, p);
-                return hipGetLastError();
-            }
-            return hipErrorInvalidValue;
-        }
+        return hipErrorInvalidValue;
     }
-    if (p.img_a) return hipErrorInvalidValue;
+    if (p.img_a) {
+        if constexpr (img_built(CFG, SB)) {
+            hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, SB, false, SEP, true>),
+                               dim3(p.nblocks), dim3(64 * NW), 0, s, p);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     hipLaunchKernelGGL((acoustic3d_tiled<R, NW, VY, SB, false, SEP, false>), dim3(p.nblocks),
                        dim3(64 * NW), 0, s, p);
     return hipGetLastError();
 }
 
-template <int R, int NW, int VY, int SB>
-hipError_t launch_tiled(const AcousticStep& p, hipStream_t s) {
-    return p.sx ? launch_tiled_sep<R, NW, VY, SB, true>(p, s)
-                : launch_tiled_sep<R, NW, VY, SB, false>(p, s);
-}
-
 // Tile configurations: 0 = 64 x 8 (4 waves x 2 rows), 1 = 64 x 16 (4 x 4),
 // 2 = 64 x 8 (8 waves x 1 row), 3 = 64 x 16 (8 x 2).  Shots per block 2 and 4
 // are built for configurations 0 and 2.
+template <int R, int CFG, int SB>
+hipError_t launch_tiled_t(const AcousticStep& p, hipStream_t s) {
+    return p.sx ? launch_tiled_sep<R, CFG, SB, true>(p, s)
+                : launch_tiled_sep<R, CFG, SB, false>(p, s);
+}
+
 template <int R>
 hipError_t launch_tiled_cfg(const AcousticStep& p, int cfg, int sb, hipStream_t s) {
     if (sb == 1) {
         switch (cfg) {
-            case 0: return launch_tiled<R, 4, 2, 1>(p, s);
-            case 1: return launch_tiled<R, 4, 4, 1>(p, s);
-            case 2: return launch_tiled<R, 8, 1, 1>(p, s);
-            case 3: return launch_tiled<R, 8, 2, 1>(p, s);
+            case 0: return launch_tiled_t<R, 0, 1>(p, s);
+            case 1: return launch_tiled_t<R, 1, 1>(p, s);
+            case 2: return launch_tiled_t<R, 2, 1>(p, s);
+            case 3: return launch_tiled_t<R, 3, 1>(p, s);
             default: return hipErrorInvalidValue;
         }
     }
-    if (p.acc) return hipErrorInvalidValue;
-    if (cfg == 0 && sb == 2) return launch_tiled<R, 4, 2, 2>(p, s);
-    if (cfg == 0 && sb == 4) return launch_tiled<R, 4, 2, 4>(p, s);
-    if (cfg == 2 && sb == 2) return launch_tiled<R, 8, 1, 2>(p, s);
-    if (cfg == 2 && sb == 4) return launch_tiled<R, 8, 1, 4>(p, s);
+    if (cfg == 0 && sb == 2) return launch_tiled_t<R, 0, 2>(p, s);
+    if (cfg == 0 && sb == 4) return launch_tiled_t<R, 0, 4>(p, s);
+    if (cfg == 2 && sb == 2) return launch_tiled_t<R, 2, 2>(p, s);
+    if (cfg == 2 && sb == 4) return launch_tiled_t<R, 2, 4>(p, s);
     return hipErrorInvalidValue;
 }
 

@@ -45,77 +45,6 @@ __global__ __launch_bounds__(kBlock) void unpack_kernel(const float* __restrict_
     }
 }
 
-// Derive the per-point coefficients the time loop reads, in FP32:
-//   A = (dt v)^2, s = eta dt / 2, for VTI and TTI e = 1 + 2 eps,
-//   d = sqrt(1 + 2 delta), and for TTI
-//   c1 = sin^2(th) cos^2(ph), c2 = sin^2(th) sin^2(ph), c3 = cos^2(th),
-//   c4 = sin(2ph) sin^2(th), c5 = sin(ph) sin(2th), c6 = cos(ph) sin(2th)
-// (the weights of Dxx, Dyy, Dzz, Dxy, Dyz, Dxz in G_zbar_zbar, Eq. (DiffOp)).
-// Also reduces the fastest speed (v, or v sqrt(1 + 2 eps) for VTI and TTI) and flags
-// invalid values and delta > eps.
-__global__ __launch_bounds__(kBlock) void setup_kernel(SetupArgs a) {
-    __shared__ float smax[kBlock / 64];
-    const Layout& L = a.L;
-    const int64_t n = (int64_t)L.nx * L.ny * L.nz;
-    float vmax = 0.f;
-    uint32_t bad = 0, dgt = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
-        const int x = (int)(i % L.nx);
-        const int64_t r = i / L.nx;
-        const int y = (int)(r % L.ny);
-        const int z = (int)(r / L.ny);
-        const int64_t k = vol_index(L, x, y, z);
-        const float v = a.vel[i];
-        if (!(v > 0.f) || !isfinite(v)) bad = 1;
-        const float dv = a.dt * v;
-        a.A[k] = dv * dv;
-        float speed = v;
-        if (a.sig) {
-            const float et = a.eta[i];
-            if (!(et >= 0.f) || !isfinite(et)) bad = 1;
-            a.sig[k] = 0.5f * a.dt * et;
-        }
-        if (a.e) {  // VTI and TTI
-            const float ep = a.eps[i], de = a.delta[i];
-            if (!isfinite(ep) || !isfinite(de)) bad = 1;
-            const float e = 1.f + 2.f * ep;
-            const float d2 = 1.f + 2.f * de;
-            if (!(e > 0.f) || !(d2 > 0.f)) bad = 1;
-            if (de > ep) dgt = 1;
-            a.e[k] = e;
-            a.d[k] = sqrtf(fmaxf(d2, 0.f));
-            speed = v * sqrtf(fmaxf(e, 0.f));
-        }
-        if (a.c[0]) {  // TTI rotation factors
-            const float th = a.theta[i], ph = a.phi[i];
-            if (!isfinite(th) || !isfinite(ph)) bad = 1;
-            float st, ct, sp, cp;
-            sincosf(th, &st, &ct);
-            sincosf(ph, &sp, &cp);
-            const float st2 = st * st;
-            a.c[0][k] = st2 * cp * cp;
-            a.c[1][k] = st2 * sp * sp;
-            a.c[2][k] = ct * ct;
-            a.c[3][k] = 2.f * sp * cp * st2;
-            a.c[4][k] = sp * 2.f * st * ct;
-            a.c[5][k] = cp * 2.f * st * ct;
-        }
-        if (isfinite(speed)) vmax = fmaxf(vmax, speed);
-    }
-    // block reduction of the maximum speed
-    for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off));
-    if ((threadIdx.x & 63) == 0) smax[threadIdx.x >> 6] = vmax;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float m = smax[0];
-        for (int i = 1; i < kBlock / 64; ++i) m = fmaxf(m, smax[i]);
-        atomicMax(&a.reduce[0], __float_as_uint(m));  // non-negative: int order = float order
-    }
-    if (bad) atomicOr(&a.reduce[1], 1u);
-    if (dgt) atomicOr(&a.reduce[2], 1u);
-}
-
 // Damping profiles through the centre point (xc, yc, zc): sx[x] = sig(x, yc,
 // zc), sy[y] = sig(xc, y, zc), sz[z] = sig(xc, yc, z).  For a field that is a
 // sum of per-axis profiles vanishing at the centre (the usual absorbing
@@ -260,12 +189,6 @@ hipError_t launch_pack(const float* vol, float* dense, const Layout& L, hipStrea
 hipError_t launch_unpack(const float* dense, float* vol, const Layout& L, hipStream_t s) {
     hipLaunchKernelGGL(unpack_kernel, dim3(grid_for((int64_t)L.nx * L.ny * L.nz)), dim3(kBlock),
                        0, s, dense, vol, L);
-    return hipGetLastError();
-}
-
-hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(setup_kernel, dim3(grid_for((int64_t)a.L.nx * a.L.ny * a.L.nz)),
-                       dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

@@ -131,25 +131,6 @@ hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t s);
 hipError_t launch_pack(const float* vol, float* dense, const Layout& L, hipStream_t s);
 hipError_t launch_unpack(const float* dense, float* vol, const Layout& L, hipStream_t s);
 
-// setup: derive coefficient volumes from the caller's dense model arrays and
-// reduce the model to {max speed, bad-value flag, delta>eps flag}.
-struct SetupArgs {
-    const float* vel;
-    const float* eta;
-    const float* eps;
-    const float* delta;
-    const float* theta;
-    const float* phi;
-    float dt;
-    float* A;
-    float* sig;     // nullptr when eta is nullptr
-    float* e;       // TTI only
-    float* d;
-    float* c[6];
-    uint32_t* reduce;  // [0] max speed bits, [1] bad flag, [2] delta>eps flag
-    Layout L;
-};
-hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
 // Per-axis damping profiles along the lines through the centre point, then
 // the largest |sig - ((sx + sy) + sz)| and the largest sig over the volume into
 // red[0] and red[1] (float bits).
@@ -211,15 +192,44 @@ hipError_t launch_restrict(const float* u, const Layout& L, int stride, float* o
 // stencils
 hipError_t launch_acoustic(const AcousticStep& p, int ndim, int radius, int variant, int tile_cfg,
                            int shots_per_block, hipStream_t s);
-// The tiled 3D kernel for radius 5-8 (a translation unit of its own).
-hipError_t launch_acoustic_tiled_hi(const AcousticStep& p, int radius, int cfg,
-                                    int shots_per_block, hipStream_t s);
-hipError_t launch_tti(const TTIStep& p, int radius, int variant, hipStream_t s);
+// The tiled 3D kernel for radius 5-6 and 7-8 (translation units of their own,
+// compiled in parallel).
+hipError_t launch_acoustic_tiled_r56(const AcousticStep& p, int radius, int cfg,
+                                     int shots_per_block, hipStream_t s);
+hipError_t launch_acoustic_tiled_r78(const AcousticStep& p, int radius, int cfg,
+                                     int shots_per_block, hipStream_t s);
+hipError_t launch_tti(const TTIStep& p, int radius, int variant, int tile_cfg, hipStream_t s);
 hipError_t launch_vti(const VTIStep& p, int ndim, int radius, int variant, hipStream_t s);
 
-// Tile height (rows) of the tiled acoustic kernel for a tile configuration.
+// Tile shapes of the tiled 3D kernels: the launchers instantiate the kernels
+// from these tables and the host sizes its tile grid and damping flags from
+// the same entries, so the two cannot disagree.
+struct TileShape {
+    int waves;  // waves per block (64 x waves threads)
+    int rows;   // rows each lane owns
+    constexpr int height() const { return waves * rows; }
+};
+// acoustic FD_OPT_TILE configurations 0..3: 64 x 8, 64 x 16, 64 x 8, 64 x 16
+constexpr TileShape kAcousticTiles[4] = {{4, 2}, {4, 4}, {8, 1}, {8, 2}};
+// TTI FD_OPT_TILE configurations 0..1: 64 x 8 (default), 64 x 4
+constexpr TileShape kTTITiles[2] = {{8, 1}, {4, 1}};
+// VTI: 64 x 16
+constexpr TileShape kVTITile = {8, 2};
+// The smallest tile height of any tiled kernel: the damping flags are sized
+// for it.
+constexpr int kMinTileRows = 4;
+// Tiled acoustic variants for gradients (configuration, shots per block):
+// the acceleration output is built with one shot per block in every
+// configuration and with two in configuration 2; the imaging fused into the
+// adjoint step in configuration 0 with one shot and configuration 2 with two.
+constexpr bool acc_built(int cfg, int sb) { return sb == 1 || (cfg == 2 && sb == 2); }
+constexpr bool img_built(int cfg, int sb) {
+    return (cfg == 0 && sb == 1) || (cfg == 2 && sb == 2);
+}
+
+// Tile height (rows) of the tiled kernels for a tile configuration.
 int acoustic_tile_y(int tile_cfg);
-int tti_tile_y(int radius);
-int vti_tile_y(int radius);
+int tti_tile_y(int tile_cfg);
+int vti_tile_y();
 
 }  // namespace fd

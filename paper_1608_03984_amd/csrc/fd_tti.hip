@@ -137,10 +137,7 @@ __device__ __forceinline__ void tstore(__amdgpu_buffer_rsrc_t r, uint32_t off, f
 
 template <int R, int NW, bool SEP>
 struct TiledTTI {
-    // Only the 64 x 8 shape (eight waves) is launched and verified against
-    // the oracle; a 64 x 4 build fails the one-step parity at radius 1.
-    static_assert(NW == 8, "the tiled TTI kernel is verified for 64 x 8 tiles only");
-    static constexpr int TY = NW;
+    static constexpr int TY = NW;  // one row per wave
     static constexpr int LW = kTileX + 2 * R;
     static constexpr int LH = TY + 2 * R;
     static constexpr int FT = (LH + 1) * LW;  // staged field tile (+1 sink row)
@@ -431,13 +428,24 @@ __global__ __launch_bounds__(64 * NW) void tti3d_tiled(TTIStep p) {
     k.run();
 }
 
-template <int R>
+template <int R, int CFG>
 hipError_t launch_tiled(const TTIStep& p, hipStream_t s) {
+    static_assert(kTTITiles[CFG].rows == 1, "the tiled TTI kernel gives each lane one row");
+    constexpr int NW = kTTITiles[CFG].waves;
     if (p.sx)
-        hipLaunchKernelGGL((tti3d_tiled<R, 8, true>), dim3(p.nblocks), dim3(512), 0, s, p);
+        hipLaunchKernelGGL((tti3d_tiled<R, NW, true>), dim3(p.nblocks), dim3(64 * NW), 0, s, p);
     else
-        hipLaunchKernelGGL((tti3d_tiled<R, 8, false>), dim3(p.nblocks), dim3(512), 0, s, p);
+        hipLaunchKernelGGL((tti3d_tiled<R, NW, false>), dim3(p.nblocks), dim3(64 * NW), 0, s, p);
     return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_tiled_cfg(const TTIStep& p, int cfg, hipStream_t s) {
+    switch (cfg) {
+        case 0: return launch_tiled<R, 0>(p, s);
+        case 1: return launch_tiled<R, 1>(p, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int R>
@@ -449,14 +457,13 @@ hipError_t launch_direct(const TTIStep& p, hipStream_t s) {
 
 }  // namespace
 
-int tti_tile_y(int radius) {
-    (void)radius;
-    return 8;  // the tiled kernel's 64 x 8 tiles
+int tti_tile_y(int cfg) {
+    return cfg >= 0 && cfg < 2 ? kTTITiles[cfg].height() : kTTITiles[0].height();
 }
 
-hipError_t launch_tti(const TTIStep& p, int radius, int variant, hipStream_t s) {
+hipError_t launch_tti(const TTIStep& p, int radius, int variant, int cfg, hipStream_t s) {
 #define FD_TCASE(RR) \
-    case RR: return variant == 0 ? launch_tiled<RR>(p, s) : launch_direct<RR>(p, s);
+    case RR: return variant == 0 ? launch_tiled_cfg<RR>(p, cfg, s) : launch_direct<RR>(p, s);
     switch (radius) {
         FD_TCASE(1)
         FD_TCASE(2)

@@ -333,19 +333,19 @@ hipError_t launch_direct(const VTIStep& p, int ndim, hipStream_t s) {
 
 template <int R>
 hipError_t launch_tiled(const VTIStep& p, hipStream_t s) {
+    constexpr int NW = kVTITile.waves, VY = kVTITile.rows;
     if (p.sx)
-        hipLaunchKernelGGL((vti3d_tiled<R, 8, 2, true>), dim3(p.nblocks), dim3(512), 0, s, p);
+        hipLaunchKernelGGL((vti3d_tiled<R, NW, VY, true>), dim3(p.nblocks), dim3(64 * NW), 0, s,
+                           p);
     else
-        hipLaunchKernelGGL((vti3d_tiled<R, 8, 2, false>), dim3(p.nblocks), dim3(512), 0, s, p);
+        hipLaunchKernelGGL((vti3d_tiled<R, NW, VY, false>), dim3(p.nblocks), dim3(64 * NW), 0, s,
+                           p);
     return hipGetLastError();
 }
 
 }  // namespace
 
-int vti_tile_y(int radius) {
-    (void)radius;
-    return 16;  // the tiled kernel's 64 x 16 tiles (8 waves x 2 rows)
-}
+int vti_tile_y() { return kVTITile.height(); }
 
 hipError_t launch_vti(const VTIStep& p, int ndim, int radius, int variant, hipStream_t s) {
     const bool tiled = ndim == 3 && variant == 0;

@@ -177,6 +177,76 @@ class Solver:
         bounds = np.concatenate([[0], np.cumsum(rc)])
         return [traces[:, bounds[k]:bounds[k + 1]] for k in range(ns)]
 
+    def _shot_points(self, nt, src_list, wavelet_list, rec_list):
+        ns = self.nshots
+        srcs = [self._coords(c) if c is not None else np.zeros((0, self.ndim)) for c in src_list]
+        recs = [self._coords(c) if c is not None else np.zeros((0, self.ndim)) for c in rec_list]
+        if len(srcs) != ns or len(recs) != ns or len(wavelet_list) != ns:
+            raise ValueError("one source set, wavelet and receiver set per shot")
+        sc = np.array([len(c) for c in srcs], np.int32)
+        rc = np.array([len(c) for c in recs], np.int32)
+        src = np.concatenate(srcs) if sc.sum() else None
+        rec = np.concatenate(recs) if rc.sum() else None
+        q = None
+        if src is not None:
+            q = torch.cat([_dev(w, self.device).reshape(nt, int(k))
+                           for w, k in zip(wavelet_list, sc)], dim=1).contiguous()
+        return src, sc, rec, rc, q
+
+    def forward_checkpointed_shots(self, nt, src_list, wavelet_list, rec_list, interval=0):
+        """``forward_checkpointed`` for every shot of a context of several
+        shots (per-shot lists as in ``forward_shots``); returns the per-shot
+        traces and keeps the checkpoints ``gradient_shots`` needs."""
+        src, sc, rec, rc, q = self._shot_points(nt, src_list, wavelet_list, rec_list)
+        nbytes, used = B.fd_checkpoint_bytes(self.ctx, nt, interval)
+        store = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (store.data_ptr() + 255) // 256 * 256
+        traces = torch.empty((nt, int(rc.sum())), dtype=torch.float32, device=self.device)
+        B.fd_forward_checkpointed_shots(self.ctx, nt, src, sc if src is not None else None,
+                                        q.data_ptr() if q is not None else 0, rec,
+                                        rc if rec is not None else None,
+                                        traces.data_ptr() if rec is not None else 0, used, ptr,
+                                        nbytes, self.stream)
+        self._ck = dict(store=store, ptr=ptr, bytes=nbytes, interval=used, nt=nt, src=src, q=q,
+                        rec=rec, sc=sc, rc=rc)
+        self._ck_traces = traces
+        bounds = np.concatenate([[0], np.cumsum(rc)])
+        return [traces[:, bounds[k]:bounds[k + 1]] for k in range(self.nshots)]
+
+    def gradient_shots(self, adj_list, wrt="vel", wavelet_grad=False, accumulate_into=None):
+        """Sum over the shots of dJ/dmodel for per-shot trace sensitivities
+        ``adj_list[k]`` [nt][nrec_k] (or one [nt][sum nrec_k] tensor, the
+        layout of the traces) of the last ``forward_checkpointed_shots`` run;
+        returns (gradient [padded field shape], dJ/dwavelet [nt][nsrc]
+        over all sources, or None)."""
+        ck = self._ck
+        nt, src, rec, sc, rc = ck["nt"], ck["src"], ck["rec"], ck["sc"], ck["rc"]
+        if isinstance(adj_list, torch.Tensor):   # already [nt][sum nrec_k]
+            d = adj_list.to(device=self.device, dtype=torch.float32).reshape(nt, int(rc.sum()))
+            d = d.contiguous()
+        else:
+            d = torch.cat([_dev(a, self.device).reshape(nt, int(k))
+                           for a, k in zip(adj_list, rc)], dim=1).contiguous()
+        if accumulate_into is not None:
+            grad = accumulate_into
+            if tuple(grad.shape) != self.field_shape or grad.dtype != torch.float32 \
+                    or not grad.is_contiguous() or not grad.is_cuda:
+                raise ValueError("accumulate_into: contiguous float32 tensor of the field shape")
+        else:
+            grad = torch.empty(self.field_shape, dtype=torch.float32, device=self.device)
+        nsrc = 0 if src is None else src.shape[0]
+        qg = torch.empty((nt, nsrc), dtype=torch.float32, device=self.device) \
+            if wavelet_grad and nsrc else None
+        B.fd_gradient_shots(self.ctx, nt, src, sc if src is not None else None,
+                            ck["q"].data_ptr() if ck["q"] is not None else 0, rec,
+                            rc if rec is not None else None, d.data_ptr(), ck["interval"],
+                            ck["ptr"], ck["bytes"],
+                            (B.FD_WRT_VEL if wrt == "vel" else B.FD_WRT_M)
+                            | (B.FD_GRAD_ACCUMULATE if accumulate_into is not None else 0),
+                            grad.data_ptr(), qg.data_ptr() if qg is not None else 0, self.stream)
+        self._keep_adj = d
+        return grad, qg
+
     def get_field(self, which=B.FD_FIELD_CUR, shot=0):
         out = torch.empty(self.field_shape, dtype=torch.float32, device=self.device)
         B.fd_get_shot_field(self.ctx, shot, which, out.data_ptr(), self.stream)

@@ -272,6 +272,79 @@ def test_gradient_accumulates_over_shots():
     assert e < 2e-4
 
 
+@pytest.mark.parametrize("so,sb,tile,nshots,interval",
+                         [(8, 2, 2, 3, 7), (4, 0, 2, 5, 0), (16, 1, 0, 2, 11), (8, 2, 2, 4, 1),
+                          (2, 4, 2, 3, 9)])
+def test_gradient_shots_equal_single_shot_sum(so, sb, tile, nshots, interval):
+    """A context of several shots forms its checkpointed forward runs,
+    adjoints and imaging in shared launches (two shots per block where the
+    tile configuration has that variant); its traces, wavelet gradients and
+    the summed model gradient equal, bit for bit, one single-shot gradient
+    per shot accumulated in shot order."""
+    from tests.test_gpu_shots import survey
+    p = acoustic_problem(3, (70, 24, 30), 5, so, 50, seed=600 + so)
+    srcs, wavs, recs = survey(p, nshots, seed=so)
+    rng = np.random.default_rng(so + nshots)
+    adjs = [rng.standard_normal((p.nt, len(r))).astype(np.float32) for r in recs]
+    say(f"case: gradient of {nshots} shots so{so} sb{sb} tile{tile} interval{interval}")
+    npts = sum(len(a) for a in srcs) + sum(len(a) for a in recs) + 1
+    s = Solver(3, p.shape, p.spacing, p.nbl, so, p.dt, p.vel, p.eta, nshots=nshots,
+               max_points=npts)
+    s.set_option(P.FD_OPT_TILE, tile)
+    s.set_option(P.FD_OPT_SHOTS_PER_BLOCK, sb)
+    trs = [t.cpu().numpy() for t in s.forward_checkpointed_shots(p.nt, srcs, wavs, recs,
+                                                                  interval=interval)]
+    g, qg = s.gradient_shots(adjs, wrt="vel", wavelet_grad=True)
+    g, qg = g.cpu().numpy(), qg.cpu().numpy()
+    torch.cuda.synchronize()
+    s.close()
+    acc, col = None, 0
+    for k in range(nshots):
+        s1 = Solver(3, p.shape, p.spacing, p.nbl, so, p.dt, p.vel, p.eta, max_points=npts)
+        t1 = s1.forward_checkpointed(p.nt, srcs[k], wavs[k], recs[k] if len(recs[k]) else None,
+                                     interval=interval)
+        assert np.array_equal(trs[k], t1.cpu().numpy()), f"shot {k} traces differ"
+        g1, q1 = s1.gradient(adjs[k], wrt="vel", wavelet_grad=True, accumulate_into=acc)
+        acc = g1
+        ns = len(srcs[k])
+        assert np.array_equal(qg[:, col:col + ns], q1.cpu().numpy()), f"shot {k} dJ/dq differs"
+        col += ns
+        torch.cuda.synchronize()
+        s1.close()
+    assert np.array_equal(g, acc.cpu().numpy())
+    assert np.abs(g).max() > 0
+
+
+def test_gradient_shots_errors():
+    p = acoustic_problem(3, (30, 20, 20), 4, 8, 10, seed=77)
+    say("case: gradient of several shots, error paths")
+    s = Solver(3, p.shape, p.spacing, p.nbl, 8, p.dt, p.vel, p.eta, nshots=2, max_points=8)
+    s1 = from_problem(p, max_points=8)
+    nbytes, used = P.fd_checkpoint_bytes(s.ctx, p.nt, 0)
+    one, used1 = P.fd_checkpoint_bytes(s1.ctx, p.nt, 0)
+    assert used == used1 and 2 * one - 4096 <= nbytes <= 2 * one
+    with pytest.raises(P.FdError) as e:   # a context of several shots needs the _shots calls
+        s.forward_checkpointed(p.nt, p.src, p.wavelet, p.rec)
+    assert e.value.code == P.FD_ERR_INVALID_ARG
+    s.forward_checkpointed_shots(p.nt, [p.src, p.src], [p.wavelet, p.wavelet],
+                                 [p.rec[:1], p.rec[:1]])
+    ck = s._ck
+    grad = torch.empty(s.field_shape, device=s.device)
+    with pytest.raises(P.FdError) as e:   # source counts that do not cover the points
+        P.fd_gradient_shots(s.ctx, p.nt, ck["src"], np.array([1, 0]), ck["q"].data_ptr(), None,
+                            None, 0, ck["interval"], ck["ptr"], ck["bytes"], P.FD_WRT_M,
+                            grad.data_ptr(), 0, s.stream)
+    assert e.value.code == P.FD_ERR_INVALID_ARG
+    with pytest.raises(P.FdError) as e:   # missing counts
+        P.fd_gradient_shots(s.ctx, p.nt, ck["src"], None, ck["q"].data_ptr(), None, None, 0,
+                            ck["interval"], ck["ptr"], ck["bytes"], P.FD_WRT_M, grad.data_ptr(),
+                            0, s.stream)
+    assert e.value.code == P.FD_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    s.close()
+    s1.close()
+
+
 def test_autograd_function():
     """torch.autograd through AcousticModeling: vel.grad and wavelet.grad of
     1/2 |d - dobs|^2 against the oracle."""

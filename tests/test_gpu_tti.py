@@ -15,10 +15,12 @@ from workloads import noise_state, tti_3d  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 
-def gpu_run(p, variant=0, damping_profile=None):
+def gpu_run(p, variant=0, damping_profile=None, tile=0):
     s = from_problem(p)
     if variant:
         s.set_option(P.FD_OPT_KERNEL, variant)
+    if tile:
+        s.set_option(P.FD_OPT_TILE, tile)
     if damping_profile is not None:
         s.set_option(P.FD_OPT_DAMPING_PROFILE, damping_profile)
     tr = s.forward(p.nt, p.src, p.wavelet, p.rec)
@@ -31,11 +33,14 @@ def gpu_run(p, variant=0, damping_profile=None):
 
 
 @pytest.mark.parametrize("so", [2, 4, 8])
-@pytest.mark.parametrize("variant", [0, 1])
-def test_tti_multi_tile_full_run(so, variant):
+@pytest.mark.parametrize("variant,tile", [(0, 0), (0, 1), (1, 0)])
+def test_tti_multi_tile_full_run(so, variant, tile):
+    """60 steps on a grid of several tiles in x and y (ragged in both) with
+    the damping layer: the tiled kernel with 64 x 8 (tile 0) and 64 x 4
+    (tile 1) tiles and the direct kernel (variant 1)."""
     p = tti_problem((80, 26, 22), 6, so, 60, seed=200 + so)
-    say(f"case: tti {p.padded} so{so} variant{variant}")
-    tr, u, r = gpu_run(p, variant)
+    say(f"case: tti {p.padded} so{so} variant{variant} tile{tile}")
+    tr, u, r = gpu_run(p, variant, tile=tile)
     tref, st, peak = oracle_run_with_peak(p, chunk=20)
     et = rel(tr, tref)
     eu = float(np.linalg.norm(u - st[1]) / peak)
@@ -56,12 +61,17 @@ def test_tti_damping_profiles():
 
 
 @pytest.mark.parametrize("so", [2, 4, 8, 12, 16])
-def test_tti_one_step_from_common_state(so):
+@pytest.mark.parametrize("tile", [0, 1])
+def test_tti_one_step_from_common_state(so, tile):
+    """One step from a common noise state at every point, for both tile
+    shapes of the tiled kernel (64 x 8 and 64 x 4)."""
     p = tti_problem((70, 18, 20), 4, so, 1, seed=so)
     shape = p.padded
     st = [noise_state(shape, 20 + k) for k in range(4)]
-    say(f"case: tti one step so{so} {shape}")
+    say(f"case: tti one step so{so} {shape} tile{tile}")
     s = from_problem(p)
+    if tile:
+        s.set_option(P.FD_OPT_TILE, tile)
     for which, f in zip((P.FD_FIELD_PREV, P.FD_FIELD_CUR, P.FD_FIELD_R_PREV, P.FD_FIELD_R_CUR), st):
         s.set_field(which, f)
     s.forward(1, zero_state=False)
