@@ -104,15 +104,22 @@ __global__ __launch_bounds__(256) void tti_direct(TTIStep p) {
 //   an LDS tile), then Dxy f = D1x(gy);
 //   the in-plane parts  Dxx p + Dyy p  and  c1 Dxx f + c2 Dyy f + c4 Dxy f
 //   (c1, c2, c4 of the head plane), parked in an LDS ring until output.
-// f, gx and gy go into per-lane register queues; at output time
+// f, gx and gy go into per-lane register queues of the 2R+1 planes of the
+// output plane's z stencil; at output time
 //   Dzz f = D2z(f queue),  Dxz f = D1z(gx queue),  Dyz f = D1z(gy queue),
 // which is the product-of-first-derivatives form of the mixed terms (the
 // same sum the zero-ghost stencil gives).  G_zbar_zbar f adds c3 Dzz + c5 Dyz
 // + c6 Dxz (c's of the output plane), H p = Laplacian p - G_zbar_zbar p, and
 // the update of Eq. (TTI) writes p^{n+1}, r^{n+1} over p^{n-1}, r^{n-1}.
 //
-// Operands are prefetched two steps ahead into register slots, the z loop is
-// unrolled by the queue period U = 2R+2, loads and stores are raw buffer
+// Registers decide the occupancy of this kernel (six queues of 2R+1 planes
+// per lane), so its operands are single-buffered and loaded half a step
+// ahead, each group as soon as its registers are free: the next head plane's
+// values right after they were staged in LDS, the head plane's c1, c2, c4
+// right after the in-plane parts are formed, and the output plane's fields
+// and coefficients right after the update.  The z loop is unrolled by the
+// queue period 2R+1 so that queue slots are compile-time registers; the LDS
+// ring slot is a block-uniform counter.  Loads and stores are raw buffer
 // accesses with out-of-range offsets for ghost points, and the 2R steps
 // before a chunk only fill the pipeline (their stores have a zero record
 // limit).  Two barriers per step: one after staging p and r, one after
@@ -142,7 +149,7 @@ struct TiledTTI {
     static constexpr int LH = TY + 2 * R;
     static constexpr int FT = (LH + 1) * LW;  // staged field tile (+1 sink row)
     static constexpr int GT = TY * LW;        // gy on the x-extended rows
-    static constexpr int U = 2 * R + 2;
+    static constexpr int U = 2 * R + 1;       // queue period: planes z-R .. z+R
     static constexpr int NHALO = LH * LW - TY * kTileX;
     static constexpr int NH = (NHALO + 64 * NW - 1) / (64 * NW);
     static constexpr int NGX = 2 * R * TY;     // x-halo gy points
@@ -162,18 +169,19 @@ struct TiledTTI {
     int64_t plane;
     int z0, z1, nz, tx, ty, ntx, nty, lane, w, tid;
     int flagbuf;
+    int rslot;              // ring slot of the head plane; the output plane's is rslot + 1
     uint32_t oc;            // own point offset (kOOBt outside the interior)
     uint32_t oh[NH];        // halo element offsets
     int lh[NH];             // halo element LDS index
     bool gx_on;             // this thread computes one x-halo gy point
     int gxf, gxg;           // its f-tile index (row, col) and gy-tile index
     float fqp[U], fqr[U], gxp[U], gxr[U], gyp[U], gyr[U];
-    // slots
-    float hp_c[2], hr_c[2], hp_h[2][NH], hr_h[2][NH], c1h[2], c2h[2], c4h[2];
-    float opp[2], orp[2], oa[2], oe[2], od[2], oc3[2], oc5[2], oc6[2], osg[2];
-    int damp[2];
-    float sxl;  // SEP: this lane's x profile value, its row's y value
-    float syl;
+    // operands, one buffer each (loaded half a step ahead)
+    float hp_c, hr_c, hp_h[NH], hr_h[NH];      // head plane: centre and halo of p, r
+    float c1h, c2h, c4h;                        // head plane: in-plane G_zbar_zbar weights
+    float opp, orp, oa, oe, od, oc3, oc5, oc6, osg;  // output plane
+    int damp;
+    float sxy;  // SEP: this lane's x profile value plus its row's y value
     const __attribute__((address_space(4))) float* szc;
 
     __device__ TiledTTI(const TTIStep& ps, float* lds) : p(ps) {
@@ -189,59 +197,66 @@ struct TiledTTI {
         return flags[((int64_t)z * nty + ty) * ntx + tx];
     }
 
-    template <int S>
-    __device__ __forceinline__ void fetch(int zc) {
-        const int64_t zh = (int64_t)(zc + R) * plane;
-        const auto rp = trsrc(pb + zh), rr = trsrc(rb + zh);
-        hp_c[S] = tload(rp, oc);
-        hr_c[S] = tload(rr, oc);
+    // centre and halo of p and r at head plane zh (beyond the grid: zero
+    // ghost planes of the volume)
+    __device__ __forceinline__ void fetch_head(int zh) {
+        const int64_t o = (int64_t)zh * plane;
+        const auto rp = trsrc(pb + o), rr = trsrc(rb + o);
+        hp_c = tload(rp, oc);
+        hr_c = tload(rr, oc);
 #pragma unroll
         for (int k = 0; k < NH; ++k) {
-            hp_h[S][k] = tload(rp, oh[k]);
-            hr_h[S][k] = tload(rr, oh[k]);
+            hp_h[k] = tload(rp, oh[k]);
+            hr_h[k] = tload(rr, oh[k]);
         }
-        c1h[S] = tload<kNT>(trsrc(cb[0] + zh), oc);
-        c2h[S] = tload<kNT>(trsrc(cb[1] + zh), oc);
-        c4h[S] = tload<kNT>(trsrc(cb[3] + zh), oc);
+    }
+    __device__ __forceinline__ void fetch_head_coef(int zh) {
+        const int64_t o = (int64_t)zh * plane;
+        c1h = tload<kNT>(trsrc(cb[0] + o), oc);
+        c2h = tload<kNT>(trsrc(cb[1] + o), oc);
+        c4h = tload<kNT>(trsrc(cb[3] + o), oc);
+    }
+    // fields and coefficients of output plane zc (steps without output read
+    // the all-zero plane), and its damping flag
+    __device__ __forceinline__ void fetch_out(int zc) {
         const bool out = zc >= z0 && zc < z1;
         const int64_t zo = (int64_t)zc * plane;
-        opp[S] = tload<kNT>(trsrc(out ? ppb + zo : zpl), oc);
-        orp[S] = tload<kNT>(trsrc(out ? rpb + zo : zpl), oc);
-        oa[S] = tload<kNT>(trsrc(out ? ab + zo : zpl), oc);
-        oe[S] = tload<kNT>(trsrc(out ? eb + zo : zpl), oc);
-        od[S] = tload<kNT>(trsrc(out ? db + zo : zpl), oc);
-        oc3[S] = tload<kNT>(trsrc(out ? cb[2] + zo : zpl), oc);
-        oc5[S] = tload<kNT>(trsrc(out ? cb[4] + zo : zpl), oc);
-        oc6[S] = tload<kNT>(trsrc(out ? cb[5] + zo : zpl), oc);
+        opp = tload<kNT>(trsrc(out ? ppb + zo : zpl), oc);
+        orp = tload<kNT>(trsrc(out ? rpb + zo : zpl), oc);
+        oa = tload<kNT>(trsrc(out ? ab + zo : zpl), oc);
+        oe = tload<kNT>(trsrc(out ? eb + zo : zpl), oc);
+        od = tload<kNT>(trsrc(out ? db + zo : zpl), oc);
+        oc3 = tload<kNT>(trsrc(out ? cb[2] + zo : zpl), oc);
+        oc5 = tload<kNT>(trsrc(out ? cb[4] + zo : zpl), oc);
+        oc6 = tload<kNT>(trsrc(out ? cb[5] + zo : zpl), oc);
         const int d = (out && flagbuf != 0) ? 1 : 0;
         flagbuf = flag_of(zc + 1);
-        damp[S] = d;
+        damp = d;
         if constexpr (SEP)
-            osg[S] = d ? szc[zc] : 0.f;  // the z value; the sum is formed at use
+            osg = d ? szc[zc] : 0.f;  // the z value; the sum is formed at use
         else
-            osg[S] = tload(trsrc(d ? sb + zo : zpl), oc);
+            osg = tload(trsrc(d ? sb + zo : zpl), oc);
     }
 
     template <int K>
     __device__ __forceinline__ bool step(int z) {
         if (z >= z1) return false;
-        constexpr int S = K & 1;
-        constexpr int H = (K + 2 * R) % U;
-        constexpr int C = (K + R) % U;
-        constexpr int RH = (K + R) % (R + 1);  // ring slot of the head plane
-        constexpr int RC = K % (R + 1);        // ring slot of the output plane
+        constexpr int H = (K + 2 * R) % U;  // queue slot of the head plane z + R
+        constexpr int C = (K + R) % U;      // queue slot of the output plane z
+        const int rh = rslot, rc = rslot == R ? 0 : rslot + 1;  // ring slots (head, output)
         const int fc = (R + w) * LW + R + lane;  // own point in the field tile
         // stage the head planes of p and r
-        fqp[H] = hp_c[S];
-        fqr[H] = hr_c[S];
-        fp_t[fc] = hp_c[S];
-        fr_t[fc] = hr_c[S];
+        fqp[H] = hp_c;
+        fqr[H] = hr_c;
+        fp_t[fc] = hp_c;
+        fr_t[fc] = hr_c;
 #pragma unroll
         for (int k = 0; k < NH; ++k) {
-            fp_t[lh[k]] = hp_h[S][k];
-            fr_t[lh[k]] = hr_h[S][k];
+            fp_t[lh[k]] = hp_h[k];
+            fr_t[lh[k]] = hr_h[k];
         }
         __syncthreads();
+        fetch_head(z + 1 + R);
 
         // first and second derivatives of the head plane at the own point
         float dxx_p = p.w2x[0] * fp_t[fc], dxx_r = p.w2x[0] * fr_t[fc];
@@ -287,22 +302,21 @@ struct TiledTTI {
             dxy_r = fmaf(p.w1x[j], gr_t[gc + j] - gr_t[gc - j], dxy_r);
         }
         const int rw = w * kTileX + lane;
-        ring[(0 * (R + 1) + RH) * TY * kTileX + rw] = dxx_p + dyy_p;
-        ring[(1 * (R + 1) + RH) * TY * kTileX + rw] =
-            fmaf(c1h[S], dxx_p, fmaf(c2h[S], dyy_p, c4h[S] * dxy_p));
-        ring[(2 * (R + 1) + RH) * TY * kTileX + rw] =
-            fmaf(c1h[S], dxx_r, fmaf(c2h[S], dyy_r, c4h[S] * dxy_r));
+        float* rhp = ring + rh * TY * kTileX + rw;
+        rhp[0 * (R + 1) * TY * kTileX] = dxx_p + dyy_p;
+        rhp[1 * (R + 1) * TY * kTileX] = fmaf(c1h, dxx_p, fmaf(c2h, dyy_p, c4h * dxy_p));
+        rhp[2 * (R + 1) * TY * kTileX] = fmaf(c1h, dxx_r, fmaf(c2h, dyy_r, c4h * dxy_r));
+        fetch_head_coef(z + 1 + R);
 
         // output plane z
-        const float lap_in = ring[(0 * (R + 1) + RC) * TY * kTileX + rw];
-        const float gzin_p = ring[(1 * (R + 1) + RC) * TY * kTileX + rw];
-        const float gzin_r = ring[(2 * (R + 1) + RC) * TY * kTileX + rw];
+        const float* rcp = ring + rc * TY * kTileX + rw;
+        const float lap_in = rcp[0 * (R + 1) * TY * kTileX];
+        const float gzin_p = rcp[1 * (R + 1) * TY * kTileX];
+        const float gzin_r = rcp[2 * (R + 1) * TY * kTileX];
         float dzz_p = p.w2z[0] * fqp[C], dzz_r = p.w2z[0] * fqr[C];
         float dxz_p = 0.f, dxz_r = 0.f, dyz_p = 0.f, dyz_r = 0.f;
 #pragma unroll
         for (int j = 1; j <= R; ++j) {
-            constexpr int dummy = 0;
-            (void)dummy;
             dzz_p = fmaf(p.w2z[j], fqp[(C + j) % U] + fqp[(C + U - j) % U], dzz_p);
             dzz_r = fmaf(p.w2z[j], fqr[(C + j) % U] + fqr[(C + U - j) % U], dzz_r);
             dxz_p = fmaf(p.w1z[j], gxp[(C + j) % U] - gxp[(C + U - j) % U], dxz_p);
@@ -310,25 +324,26 @@ struct TiledTTI {
             dyz_p = fmaf(p.w1z[j], gyp[(C + j) % U] - gyp[(C + U - j) % U], dyz_p);
             dyz_r = fmaf(p.w1z[j], gyr[(C + j) % U] - gyr[(C + U - j) % U], dyz_r);
         }
-        const float gz_p = gzin_p + oc3[S] * dzz_p + oc5[S] * dyz_p + oc6[S] * dxz_p;
-        const float gz_r = gzin_r + oc3[S] * dzz_r + oc5[S] * dyz_r + oc6[S] * dxz_r;
+        const float gz_p = gzin_p + oc3 * dzz_p + oc5 * dyz_p + oc6 * dxz_p;
+        const float gz_r = gzin_r + oc3 * dzz_r + oc5 * dyz_r + oc6 * dxz_r;
         const float h_p = (lap_in + dzz_p) - gz_p;
-        const float fpv = oa[S] * (oe[S] * h_p + od[S] * gz_r);
-        const float frv = oa[S] * (od[S] * h_p + gz_r);
-        const float pc = fqp[C], rc = fqr[C];
-        float pn = (2.f * pc - opp[S]) + fpv;
-        float rn = (2.f * rc - orp[S]) + frv;
-        if (damp[S]) {
+        const float fpv = oa * (oe * h_p + od * gz_r);
+        const float frv = oa * (od * h_p + gz_r);
+        const float pc = fqp[C], rcv = fqr[C];
+        float pn = (2.f * pc - opp) + fpv;
+        float rn = (2.f * rcv - orp) + frv;
+        if (damp) {
             // the profile sum in the same order as the setup's check
-            const float sv = SEP ? (sxl + syl) + osg[S] : osg[S];
-            pn = (2.f * pc - (1.f - sv) * opp[S] + fpv) / (1.f + sv);
-            rn = (2.f * rc - (1.f - sv) * orp[S] + frv) / (1.f + sv);
+            const float sv = SEP ? sxy + osg : osg;
+            pn = (2.f * pc - (1.f - sv) * opp + fpv) / (1.f + sv);
+            rn = (2.f * rcv - (1.f - sv) * orp + frv) / (1.f + sv);
         }
         const int64_t zo = (int64_t)z * plane;
         const int rec = z >= z0 ? kRecordsT : 0;
         tstore(trsrc(ppb + zo, rec), oc, pn);
         tstore(trsrc(rpb + zo, rec), oc, rn);
-        fetch<S>(z + 2);
+        fetch_out(z + 1);
+        rslot = rc;  // the head plane of the next step takes the output plane's slot
         return true;
     }
 
@@ -370,13 +385,12 @@ struct TiledTTI {
         for (int k = 0; k < 6; ++k) cb[k] = p.c[k] + org;
         zpl = p.A + org - (int64_t)kGhostYZ * plane;
         flags = (tflag_t*)p.dflag;
-        sxl = syl = 0.f;
+        sxy = 0.f;
         if constexpr (SEP) {
             // lanes and rows past the interior read the last value (their
             // stores drop)
             szc = (const __attribute__((address_space(4))) float*)p.sz;
-            sxl = p.sx[min(x0 + lane, nx - 1)];
-            syl = p.sy[min(y0 + w, ny - 1)];
+            sxy = p.sx[min(x0 + lane, nx - 1)] + p.sy[min(y0 + w, ny - 1)];
         }
         auto off = [&](int r, int c) -> uint32_t {
             const int y = y0 - R + r, x = x0 - R + c;
@@ -413,16 +427,26 @@ struct TiledTTI {
         for (int i = 0; i < U; ++i) fqp[i] = fqr[i] = gxp[i] = gxr[i] = gyp[i] = gyr[i] = 0.f;
         // 2R pipeline-fill steps: planes z0-R .. z0+R-1 enter as heads
         const int zs = z0 - 2 * R;
+        rslot = 0;
         flagbuf = flag_of(zs);
-        fetch<0>(zs);
-        fetch<1>(zs + 1);
+        fetch_head(zs + R);
+        fetch_head_coef(zs + R);
+        fetch_out(zs);
         for (int zb_ = zs; period(zb_, std::make_integer_sequence<int, U>{}); zb_ += U) {
         }
     }
 };
 
+// Waves per SIMD the compiler is asked to fit (register budget 512 / waves):
+// radius up to 4 with 64 x 8 tiles fits four (128 registers) without
+// spilling, so two blocks share a CU and a 464^3 grid's 464 column blocks
+// are all resident at once; the other shapes keep the compiler's choice.
+template <int R, int NW>
+constexpr int tti_waves_per_simd() { return (R <= 4 && NW == 8) ? 4 : 1; }
+
 template <int R, int NW, bool SEP>
-__global__ __launch_bounds__(64 * NW) void tti3d_tiled(TTIStep p) {
+__global__ __launch_bounds__(64 * NW)
+__attribute__((amdgpu_waves_per_eu(tti_waves_per_simd<R, NW>()))) void tti3d_tiled(TTIStep p) {
     __shared__ float lds[TiledTTI<R, NW, SEP>::LDS_FLOATS];
     TiledTTI<R, NW, SEP> k(p, lds);
     k.run();

@@ -12,11 +12,14 @@ What is asserted:
   * the correction scheme itself works: with the exact residual in place of
     the network, the late traces of receivers outside the source ball match
     the fine solve far better than the plain coarse solve's;
-  * the corrected solver stays stable (finite traces, error within a small
-    factor of the plain coarse solver's).
+  * the corrected solver stays stable (finite traces, whole-run error within
+    10 % of the plain coarse solver's: a trained network that makes the run
+    worse than that is a regression).
 What the trained network gains over the plain coarse solver over a whole run
-is measured and printed; on this workload it is not a gain, so it is
-reported, not asserted.
+is measured and printed; on these small models it is 1.06x on one held-out
+model and 0.98x on the other, so it is reported, not asserted (the
+learned-correction target is not met: its cost, not its accuracy, rules it
+out against a higher-order plain solve).
 """
 import numpy as np
 import pytest
@@ -75,5 +78,5 @@ def test_learned_correction_small():
             f"(gain {e0 / e1:.2f}x); far receivers after step {start}: plain {l0:.4f}, "
             f"learned {l1:.4f}, exact residual {lx:.4f}")
         assert bool(torch.isfinite(tl).all())
-        assert e1 < 1.3 * e0
+        assert e1 < 1.1 * e0
         assert lx < 0.1 * l0
