@@ -459,14 +459,14 @@ def fwi_bench(args):
 
     import paper_1608_03984_amd as P
     st = torch.cuda.current_stream().cuda_stream
-    Jdev = torch.zeros(1, dtype=torch.float64, device=dev)
+    Jdev = torch.zeros(P.FD_MISFIT_DOUBLES, dtype=torch.float64, device=dev)
 
     def misfit(tr, dobs):
         """J = 1/2 sum over shots |d - d_obs|^2 (fd_misfit, residuals in place)."""
         Jdev.zero_()
         for a, b in zip(tr, dobs):
             P.fd_misfit(a.data_ptr(), b.data_ptr(), a.numel(), a.data_ptr(), Jdev.data_ptr(), st)
-        return float(Jdev.item())
+        return float(Jdev[0].item())
 
     t0 = time.perf_counter()
     dobs = survey(p.vel)
@@ -495,7 +495,7 @@ def fwi_bench(args):
     s.gradient(tr, wrt="vel", wavelet_grad=False)
     Jdev.zero_()
     t_grad = timed(gradient, ev)
-    J_grad = float(Jdev.item())
+    J_grad = float(Jdev[0].item())
     say(f"# gradient of {S} shots in {t_grad:.2f} s (one shot at a time)")
     finite = bool(torch.isfinite(g).all().item())
     s.close()
@@ -529,7 +529,7 @@ def fwi_bench(args):
                    "speedup_vs_one_at_a_time": round(t_grad / t_g, 3),
                    "store_gb_per_context": round(info["group_store_gb"], 1),
                    "bitwise_equal_to_one_at_a_time": bool(torch.equal(g, g2)),
-                   "misfit": float(Jdev.item())}
+                   "misfit": float(Jdev[0].item())}
         say(f"# gradient of {S} shots in {t_g:.2f} s ({G} shots per context), "
             f"equal bits: {grouped['bitwise_equal_to_one_at_a_time']}")
         sg.close()

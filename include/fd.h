@@ -119,9 +119,9 @@ typedef struct fd_points {
 typedef struct fd_ctx fd_ctx;
 
 /* Bytes of device workspace fd_setup needs for this grid with room for up to
- * `max_points` sparse points per fd_forward call (sources + receivers).
- * Pure host computation.  Returns FD_ERR_INVALID_ARG / FD_ERR_UNSUPPORTED for
- * grids fd_setup would reject. */
+ * `max_points` sparse points per fd_forward call (sources + receivers,
+ * 0 <= max_points <= 2^27).  Pure host computation.  Returns
+ * FD_ERR_INVALID_ARG / FD_ERR_UNSUPPORTED for grids fd_setup would reject. */
 int32_t fd_workspace_bytes(const fd_grid* grid, int32_t max_points, uint64_t* bytes);
 
 /* Validates the grid, derives the per-point coefficients the time loop reads
@@ -143,7 +143,9 @@ int32_t fd_setup(const fd_grid* grid, const fd_model* model, void* workspace,
  * the new level (Algorithm 1, "Add Source"; for TTI into both p and r), then
  * receivers sampled from the new level into rec->data[n] (TTI: from p).
  * The point-source amplitude q enters as dt^2 v^2 q / (prod h) / (1 + eta dt/2)
- * spread over the multilinear corners.  flags & FD_ZERO_STATE starts from
+ * spread over the multilinear corners; where several points share a corner
+ * their contributions are added in point order, so runs are bitwise
+ * reproducible.  flags & FD_ZERO_STATE starts from
  * zero; otherwise the run continues from the held state (fd_set_field or a
  * previous call).  src or rec may be NULL.  Asynchronous on `stream`, except
  * that new point coordinates are uploaded with one synchronisation.  A call
@@ -322,10 +324,13 @@ int32_t fd_gradient_shots(fd_ctx* ctx, int32_t nt, const fd_points* src,
 /* The least-squares misfit of full-waveform inversion (the objective whose
  * gradient fd_gradient returns when given res as the trace sensitivities):
  * res = d - d_obs elementwise (n FP32 values, device; res may alias d) and
- * *J += 1/2 sum res^2 (J: one device double, accumulated, so the caller
- * clears it; the sum is taken in FP64 because finite differences of J check
- * the gradient).  Asynchronous on `stream`.  FD_ERR_INVALID_ARG for n < 0 or
- * missing pointers. */
+ * J[0] += 1/2 sum res^2.  J is a device array of FD_MISFIT_DOUBLES doubles:
+ * J[0] accumulates (the caller clears it), J[1..] receive per-block partial
+ * sums, which are added to J[0] in a fixed order, so the result is the same
+ * bits on every run.  The sum is taken in FP64 because finite differences of
+ * J check the gradient.  Asynchronous on `stream`.  FD_ERR_INVALID_ARG for
+ * n < 0 or missing pointers. */
+#define FD_MISFIT_DOUBLES 1025
 int32_t fd_misfit(const float* d, const float* d_obs, int64_t n, float* res, double* J,
                   void* stream);
 
@@ -417,7 +422,10 @@ int32_t fd_cnn_wgrad_noalloc(const uint16_t* x, int32_t cx, const uint16_t* dz, 
 
 /* Masked mean-square loss L = 1/(2n) sum_mask |out - target|^2 (out, target
  * FP32 [nvox][cout]; mask uint8 [nvox]; inv_n = 1/n): dz = dL/dout as BF16
- * [nvox][cpad] and L added to *loss (FP32, device). */
+ * [nvox][cpad] and L added to loss[0]; loss is a device array of
+ * FD_CNN_LOSS_FLOATS floats whose entries 1.. receive per-block partial sums
+ * (added in a fixed order: the same bits on every run). */
+#define FD_CNN_LOSS_FLOATS 257
 int32_t fd_cnn_loss_grad(const float* out, const float* target, const uint8_t* mask,
                          int64_t nvox, int32_t cout, int32_t cpad, float inv_n, uint16_t* dz,
                          float* loss, void* stream);

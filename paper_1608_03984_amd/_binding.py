@@ -51,6 +51,8 @@ FD_CNN_MASKED = 2
 FD_CNN_IDENTITY = 3
 FD_CNN_UNMASKED = 4
 FD_CNN_NOALLOC_SCRATCH_FLOATS = 12582912
+FD_CNN_LOSS_FLOATS = 257
+FD_MISFIT_DOUBLES = 1025
 
 EXPORTS = (
     "fd_workspace_bytes", "fd_setup", "fd_forward", "fd_get_field", "fd_set_field",

@@ -46,6 +46,12 @@ struct fd_ctx {
     bool sep_use;     // FD_OPT_DAMPING_PROFILE
     bool fuse_image;  // FD_OPT_FUSED_IMAGING
     SparsePoint* pts;
+    // injection plans (device) of the two point sets of the last upload
+    int64_t* plan_target;
+    int32_t* plan_shot;
+    int32_t* plan_start;
+    int32_t* plan_entry;
+    fd::InjectPlan plan[2];
     int cur;  // index of the level holding u^n in u[]/r[]
     // derived stencil coefficients (float, already divided by h or h^2)
     float w2[3][fd::kMaxRadius + 1];
@@ -199,6 +205,11 @@ struct Carve {
 int min_tile_y() { return fd::kMinTileRows; }
 
 constexpr int32_t kMaxShots = 4096;
+static_assert(FD_MISFIT_DOUBLES == 1 + fd::kMisfitBlocks, "misfit partial slots");
+static_assert(FD_CNN_LOSS_FLOATS == 1 + fd::kLossBlocks, "loss partial slots");
+// Sparse points per context: the injection plan codes a point index in the
+// upper 29 bits of an int32 (the corner in the lower 3).
+constexpr int32_t kMaxPoints = 1 << 27;
 
 // The imaging condition is summed in FP32 in two levels: a partial sum over
 // at most this many adjoint steps, then the running total (bounded rounding
@@ -233,6 +244,12 @@ uint64_t plan_workspace(const fd_grid* g, const Layout& L, int32_t nshots, int32
     const uint64_t o_flag = cv.take((uint64_t)(ntx * nty * L.nz) * sizeof(int32_t));
     const uint64_t o_prof = cv.take((uint64_t)(L.nx + L.ny + L.nz) * sizeof(float));
     const uint64_t o_pts = cv.take((uint64_t)(max_points > 0 ? max_points : 1) * sizeof(SparsePoint));
+    // injection plans: at most 8 corners per point, over both point sets
+    const uint64_t cap = 8 * (uint64_t)(max_points > 0 ? max_points : 1);
+    const uint64_t o_ptg = cv.take(cap * sizeof(int64_t));
+    const uint64_t o_psh = cv.take(cap * sizeof(int32_t));
+    const uint64_t o_pst = cv.take((cap + 2) * sizeof(int32_t));
+    const uint64_t o_pen = cv.take(cap * sizeof(int32_t));
     if (ctx && base) {
         ctx->reduce = reinterpret_cast<uint32_t*>(base + o_red);
         ctx->A = reinterpret_cast<float*>(base + o_A);
@@ -247,6 +264,10 @@ uint64_t plan_workspace(const fd_grid* g, const Layout& L, int32_t nshots, int32
         ctx->dflag = reinterpret_cast<int32_t*>(base + o_flag);
         ctx->prof = reinterpret_cast<float*>(base + o_prof);
         ctx->pts = reinterpret_cast<SparsePoint*>(base + o_pts);
+        ctx->plan_target = reinterpret_cast<int64_t*>(base + o_ptg);
+        ctx->plan_shot = reinterpret_cast<int32_t*>(base + o_psh);
+        ctx->plan_start = reinterpret_cast<int32_t*>(base + o_pst);
+        ctx->plan_entry = reinterpret_cast<int32_t*>(base + o_pen);
     }
     return cv.off;
 }
@@ -363,6 +384,51 @@ void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, int ng
     }
 }
 
+// Injection plan of n points (host table pts[0..n)): every non-zero corner
+// weight as a contribution (point << 3 | corner) to its target (shot,
+// flat index), targets in (shot, index) order and each target's
+// contributions in point order.  Appends to the concatenated plan arrays;
+// `start` values are offsets into the concatenated entries (entry_base for
+// this set's first entry).
+void build_plan(const fd_ctx* ctx, const SparsePoint* pts, int n, int32_t entry_base,
+                std::vector<int64_t>& tg, std::vector<int32_t>& sh, std::vector<int32_t>& st,
+                std::vector<int32_t>& en) {
+    struct Contribution {
+        int32_t shot;
+        int64_t index;
+        int32_t code;
+    };
+    const int nd = ctx->g.ndim, nc = nd == 3 ? 8 : 4;
+    std::vector<Contribution> cs;
+    cs.reserve((size_t)n * nc);
+    for (int i = 0; i < n; ++i) {
+        const SparsePoint& P = pts[i];
+        for (int c = 0; c < nc; ++c) {
+            const int dx = c & 1;
+            const int dy = nd == 3 ? (c >> 1) & 1 : 0;
+            const int dz = nd == 3 ? c >> 2 : c >> 1;
+            // the weight as the injection kernel forms it (FP32 products)
+            const float w =
+                (dx ? P.fx : 1.f - P.fx) * (dy ? P.fy : 1.f - P.fy) * (dz ? P.fz : 1.f - P.fz);
+            if (w == 0.f) continue;
+            cs.push_back({P.shot, P.base + dx + (int64_t)dy * ctx->L.pitch +
+                                      (int64_t)dz * ctx->L.plane,
+                          (i << 3) | c});
+        }
+    }
+    std::stable_sort(cs.begin(), cs.end(), [](const Contribution& a, const Contribution& b) {
+        return a.shot != b.shot ? a.shot < b.shot : a.index < b.index;
+    });
+    for (size_t k = 0; k < cs.size(); ++k) {
+        if (k == 0 || cs[k].shot != cs[k - 1].shot || cs[k].index != cs[k - 1].index) {
+            tg.push_back(cs[k].index);
+            sh.push_back(cs[k].shot);
+            st.push_back(entry_base + (int32_t)k);
+        }
+        en.push_back(cs[k].code);
+    }
+}
+
 // True when the given points are those of the last upload (compared in
 // place: no copy of the coordinates).
 bool same_points(const fd_ctx* ctx, int n1, const double* c1, int n2, const double* c2,
@@ -412,12 +478,39 @@ int32_t sync_points(fd_ctx* ctx, int n1, const double* c1, int n2, const double*
     };
     if (!k1.empty()) assign(k1, 0, n1);
     if (!k2.empty()) assign(k2, (size_t)n1, n2);
+    // injection plans of both sets, concatenated: targets of set 1, then set 2
+    std::vector<int64_t> tg;
+    std::vector<int32_t> sh, st, en;
+    int32_t nt1 = 0;
+    for (int set = 0; set < 2; ++set) {
+        const int first = set == 0 ? 0 : n1, n = set == 0 ? n1 : n2;
+        const int t0 = (int)tg.size();
+        build_plan(ctx, host.data() + first, n, (int32_t)en.size(), tg, sh, st, en);
+        if (set == 0) nt1 = (int32_t)tg.size() - t0;
+    }
+    st.push_back((int32_t)en.size());
     if (!host.empty()) {
         hipError_t he = hipMemcpyAsync(ctx->pts, host.data(), host.size() * sizeof(SparsePoint),
                                        hipMemcpyHostToDevice, s);
-        if (he == hipSuccess) he = hipStreamSynchronize(s);  // host table goes out of scope
+        if (he == hipSuccess && !tg.empty())
+            he = hipMemcpyAsync(ctx->plan_target, tg.data(), tg.size() * sizeof(int64_t),
+                                hipMemcpyHostToDevice, s);
+        if (he == hipSuccess && !tg.empty())
+            he = hipMemcpyAsync(ctx->plan_shot, sh.data(), sh.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, s);
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(ctx->plan_start, st.data(), st.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, s);
+        if (he == hipSuccess && !en.empty())
+            he = hipMemcpyAsync(ctx->plan_entry, en.data(), en.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, s);
+        if (he == hipSuccess) he = hipStreamSynchronize(s);  // host tables go out of scope
         if (he != hipSuccess) return hip_fail(ctx, he, "point upload");
     }
+    const int32_t ntot = (int32_t)tg.size();
+    ctx->plan[0] = {ctx->plan_target, ctx->plan_shot, ctx->plan_start, ctx->plan_entry, nt1};
+    ctx->plan[1] = {ctx->plan_target + nt1, ctx->plan_shot + nt1, ctx->plan_start + nt1,
+                    ctx->plan_entry, ntot - nt1};
     ctx->src_coords.swap(a);
     ctx->rec_coords.swap(b);
     ctx->src_counts.swap(k1);
@@ -771,7 +864,8 @@ int32_t fd_cfl_dt(const fd_grid* grid, double vmax, double* dt_max) {
 int32_t fd_workspace_bytes_shots(const fd_grid* grid, int32_t nshots, int32_t max_points,
                                  uint64_t* bytes) {
     std::string msg;
-    if (!bytes || max_points < 0 || nshots < 1 || nshots > kMaxShots) return FD_ERR_INVALID_ARG;
+    if (!bytes || max_points < 0 || max_points > kMaxPoints || nshots < 1 || nshots > kMaxShots)
+        return FD_ERR_INVALID_ARG;
     const int32_t rc = validate_grid(grid, msg);
     if (rc != FD_OK) return rc;
     if (nshots > 1 && grid->physics != FD_ACOUSTIC) return FD_ERR_UNSUPPORTED;
@@ -797,7 +891,8 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
     *out = nullptr;
     int32_t rc = validate_grid(grid, msg);
     if (rc != FD_OK) return rc;
-    if (!model || !model->vel || max_points < 0 || !workspace) return FD_ERR_INVALID_ARG;
+    if (!model || !model->vel || max_points < 0 || max_points > kMaxPoints || !workspace)
+        return FD_ERR_INVALID_ARG;
     if (nshots < 1 || nshots > kMaxShots) return FD_ERR_INVALID_ARG;
     const bool tti = grid->physics == FD_TTI;
     const bool vti = grid->physics == FD_VTI;
@@ -1040,11 +1135,11 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
             he = fd::launch_vti(p, nd, ctx->radius, ctx->variant, s);
             if (he == hipSuccess && nsrc) {
                 const float* q = src->data + (size_t)n * nsrc;
-                he = fd::launch_inject(pn, ctx->A, sig, spts, nsrc, q, scale, ctx->L, nd,
+                he = fd::launch_inject(pn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L, nd,
                                        ctx->L.volume, s);
                 if (he == hipSuccess)
-                    he = fd::launch_inject(rn, ctx->A, sig, spts, nsrc, q, scale, ctx->L, nd,
-                                           ctx->L.volume, s);
+                    he = fd::launch_inject(rn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L,
+                                           nd, ctx->L.volume, s);
             }
             if (he == hipSuccess && nrec)
                 he = fd::launch_record(pn, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
@@ -1058,8 +1153,9 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
             float* un = ctx->u[1 - ctx->cur];  // holds u^{n-1}, receives u^{n+1}
             he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, 1, s);
             if (he == hipSuccess && nsrc)
-                he = fd::launch_inject(un, ctx->A, sig, spts, nsrc, src->data + (size_t)n * nsrc,
-                                       scale, ctx->L, nd, ctx->L.volume, s);
+                he = fd::launch_inject(un, ctx->A, sig, spts, ctx->plan[0],
+                                       src->data + (size_t)n * nsrc, scale, ctx->L, nd,
+                                       ctx->L.volume, s);
             if (he == hipSuccess && nrec)
                 he = fd::launch_record(un, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
                                        nd, ctx->L.volume, s);
@@ -1100,11 +1196,11 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
             he = fd::launch_tti(p, ctx->radius, ctx->variant, ctx->tile_cfg, s);
             if (he == hipSuccess && nsrc) {
                 const float* q = src->data + (size_t)n * nsrc;
-                he = fd::launch_inject(pn, ctx->A, sig, spts, nsrc, q, scale, ctx->L, 3,
+                he = fd::launch_inject(pn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L, 3,
                                        ctx->L.volume, s);
                 if (he == hipSuccess)
-                    he = fd::launch_inject(rn, ctx->A, sig, spts, nsrc, q, scale, ctx->L, 3,
-                                           ctx->L.volume, s);
+                    he = fd::launch_inject(rn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L,
+                                           3, ctx->L.volume, s);
             }
             if (he == hipSuccess && nrec)
                 he = fd::launch_record(pn, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
@@ -1171,12 +1267,12 @@ hipError_t forward_segment(fd_ctx* ctx, fd::AcousticStep& p, int sb, const Store
         he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, acc, sb, s);
         if (he == hipSuccess && nsrc) {
             const float* q = src->data + (size_t)n * nsrc;
-            he = fd::launch_inject(un, ctx->A, sig, ctx->pts, nsrc, q, scale, ctx->L, nd,
+            he = fd::launch_inject(un, ctx->A, sig, ctx->pts, ctx->plan[0], q, scale, ctx->L, nd,
                                    ctx->L.volume, s);
             // the acceleration carries the source term without the damping divisor
             if (he == hipSuccess && acc)
-                he = fd::launch_inject(acc, ctx->A, nullptr, ctx->pts, nsrc, q, scale, ctx->L, nd,
-                                       ctx->L.volume, s);
+                he = fd::launch_inject(acc, ctx->A, nullptr, ctx->pts, ctx->plan[0], q, scale,
+                                       ctx->L, nd, ctx->L.volume, s);
         }
         if (he == hipSuccess && nrec)
             he = fd::launch_record(un, ctx->pts + nsrc, nrec, rec->data + (size_t)n * nrec, 1.f,
@@ -1197,7 +1293,7 @@ hipError_t adjoint_step(fd_ctx* ctx, fd::AcousticStep& p, int sb, const float* m
     const float* sig = ctx->damping ? ctx->sig : nullptr;
     hipError_t he = acoustic_stencil(ctx, p, mu1, mu2, nullptr, sb, s);
     if (he == hipSuccess && nadj)
-        he = fd::launch_inject(mu2, ctx->A, sig, ctx->pts + nsrc, nadj,
+        he = fd::launch_inject(mu2, ctx->A, sig, ctx->pts + nsrc, ctx->plan[1],
                                adj->data + (size_t)(k - 1) * nadj, 1.f, ctx->L, nd, ctx->L.volume,
                                s);
     if (he == hipSuccess && nsrc && qgrad)
@@ -1501,8 +1597,9 @@ int32_t fd_forward_shots(fd_ctx* ctx, int32_t nt, const fd_points* src, const in
         float* un = ctx->u[1 - ctx->cur];
         he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, sb, s);
         if (he == hipSuccess && nsrc)
-            he = fd::launch_inject(un, ctx->A, sig, ctx->pts, nsrc, src->data + (size_t)n * nsrc,
-                                   scale, ctx->L, nd, ctx->L.volume, s);
+            he = fd::launch_inject(un, ctx->A, sig, ctx->pts, ctx->plan[0],
+                                   src->data + (size_t)n * nsrc, scale, ctx->L, nd,
+                                   ctx->L.volume, s);
         if (he == hipSuccess && nrec)
             he = fd::launch_record(un, ctx->pts + nsrc, nrec, rec->data + (size_t)n * nrec, 1.f,
                                    ctx->L, nd, ctx->L.volume, s);

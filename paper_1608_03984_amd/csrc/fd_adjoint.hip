@@ -74,11 +74,15 @@ __global__ __launch_bounds__(256) void finish_kernel(const float* __restrict__ g
     }
 }
 
-// res = d - d_obs and J += 1/2 sum res^2.  The sum is taken in FP64: the
-// misfit is what the finite-difference checks of the gradient difference.
+// res = d - d_obs and 1/2 sum res^2 in FP64 (the misfit is what the
+// finite-difference checks of the gradient difference), in two passes with
+// a fixed grid, so the sum is the same bits on every run: block b sums the
+// elements b*256 + t + k*kMisfitBlocks*256 of each thread t in a fixed tree
+// into J[1 + b]; one block then adds J[1..kMisfitBlocks] (four consecutive
+// partials per thread, then a fixed tree) to J[0].
 __global__ __launch_bounds__(256) void misfit_kernel(const float* __restrict__ d,
                                                      const float* __restrict__ dobs, int64_t n,
-                                                     float* res, double* J) {
+                                                     float* res, double* __restrict__ J) {
     __shared__ double part[4];
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
@@ -90,7 +94,18 @@ __global__ __launch_bounds__(256) void misfit_kernel(const float* __restrict__ d
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(J, (part[0] + part[1]) + (part[2] + part[3]));
+    if (threadIdx.x == 0) J[1 + blockIdx.x] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+__global__ __launch_bounds__(256) void misfit_sum_kernel(double* __restrict__ J, int nblocks) {
+    __shared__ double part[4];
+    double acc = 0.0;  // thread t: partials 4t .. 4t+3 in order
+    for (int k = 0; k < 4; ++k)
+        if (4 * (int)threadIdx.x + k < nblocks) acc += J[1 + 4 * threadIdx.x + k];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) J[0] += (part[0] + part[1]) + (part[2] + part[3]);
 }
 
 dim3 plane_grid(const Layout& L, int& ntx) {
@@ -127,10 +142,9 @@ hipError_t launch_finish_gradient(const float* gsum, const float* A, float* out,
 
 hipError_t launch_misfit(const float* d, const float* dobs, int64_t n, float* res, double* J,
                          hipStream_t s) {
-    int64_t g = (n + 255) / 256;
-    if (g > 1024) g = 1024;  // few blocks: each ends in one atomic on J
-    if (g < 1) g = 1;
-    hipLaunchKernelGGL(misfit_kernel, dim3((unsigned)g), dim3(256), 0, s, d, dobs, n, res, J);
+    static_assert(kMisfitBlocks <= 4 * 256, "one block of the second pass sums the partials");
+    hipLaunchKernelGGL(misfit_kernel, dim3(kMisfitBlocks), dim3(256), 0, s, d, dobs, n, res, J);
+    hipLaunchKernelGGL(misfit_sum_kernel, dim3(1), dim3(256), 0, s, J, kMisfitBlocks);
     return hipGetLastError();
 }
 

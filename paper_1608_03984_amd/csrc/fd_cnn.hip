@@ -417,7 +417,17 @@ __global__ __launch_bounds__(256) void loss_grad_kernel(const float* __restrict_
     for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = l;
     __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(loss, part[0] + part[1] + part[2] + part[3]);
+    if (threadIdx.x == 0) loss[1 + blockIdx.x] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+// loss[0] += the block partials loss[1 .. nblocks], in a fixed tree.
+__global__ __launch_bounds__(256) void loss_sum_kernel(float* __restrict__ loss, int nblocks) {
+    __shared__ float part[4];
+    float l = threadIdx.x < nblocks ? loss[1 + threadIdx.x] : 0.f;
+    for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) loss[0] += (part[0] + part[1]) + (part[2] + part[3]);
 }
 
 __global__ void zero_u32_kernel(uint32_t* p) { *p = 0u; }
@@ -627,10 +637,11 @@ hipError_t launch_cnn_wgrad(const uint16_t* x, int cx, const uint16_t* dz, int c
 hipError_t launch_cnn_loss_grad(const float* out, const float* target, const uint8_t* mask,
                                 int64_t nvox, int cout, int cpad, float inv_n, uint16_t* dz,
                                 float* loss, hipStream_t s) {
-    // few blocks: each block ends in one atomic on the loss
-    const int gmax = grid1(nvox) < 1024 ? grid1(nvox) : 1024;
-    hipLaunchKernelGGL(loss_grad_kernel, dim3(gmax), dim3(256), 0, s, out, target, mask,
+    // a fixed grid: every run sums the same partials in the same order
+    static_assert(kLossBlocks <= 256, "one block of the second pass sums the partials");
+    hipLaunchKernelGGL(loss_grad_kernel, dim3(kLossBlocks), dim3(256), 0, s, out, target, mask,
                        nvox, cout, cpad, inv_n, dz, loss);
+    hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, s, loss, kLossBlocks);
     return hipGetLastError();
 }
 

@@ -119,30 +119,36 @@ __global__ __launch_bounds__(kBlock) void damping_flags_kernel(const float* __re
     if (threadIdx.x == 0) flags[((int64_t)z * nty + ty) * ntx + tx] = any ? 1 : 0;
 }
 
-// One thread per (point, corner): u[corner] += w A q scale / (1 + s), in the
-// volume of the point's shot.
+// One thread per target corner of the plan: u[corner] += w A q scale / (1 + s)
+// for each contribution (point, corner weight w) in point order, in the
+// volume of the target's shot.  A corner reached by one point gets exactly
+// the single addition of that point.
 __global__ __launch_bounds__(kBlock) void inject_kernel(float* u, const float* __restrict__ A,
                                                         const float* __restrict__ sig,
                                                         const SparsePoint* __restrict__ pts,
-                                                        int n, const float* __restrict__ q,
-                                                        float scale, Layout L, int ndim,
-                                                        int64_t shot_stride) {
-    const int ncorner = ndim == 3 ? 8 : 4;
-    const int k = blockIdx.x * kBlock + threadIdx.x;
-    if (k >= n * ncorner) return;
-    const int s = k / ncorner, c = k % ncorner;
-    const SparsePoint P = pts[s];
-    const int dx = c & 1;
-    const int dy = ndim == 3 ? (c >> 1) & 1 : 0;
-    const int dz = ndim == 3 ? c >> 2 : c >> 1;
-    const float w = (dx ? P.fx : 1.f - P.fx) * (dy ? P.fy : 1.f - P.fy) * (dz ? P.fz : 1.f - P.fz);
-    if (w == 0.f) return;
-    const int64_t i = P.base + dx + (int64_t)dy * L.pitch + (int64_t)dz * L.plane;
+                                                        InjectPlan plan,
+                                                        const float* __restrict__ q, float scale,
+                                                        Layout L, int ndim, int64_t shot_stride) {
+    const int m = blockIdx.x * kBlock + threadIdx.x;
+    if (m >= plan.ntarget) return;
+    const int64_t i = plan.target[m];
+    float* up = u + plan.shot[m] * shot_stride + i;
+    const float a = A[i];
     const float sg = sig ? sig[i] : 0.f;
-    atomicAdd(&u[P.shot * shot_stride + i], w * A[i] * q[s] * scale / (1.f + sg));
+    float uv = *up;
+    for (int e = plan.start[m]; e < plan.start[m + 1]; ++e) {
+        const int s = plan.entry[e] >> 3, c = plan.entry[e] & 7;
+        const SparsePoint P = pts[s];
+        const int dx = c & 1;
+        const int dy = ndim == 3 ? (c >> 1) & 1 : 0;
+        const int dz = ndim == 3 ? c >> 2 : c >> 1;
+        const float w =
+            (dx ? P.fx : 1.f - P.fx) * (dy ? P.fy : 1.f - P.fy) * (dz ? P.fz : 1.f - P.fz);
+        uv += w * a * q[s] * scale / (1.f + sg);
+    }
+    *up = uv;
 }
 
-// One thread per receiver: multilinear interpolation of u, times scale.
 __global__ __launch_bounds__(kBlock) void record_kernel(const float* __restrict__ u,
                                                         const SparsePoint* __restrict__ pts,
                                                         int n, float* __restrict__ out,
@@ -213,12 +219,11 @@ hipError_t launch_damping_flags(const float* sig, int32_t* flags, const Layout& 
 }
 
 hipError_t launch_inject(float* u, const float* A, const float* sig, const SparsePoint* pts,
-                         int n, const float* q, float scale, const Layout& L, int ndim,
-                         int64_t shot_stride, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const int total = n * (ndim == 3 ? 8 : 4);
-    hipLaunchKernelGGL(inject_kernel, dim3((total + kBlock - 1) / kBlock), dim3(kBlock), 0, s, u,
-                       A, sig, pts, n, q, scale, L, ndim, shot_stride);
+                         const InjectPlan& plan, const float* q, float scale, const Layout& L,
+                         int ndim, int64_t shot_stride, hipStream_t s) {
+    if (plan.ntarget <= 0) return hipSuccess;
+    hipLaunchKernelGGL(inject_kernel, dim3((plan.ntarget + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                       s, u, A, sig, pts, plan, q, scale, L, ndim, shot_stride);
     return hipGetLastError();
 }
 

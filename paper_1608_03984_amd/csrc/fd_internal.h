@@ -139,17 +139,32 @@ hipError_t launch_damping_profiles(const float* sig, const Layout& L, float* sx,
 hipError_t launch_damping_flags(const float* sig, int32_t* flags, const Layout& L, int tile_y,
                                 int ntx, int nty, hipStream_t s);
 
+// Injection plan of one point set: the distinct (shot, corner) targets that
+// its points' non-zero multilinear weights reach, each with its
+// contributions (point index within the set << 3 | corner) in point order, so
+// that one thread adds every contribution to a target in a fixed order: the
+// result does not depend on scheduling (no atomics).
+struct InjectPlan {
+    const int64_t* target;  // [ntarget] flat index of the corner within its volume
+    const int32_t* shot;    // [ntarget] volume (shot) of the target
+    const int32_t* start;   // [ntarget + 1] first contribution of each target
+    const int32_t* entry;   // [start[ntarget]] contributions
+    int32_t ntarget;
+};
+
 // sparse points
 // Shot k of a point writes / reads the volume u + k * shot_stride.
 hipError_t launch_inject(float* u, const float* A, const float* sig, const SparsePoint* pts,
-                         int n, const float* q, float scale, const Layout& L, int ndim,
-                         int64_t shot_stride, hipStream_t s);
+                         const InjectPlan& plan, const float* q, float scale, const Layout& L,
+                         int ndim, int64_t shot_stride, hipStream_t s);
 hipError_t launch_record(const float* u, const SparsePoint* pts, int n, float* out, float scale,
                          const Layout& L, int ndim, int64_t shot_stride, hipStream_t s);
 
 // adjoint / gradient (FP32, two-level summation)
 // gpart[vol] += mu[vol] * acc[vol] over the interior.
-// res = d - dobs (n values), *J += 1/2 sum res^2 (summed in FP64).
+// res = d - dobs (n values), J[0] += 1/2 sum res^2 (summed in FP64 in a
+// fixed order; J[1 .. kMisfitBlocks] hold the per-block partial sums).
+constexpr int kMisfitBlocks = 1024;
 hipError_t launch_misfit(const float* d, const float* dobs, int64_t n, float* res, double* J,
                          hipStream_t s);
 hipError_t launch_image(const float* mu, const float* acc, float* gpart, const Layout& L,
@@ -173,6 +188,9 @@ hipError_t launch_cnn_conv(const uint16_t* x, int cin_pad, int D, int H, int W,
                            hipStream_t s);
 hipError_t launch_cnn_wgrad(const uint16_t* x, int cx, const uint16_t* dz, int cz, int D, int H,
                             int W, int zchunk, float* partials, float* out, hipStream_t s);
+// loss[0] += the masked loss (loss[1 .. kLossBlocks]: per-block partials,
+// summed in a fixed order).
+constexpr int kLossBlocks = 256;
 hipError_t launch_cnn_loss_grad(const float* out, const float* target, const uint8_t* mask,
                                 int64_t nvox, int cout, int cpad, float inv_n, uint16_t* dz,
                                 float* loss, hipStream_t s);

@@ -69,7 +69,8 @@ class CorrectionNet:
         mk = lambda n: torch.empty(n, dtype=torch.int16, device=self.device)
         self.pk = [mk(e8), mk(e16), mk(e16)]           # forward operands
         self.pkT = [None, mk(e16), mk(e8)]             # backward-data operands (layers 2, 3)
-        self.loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        # loss[0] accumulates; the rest are the loss kernel's per-block partials
+        self.loss = torch.zeros(B.FD_CNN_LOSS_FLOATS, dtype=torch.float32, device=self.device)
         self._shape = None
 
     # -- buffers -------------------------------------------------------------
@@ -262,7 +263,7 @@ def train(net, samples, shape_c, iters, lr=1e-3, lr_end=1e-4, log=None, seed=0):
         net.backward(x0, tgt, mask, shape_c, n_mask)
         net.adam(lr_it)
         if (it + 1) % 50 == 0 or it == iters - 1:
-            hist.append((it + 1, float(net.loss.item())))
+            hist.append((it + 1, float(net.loss[0].item())))
             if log:
                 log(f"  iter {it + 1}: loss {hist[-1][1]:.4e}")
     return hist
@@ -279,7 +280,7 @@ def sample_loss(net, samples, shape_c):
         net.loss.zero_()
         net.forward(x0, shape_c)
         net.backward(x0, tgt, mask, shape_c, n)
-        tot += float(net.loss.item())
+        tot += float(net.loss[0].item())
     return tot / max(len(samples), 1)
 
 

@@ -97,6 +97,9 @@ def test_workspace_validation_codes():
     for g, code in bad:
         assert _code(lambda: P.fd_workspace_bytes(g, 1)) == code
     assert _code(lambda: P.fd_workspace_bytes(ok, -1)) == P.FD_ERR_INVALID_ARG
+    # the injection plan codes a point index in 29 bits: at most 2^27 points
+    assert P.fd_workspace_bytes(ok, 1 << 27) > 0
+    assert _code(lambda: P.fd_workspace_bytes(ok, (1 << 27) + 1)) == P.FD_ERR_INVALID_ARG
 
 
 def test_setup_rejects_before_device_work():

@@ -176,7 +176,7 @@ def test_network_gradient_and_adam_vs_oracle():
     torch.cuda.synchronize()
     got_out = out.cpu().numpy().reshape(shape + (2,))
     grads = net.grads.cpu().numpy()
-    loss_gpu = float(net.loss.item())
+    loss_gpu = float(net.loss[0].item())
     # oracle with BF16-rounded weights (what the matrix cores multiply)
     W = [C.bf16_round(p0[k, :27 * 256].reshape(27, 16, 16)) for k in range(3)]
     bias = [p0[k, 27 * 256:].astype(np.float64) for k in range(3)]

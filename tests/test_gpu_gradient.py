@@ -166,12 +166,15 @@ def test_misfit_vs_oracle():
     tr = s.forward(p.nt, p.src, p.wavelet, p.rec)
     do = torch.from_numpy(dobs.astype(np.float32)).to(tr.device)
     res = torch.empty_like(tr)
-    J = torch.zeros(1, dtype=torch.float64, device=tr.device)
+    J = torch.zeros(P.FD_MISFIT_DOUBLES, dtype=torch.float64, device=tr.device)
     st = torch.cuda.current_stream().cuda_stream
     P.fd_misfit(tr.data_ptr(), do.data_ptr(), tr.numel(), res.data_ptr(), J.data_ptr(), st)
+    J1 = float(J[0].item())
     P.fd_misfit(tr.data_ptr(), do.data_ptr(), tr.numel(), res.data_ptr(), J.data_ptr(), st)
     torch.cuda.synchronize()
-    got_res, got_J, d = res.cpu().numpy(), float(J.item()) / 2, tr.cpu().numpy()
+    got_res, got_J, d = res.cpu().numpy(), float(J[0].item()) / 2, tr.cpu().numpy()
+    # the partials are summed in a fixed order: the second call adds the same bits
+    assert float(J[0].item()) == 2 * J1
     s.close()
     assert np.array_equal(got_res, d - dobs.astype(np.float32))
     oracle.set_threads(THREADS)
@@ -220,7 +223,7 @@ def test_taylor_remainder_is_second_order():
             tr = s.forward(p.nt, p.src, p.wavelet, p.rec)
         else:
             tr = s.forward_checkpointed(p.nt, p.src, p.wavelet, p.rec)
-        J = torch.zeros(1, dtype=torch.float64, device=tr.device)
+        J = torch.zeros(P.FD_MISFIT_DOUBLES, dtype=torch.float64, device=tr.device)
         do = dobs.to(tr.device)
         P.fd_misfit(tr.data_ptr(), do.data_ptr(), tr.numel(), tr.data_ptr(), J.data_ptr(), st)
         if keep is not None:
@@ -228,7 +231,7 @@ def test_taylor_remainder_is_second_order():
             keep.append(g.cpu().numpy().astype(np.float64))
         torch.cuda.synchronize()
         s.close()
-        return float(J.item())
+        return float(J[0].item())
 
     keep = []
     J0 = J_of(p.vel, keep)
