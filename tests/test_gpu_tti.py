@@ -49,12 +49,14 @@ def test_tti_multi_tile_full_run(so, variant, tile):
     assert et < 1e-4 and eu < 1e-4 and er < 1e-4
 
 
-def test_tti_damping_profiles():
+@pytest.mark.parametrize("tile", [0, 1])
+def test_tti_damping_profiles(tile):
     """The tiled TTI kernel with the layer evaluated from its per-axis
-    profiles matches the run that reads the damping field."""
+    profiles matches the run that reads the damping field (through the
+    per-tile damping flags), for both tile shapes."""
     p = tti_problem((90, 37, 30), 6, 8, 60, seed=590)
-    say(f"case: tti damping profiles {p.padded}")
-    on, off = gpu_run(p), gpu_run(p, damping_profile=0)
+    say(f"case: tti damping profiles {p.padded} tile{tile}")
+    on, off = gpu_run(p, tile=tile), gpu_run(p, damping_profile=0, tile=tile)
     e = [rel(a, b) for a, b in zip(on, off)]
     say(f"  profiles vs field: traces {e[0]:.2e} p {e[1]:.2e} r {e[2]:.2e}")
     assert max(e) < 1e-6
