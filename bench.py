@@ -228,8 +228,16 @@ def cpu_baseline(problem, seconds: float):
             steps += 1
         rates1[so] = v1.size * steps / (time.perf_counter() - t0) / 1e9
     agg = len(ORDERS) / sum(1.0 / r for r in rates.values())
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                         None)
+    except OSError:
+        pass
     return {
         "value": round(agg, 5), "unit": "Gpt/s", "cores": threads, "kind": "oracle",
+        "cpu_model": model, "host_cpus": os.cpu_count(),
         "sample": (f"FP64 oracle, {vel.shape[2]}x{vel.shape[1]}x{slab} slab of the workload, "
                    f"so 4/8/12/16, ~{seconds:.0f} s total; per order Gpt/s "
                    + ", ".join(f"so{k} {v:.4f}" for k, v in rates.items())),
