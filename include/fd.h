@@ -465,7 +465,9 @@ int32_t fd_restrict(fd_ctx* ctx, int32_t which, int32_t stride, float* dst, void
  * FD_OPT_TILE: (x, y) tile of the tiled 3D acoustic kernel: 0 = 64x8 with 256
  *   threads, 1 = 64x16 with 256, 2 = 64x8 with 512, 3 = 64x16 with 512,
  *   -1 = the default for the space order (and shot count); of the tiled TTI
- *   kernel: 0 = 64x8 with 512 threads (default, also -1), 1 = 64x4 with 256.
+ *   kernel: 0 = 64x8 with 512 threads, 1 = 64x4 with 256, 2 = 64x16 with
+ *   1024 (space orders up to 8, else FD_ERR_UNSUPPORTED), -1 = the default
+ *   (2 up to space order 8, 0 above).
  *   FD_ERR_UNSUPPORTED for VTI (one tile shape).
  * FD_OPT_SHOTS_PER_BLOCK: shots a block of the tiled 3D acoustic kernel
  *   advances together (1, 2 or 4; 0 = default; 2 and 4 need tile 0 or 2).

@@ -333,6 +333,14 @@ int default_shots_per_block(int radius, int nshots) {
 }
 int shots_tile(int radius) { return radius <= 6 ? 2 : 0; }
 
+// TTI (measured at 464^3, so 8): 64 x 16 tiles of 1024 threads where they
+// fit 128 registers per lane (radius up to 4), 1.17 ms per step against 1.33
+// for 64 x 8 of 512 threads: the y halo is 8 rows per 16 instead of per 8,
+// and the 232 column blocks each hold a CU alone, so no block is slowed by a
+// neighbour on its CU and neighbouring tiles keep marching through the same
+// planes.  64 x 8 above radius 4.
+int tti_default_tile(int radius) { return radius <= fd::kTTITallMaxRadius ? 2 : 0; }
+
 void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, int ngroups,
                fd::AcousticStep* a, fd::TTIStep* t) {
     const Layout& L = ctx->L;
@@ -349,7 +357,9 @@ void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, int ng
         // rounding the count down.  Several shots (many more blocks than the
         // chip holds at once): three chunks per column, 4-10 % faster than
         // whole columns for 16 shots at 336^3.
-        const int waves = (ctx->tti || ctx->vti) ? 8 : (ctx->tile_cfg <= 1 ? 4 : 8);
+        const int waves = ctx->tti   ? fd::kTTITiles[ctx->tile_cfg].waves
+                          : ctx->vti ? fd::kVTITile.waves
+                                     : fd::kAcousticTiles[ctx->tile_cfg].waves;
         const int64_t xy = (int64_t)ntx * nty * ngroups;
         int64_t nzc;
         if (ctx->nshots > 1)
@@ -918,7 +928,8 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
     ctx->max_points = max_points;
     ctx->cur = 1;
     ctx->variant = 0;
-    ctx->tile_cfg = tti || vti ? 0
+    ctx->tile_cfg = tti ? tti_default_tile(ctx->radius)
+                    : vti ? 0
                     : nshots > 1 ? shots_tile(ctx->radius) : default_tile(ctx->radius);
     ctx->zchunk_opt = 0;
     ctx->tile_y = tti ? fd::tti_tile_y(ctx->tile_cfg)
@@ -1013,8 +1024,11 @@ int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value) {
         case FD_OPT_TILE: {
             if (ctx->vti) return fail(ctx, FD_ERR_UNSUPPORTED, "the VTI kernel has one tile shape");
             if (ctx->tti) {
-                const int v = value < 0 ? 0 : (int)value;
-                if (v > 1) return fail(ctx, FD_ERR_INVALID_ARG, "TTI tile configuration is 0..1");
+                const int v = value < 0 ? tti_default_tile(ctx->radius) : (int)value;
+                if (v > 2) return fail(ctx, FD_ERR_INVALID_ARG, "TTI tile configuration is 0..2");
+                if (v == 2 && ctx->radius > fd::kTTITallMaxRadius)
+                    return fail(ctx, FD_ERR_UNSUPPORTED,
+                                "the 64x16 TTI tile is built for space orders up to 8");
                 ctx->tile_cfg = v;
                 ctx->tile_y = fd::tti_tile_y(v);
                 ctx->flags_stale = true;  // rebuilt on the caller's stream by fd_forward

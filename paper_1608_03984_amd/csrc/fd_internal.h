@@ -229,8 +229,11 @@ struct TileShape {
 };
 // acoustic FD_OPT_TILE configurations 0..3: 64 x 8, 64 x 16, 64 x 8, 64 x 16
 constexpr TileShape kAcousticTiles[4] = {{4, 2}, {4, 4}, {8, 1}, {8, 2}};
-// TTI FD_OPT_TILE configurations 0..1: 64 x 8 (default), 64 x 4
-constexpr TileShape kTTITiles[2] = {{8, 1}, {4, 1}};
+// TTI FD_OPT_TILE configurations 0..2: 64 x 8, 64 x 4, 64 x 16 (radius up to
+// 4: a 1024-thread block must fit in 128 registers per lane; the default
+// there, 64 x 8 above)
+constexpr TileShape kTTITiles[3] = {{8, 1}, {4, 1}, {16, 1}};
+constexpr int kTTITallMaxRadius = 4;
 // VTI: 64 x 16
 constexpr TileShape kVTITile = {8, 2};
 // The smallest tile height of any tiled kernel: the damping flags are sized

@@ -440,9 +440,10 @@ struct TiledTTI {
 // Waves per SIMD the compiler is asked to fit (register budget 512 / waves):
 // radius up to 4 with 64 x 8 tiles fits four (128 registers) without
 // spilling, so two blocks share a CU and a 464^3 grid's 464 column blocks
-// are all resident at once; the other shapes keep the compiler's choice.
+// are all resident at once; 64 x 16 tiles (16 waves) need four to fit one
+// block; the other shapes keep the compiler's choice.
 template <int R, int NW>
-constexpr int tti_waves_per_simd() { return (R <= 4 && NW == 8) ? 4 : 1; }
+constexpr int tti_waves_per_simd() { return (R <= 4 && NW >= 8) ? 4 : 1; }
 
 template <int R, int NW, bool SEP>
 __global__ __launch_bounds__(64 * NW)
@@ -468,6 +469,9 @@ hipError_t launch_tiled_cfg(const TTIStep& p, int cfg, hipStream_t s) {
     switch (cfg) {
         case 0: return launch_tiled<R, 0>(p, s);
         case 1: return launch_tiled<R, 1>(p, s);
+        case 2:
+            if constexpr (R <= kTTITallMaxRadius) return launch_tiled<R, 2>(p, s);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -482,7 +486,7 @@ hipError_t launch_direct(const TTIStep& p, hipStream_t s) {
 }  // namespace
 
 int tti_tile_y(int cfg) {
-    return cfg >= 0 && cfg < 2 ? kTTITiles[cfg].height() : kTTITiles[0].height();
+    return cfg >= 0 && cfg < 3 ? kTTITiles[cfg].height() : kTTITiles[0].height();
 }
 
 hipError_t launch_tti(const TTIStep& p, int radius, int variant, int cfg, hipStream_t s) {

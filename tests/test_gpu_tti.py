@@ -15,11 +15,11 @@ from workloads import noise_state, tti_3d  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 
-def gpu_run(p, variant=0, damping_profile=None, tile=0):
+def gpu_run(p, variant=0, damping_profile=None, tile=None):
     s = from_problem(p)
     if variant:
         s.set_option(P.FD_OPT_KERNEL, variant)
-    if tile:
+    if tile is not None:
         s.set_option(P.FD_OPT_TILE, tile)
     if damping_profile is not None:
         s.set_option(P.FD_OPT_DAMPING_PROFILE, damping_profile)
@@ -33,11 +33,11 @@ def gpu_run(p, variant=0, damping_profile=None, tile=0):
 
 
 @pytest.mark.parametrize("so", [2, 4, 8])
-@pytest.mark.parametrize("variant,tile", [(0, 0), (0, 1), (1, 0)])
+@pytest.mark.parametrize("variant,tile", [(0, 0), (0, 1), (0, 2), (1, 0)])
 def test_tti_multi_tile_full_run(so, variant, tile):
     """60 steps on a grid of several tiles in x and y (ragged in both) with
-    the damping layer: the tiled kernel with 64 x 8 (tile 0) and 64 x 4
-    (tile 1) tiles and the direct kernel (variant 1)."""
+    the damping layer: the tiled kernel with 64 x 8 (tile 0), 64 x 4 (tile 1)
+    and 64 x 16 (tile 2) tiles and the direct kernel (variant 1)."""
     p = tti_problem((80, 26, 22), 6, so, 60, seed=200 + so)
     say(f"case: tti {p.padded} so{so} variant{variant} tile{tile}")
     tr, u, r = gpu_run(p, variant, tile=tile)
@@ -49,11 +49,11 @@ def test_tti_multi_tile_full_run(so, variant, tile):
     assert et < 1e-4 and eu < 1e-4 and er < 1e-4
 
 
-@pytest.mark.parametrize("tile", [0, 1])
+@pytest.mark.parametrize("tile", [0, 1, 2])
 def test_tti_damping_profiles(tile):
     """The tiled TTI kernel with the layer evaluated from its per-axis
     profiles matches the run that reads the damping field (through the
-    per-tile damping flags), for both tile shapes."""
+    per-tile damping flags), for every tile shape."""
     p = tti_problem((90, 37, 30), 6, 8, 60, seed=590)
     say(f"case: tti damping profiles {p.padded} tile{tile}")
     on, off = gpu_run(p, tile=tile), gpu_run(p, damping_profile=0, tile=tile)
@@ -63,17 +63,18 @@ def test_tti_damping_profiles(tile):
 
 
 @pytest.mark.parametrize("so", [2, 4, 8, 12, 16])
-@pytest.mark.parametrize("tile", [0, 1])
+@pytest.mark.parametrize("tile", [0, 1, 2])
 def test_tti_one_step_from_common_state(so, tile):
-    """One step from a common noise state at every point, for both tile
-    shapes of the tiled kernel (64 x 8 and 64 x 4)."""
+    """One step from a common noise state at every point, for every tile
+    shape of the tiled kernel (64 x 8, 64 x 4, and 64 x 16 up to so 8)."""
+    if tile == 2 and so > 8:
+        pytest.skip("the 64 x 16 tile is built for space orders up to 8")
     p = tti_problem((70, 18, 20), 4, so, 1, seed=so)
     shape = p.padded
     st = [noise_state(shape, 20 + k) for k in range(4)]
     say(f"case: tti one step so{so} {shape} tile{tile}")
     s = from_problem(p)
-    if tile:
-        s.set_option(P.FD_OPT_TILE, tile)
+    s.set_option(P.FD_OPT_TILE, tile)
     for which, f in zip((P.FD_FIELD_PREV, P.FD_FIELD_CUR, P.FD_FIELD_R_PREV, P.FD_FIELD_R_CUR), st):
         s.set_field(which, f)
     s.forward(1, zero_state=False)
@@ -116,6 +117,25 @@ def test_tti_full_size_one_step_sampled():
     ep, er = rel(gp[pts], rp), rel(gr[pts], rr)
     say(f"  sampled one-step rel L2 p {ep:.2e} r {er:.2e}")
     assert ep < 1e-5 and er < 1e-5
+
+
+def test_tti_tall_tile_limited_to_so8():
+    """The 64 x 16 tile is refused above so 8 (its 1024-thread blocks fit
+    128 registers per lane only up to radius 4) and out-of-range tiles are
+    refused; the context keeps its previous tile, and -1 (the default for
+    the order) is accepted."""
+    p = tti_problem((20, 20, 20), 2, 12, 1, seed=3)
+    s = from_problem(p)
+    with pytest.raises(P.FdError) as e:
+        s.set_option(P.FD_OPT_TILE, 2)
+    assert e.value.code == P.FD_ERR_UNSUPPORTED
+    with pytest.raises(P.FdError) as e:
+        s.set_option(P.FD_OPT_TILE, 3)
+    assert e.value.code == P.FD_ERR_INVALID_ARG
+    s.set_option(P.FD_OPT_TILE, -1)
+    s.forward(1)
+    torch.cuda.synchronize()
+    s.close()
 
 
 def test_tti_rejects_delta_above_epsilon():
