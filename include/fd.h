@@ -464,7 +464,8 @@ int32_t fd_restrict(fd_ctx* ctx, int32_t which, int32_t stride, float* dst, void
  * FD_OPT_ZCHUNK: z-planes per thread block of the tiled 3D kernels (0 = auto).
  * FD_OPT_TILE: (x, y) tile of the tiled 3D acoustic kernel: 0 = 64x8 with 256
  *   threads, 1 = 64x16 with 256, 2 = 64x8 with 512, 3 = 64x16 with 512,
- *   -1 = the default for the space order (and shot count); of the tiled TTI
+ *   4 = 64x24 with 768, -1 = the default for the space order and shot count
+ *   (one shot: 4 up to space order 6, 0 above); of the tiled TTI
  *   kernel: 0 = 64x8 with 512 threads, 1 = 64x4 with 256, 2 = 64x16 with
  *   1024 (space orders up to 8, else FD_ERR_UNSUPPORTED), -1 = the default
  *   (2 up to space order 8, 0 above).
@@ -485,8 +486,9 @@ int32_t fd_restrict(fd_ctx* ctx, int32_t which, int32_t stride, float* dst, void
 #define FD_OPT_SHOTS_PER_BLOCK 4
 #define FD_OPT_DAMPING_PROFILE 5
 /* FD_OPT_FUSED_IMAGING: 1 (default) = fd_gradient adds the imaging term
- * inside the adjoint stencil launch (tiled 3D kernel with the default 64 x 8
- * tile: one read of the adjoint field less per point and step); 0 = a
+ * inside the adjoint stencil launch (tiled 3D kernel with tile 0 or 4, or
+ * tile 2 with two shots per block: one read of the adjoint field less per
+ * point and step); 0 = a
  * separate imaging launch per step.  Both give the same bits. */
 #define FD_OPT_FUSED_IMAGING 6
 int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value);

@@ -315,11 +315,15 @@ bool locate(const fd_ctx* ctx, const double* c, SparsePoint* P) {
 }
 
 // Tile shape of the tiled acoustic kernel (measured on the 592^3 workload
-// with the damping layer evaluated from its profiles): 64 x 8 with 256
-// threads at every radius.  With the automatic z chunk every block then owns
-// a whole column (740 blocks at 592^3, all resident at once), so neighbouring
-// tiles march through z together and share their halo rows in L2.
-int default_tile(int) { return 0; }
+// with the damping layer evaluated from its profiles, whole columns):
+// 64 x 24 with 768 threads up to radius 3 (250 blocks, one per CU, fewer
+// halo rows per point: 582 / 585 / 608 us at so 2 / 4 / 6 against 621 / 621
+// / 631 for 64 x 8), 64 x 8 with 256 threads above (740 blocks, up to three
+// per CU, all resident at once: 624 / 670 / 715 us at so 8 / 12 / 16
+// against 628 / 663 / 741 for 64 x 24, whose single block per CU lines all
+// its waves up at every barrier while the longer steps of these orders need
+// independent blocks to overlap).
+int default_tile(int radius) { return radius <= 3 ? 4 : 0; }
 
 // Several shots (measured with 16 shots on the 336^3 survey grid, three z
 // chunks): 4 shots per block up to radius 2, 2 up to radius 6, one above,
@@ -1037,7 +1041,7 @@ int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value) {
             const int v = value < 0 ? (ctx->nshots > 1 ? shots_tile(ctx->radius)
                                                        : default_tile(ctx->radius))
                                     : (int)value;
-            if (v < 0 || v > 3) return fail(ctx, FD_ERR_INVALID_ARG, "tile configuration is 0..3");
+            if (v < 0 || v > 4) return fail(ctx, FD_ERR_INVALID_ARG, "tile configuration is 0..4");
             if (ctx->nshots > 1 && ctx->shots_per_block > 1 && v != 0 && v != 2)
                 return fail(ctx, FD_ERR_UNSUPPORTED,
                             "several shots per block are built for tile configurations 0 and 2");

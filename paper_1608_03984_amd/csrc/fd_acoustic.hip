@@ -63,7 +63,7 @@ hipError_t launch_direct(const AcousticStep& p, int ndim, hipStream_t s) {
 }  // namespace
 
 int acoustic_tile_y(int cfg) {
-    return cfg >= 0 && cfg < 4 ? kAcousticTiles[cfg].height() : kAcousticTiles[0].height();
+    return cfg >= 0 && cfg < 5 ? kAcousticTiles[cfg].height() : kAcousticTiles[0].height();
 }
 
 hipError_t launch_acoustic(const AcousticStep& p, int ndim, int radius, int variant, int cfg,

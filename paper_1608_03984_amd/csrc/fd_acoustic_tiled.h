@@ -443,8 +443,8 @@ hipError_t launch_tiled_sep(const AcousticStep& p, hipStream_t s) {
 }
 
 // Tile configurations: 0 = 64 x 8 (4 waves x 2 rows), 1 = 64 x 16 (4 x 4),
-// 2 = 64 x 8 (8 waves x 1 row), 3 = 64 x 16 (8 x 2).  Shots per block 2 and 4
-// are built for configurations 0 and 2.
+// 2 = 64 x 8 (8 waves x 1 row), 3 = 64 x 16 (8 x 2), 4 = 64 x 24 (12 x 2).
+// Shots per block 2 and 4 are built for configurations 0 and 2.
 template <int R, int CFG, int SB>
 hipError_t launch_tiled_t(const AcousticStep& p, hipStream_t s) {
     return p.sx ? launch_tiled_sep<R, CFG, SB, true>(p, s)
@@ -459,6 +459,7 @@ hipError_t launch_tiled_cfg(const AcousticStep& p, int cfg, int sb, hipStream_t 
             case 1: return launch_tiled_t<R, 1, 1>(p, s);
             case 2: return launch_tiled_t<R, 2, 1>(p, s);
             case 3: return launch_tiled_t<R, 3, 1>(p, s);
+            case 4: return launch_tiled_t<R, 4, 1>(p, s);
             default: return hipErrorInvalidValue;
         }
     }

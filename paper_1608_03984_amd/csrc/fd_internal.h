@@ -227,8 +227,9 @@ struct TileShape {
     int rows;   // rows each lane owns
     constexpr int height() const { return waves * rows; }
 };
-// acoustic FD_OPT_TILE configurations 0..3: 64 x 8, 64 x 16, 64 x 8, 64 x 16
-constexpr TileShape kAcousticTiles[4] = {{4, 2}, {4, 4}, {8, 1}, {8, 2}};
+// acoustic FD_OPT_TILE configurations 0..4: 64 x 8, 64 x 16, 64 x 8, 64 x 16,
+// 64 x 24
+constexpr TileShape kAcousticTiles[5] = {{4, 2}, {4, 4}, {8, 1}, {8, 2}, {12, 2}};
 // TTI FD_OPT_TILE configurations 0..2: 64 x 8, 64 x 4, 64 x 16 (radius up to
 // 4: a 1024-thread block must fit in 128 registers per lane; the default
 // there, 64 x 8 above)
@@ -242,10 +243,11 @@ constexpr int kMinTileRows = 4;
 // Tiled acoustic variants for gradients (configuration, shots per block):
 // the acceleration output is built with one shot per block in every
 // configuration and with two in configuration 2; the imaging fused into the
-// adjoint step in configuration 0 with one shot and configuration 2 with two.
+// adjoint step in configurations 0 and 4 (the single-shot defaults) with one
+// shot and configuration 2 with two.
 constexpr bool acc_built(int cfg, int sb) { return sb == 1 || (cfg == 2 && sb == 2); }
 constexpr bool img_built(int cfg, int sb) {
-    return (cfg == 0 && sb == 1) || (cfg == 2 && sb == 2);
+    return ((cfg == 0 || cfg == 4) && sb == 1) || (cfg == 2 && sb == 2);
 }
 
 // Tile height (rows) of the tiled kernels for a tile configuration.

@@ -66,7 +66,7 @@ def test_acoustic_3d_multi_tile_full_run(so, variant):
     assert et < 1e-4 and eu < 1e-4
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("so", [2, 4, 12, 16])
 @pytest.mark.parametrize("zchunk", [0, 5, 23])
 def test_acoustic_3d_tile_shapes(so, tile, zchunk):
@@ -304,6 +304,6 @@ def test_acoustic_error_paths():
         s.forward(2, np.array([[1e6, 0.0, 0.0]]), p.wavelet, p.rec)
     assert e.value.code == P.FD_ERR_INVALID_ARG and "outside" in str(e.value)
     with pytest.raises(P.FdError):
-        s.set_option(P.FD_OPT_TILE, 4)
+        s.set_option(P.FD_OPT_TILE, 5)
     s.close()
     del g

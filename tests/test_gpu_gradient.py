@@ -187,14 +187,15 @@ def test_misfit_vs_oracle():
     assert abs(got_J - Jref) <= 2e-4 * Jref
 
 
-@pytest.mark.parametrize("interval", [0, 7, 1])
-def test_fused_imaging_gives_the_same_bits(interval):
+@pytest.mark.parametrize("so,interval", [(8, 0), (8, 7), (8, 1), (4, 7)])
+def test_fused_imaging_gives_the_same_bits(so, interval):
     """The imaging term fused into the adjoint stencil launch and the separate
     imaging kernel give bitwise equal gradients (same terms, same order, same
-    fmaf), for several checkpoint intervals (1: every segment one step)."""
-    p = with_sources(acoustic_problem(3, (75, 30, 34), 6, 8, 50, seed=77), nsrc=2)
+    fmaf), for several checkpoint intervals (1: every segment one step) and
+    both default tiles (64 x 8 at so 8, 64 x 24 at so 4)."""
+    p = with_sources(acoustic_problem(3, (75, 30, 34), 6, so, 50, seed=77), nsrc=2)
     dobs = observed(p)
-    say(f"case: fused imaging, interval {interval}")
+    say(f"case: fused imaging, so{so} interval {interval}")
     out = []
     for fused in (1, 0):
         s = from_problem(p)
