@@ -464,11 +464,13 @@ int32_t fd_restrict(fd_ctx* ctx, int32_t which, int32_t stride, float* dst, void
  * FD_OPT_ZCHUNK: z-planes per thread block of the tiled 3D kernels (0 = auto).
  * FD_OPT_TILE: (x, y) tile of the tiled 3D acoustic kernel: 0 = 64x8 with 256
  *   threads, 1 = 64x16 with 256, 2 = 64x8 with 512, 3 = 64x16 with 512,
- *   4 = 64x24 with 768, -1 = the default for the space order and shot count
- *   (one shot: 4 up to space order 6, 0 above); of the tiled TTI
+ *   4 = 64x24 with 768, -1 = the default for the space order, shot count and
+ *   grid (one shot: 4 up to space order 6 when its x-y tiles number 90-100 %
+ *   of the device's compute units, else 0); of the tiled TTI
  *   kernel: 0 = 64x8 with 512 threads, 1 = 64x4 with 256, 2 = 64x16 with
  *   1024 (space orders up to 8, else FD_ERR_UNSUPPORTED), -1 = the default
- *   (2 up to space order 8, 0 above).
+ *   (2 up to space order 8 when its x-y tiles number 90-100 % of the
+ *   device's compute units, else 0).
  *   FD_ERR_UNSUPPORTED for VTI (one tile shape).
  * FD_OPT_SHOTS_PER_BLOCK: shots a block of the tiled 3D acoustic kernel
  *   advances together (1, 2 or 4; 0 = default; 2 and 4 need tile 0 or 2).

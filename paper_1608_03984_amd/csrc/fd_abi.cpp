@@ -62,6 +62,7 @@ struct fd_ctx {
     int zchunk_opt;
     int shots_per_block;
     int tile_y;
+    int ncu;  // compute units of the device current at setup (0 if unknown)
     bool flags_stale;
     // cached sparse-point coordinates of the last upload
     std::vector<double> src_coords, rec_coords;
@@ -314,16 +315,31 @@ bool locate(const fd_ctx* ctx, const double* c, SparsePoint* P) {
     return true;
 }
 
+// Tiles of one block per CU (a whole column each) pay only when their blocks
+// fill the chip in one round: between 90 % and 100 % of the device's compute
+// units.  Fewer leave CUs idle (500^3, so 2: 168 blocks of 64 x 24 took
+// 0.50 s for the cost-to-solution run against 0.41 s with 64 x 8 tiles);
+// more run in rounds of lone blocks.
+bool fills_chip_once(const fd_ctx* ctx, int tile_y) {
+    const int64_t ntx = (ctx->L.nx + fd::kTileX - 1) / fd::kTileX;
+    const int64_t nty = (ctx->L.ny + tile_y - 1) / tile_y;
+    const int64_t blocks = ntx * nty;
+    return ctx->ncu > 0 && 10 * blocks >= 9 * (int64_t)ctx->ncu && blocks <= ctx->ncu;
+}
+
 // Tile shape of the tiled acoustic kernel (measured on the 592^3 workload
 // with the damping layer evaluated from its profiles, whole columns):
-// 64 x 24 with 768 threads up to radius 3 (250 blocks, one per CU, fewer
-// halo rows per point: 582 / 585 / 608 us at so 2 / 4 / 6 against 621 / 621
-// / 631 for 64 x 8), 64 x 8 with 256 threads above (740 blocks, up to three
-// per CU, all resident at once: 624 / 670 / 715 us at so 8 / 12 / 16
-// against 628 / 663 / 741 for 64 x 24, whose single block per CU lines all
-// its waves up at every barrier while the longer steps of these orders need
-// independent blocks to overlap).
-int default_tile(int radius) { return radius <= 3 ? 4 : 0; }
+// 64 x 24 with 768 threads up to radius 3 where its blocks fill the chip
+// once (250 blocks at 592^3, one per CU, fewer halo rows per point: 582 /
+// 585 / 608 us at so 2 / 4 / 6 against 621 / 621 / 631 for 64 x 8), else
+// 64 x 8 with 256 threads (740 blocks at 592^3, up to three per CU, all
+// resident at once: 624 / 670 / 715 us at so 8 / 12 / 16 against 628 / 663
+// / 741 for 64 x 24, whose single block per CU lines all its waves up at
+// every barrier while the longer steps of these orders need independent
+// blocks to overlap).
+int default_tile(const fd_ctx* ctx) {
+    return ctx->radius <= 3 && fills_chip_once(ctx, fd::kAcousticTiles[4].height()) ? 4 : 0;
+}
 
 // Several shots (measured with 16 shots on the 336^3 survey grid, three z
 // chunks): 4 shots per block up to radius 2, 2 up to radius 6, one above,
@@ -338,12 +354,17 @@ int default_shots_per_block(int radius, int nshots) {
 int shots_tile(int radius) { return radius <= 6 ? 2 : 0; }
 
 // TTI (measured at 464^3, so 8): 64 x 16 tiles of 1024 threads where they
-// fit 128 registers per lane (radius up to 4), 1.17 ms per step against 1.33
-// for 64 x 8 of 512 threads: the y halo is 8 rows per 16 instead of per 8,
-// and the 232 column blocks each hold a CU alone, so no block is slowed by a
-// neighbour on its CU and neighbouring tiles keep marching through the same
-// planes.  64 x 8 above radius 4.
-int tti_default_tile(int radius) { return radius <= fd::kTTITallMaxRadius ? 2 : 0; }
+// fit 128 registers per lane (radius up to 4) and fill the chip once, 1.15
+// ms per step against 1.33 for 64 x 8 of 512 threads: the y halo is 8 rows
+// per 16 instead of per 8, and the 232 column blocks each hold a CU alone,
+// so no block is slowed by a neighbour on its CU and neighbouring tiles keep
+// marching through the same planes.  64 x 8 otherwise.
+int tti_default_tile(const fd_ctx* ctx) {
+    return ctx->radius <= fd::kTTITallMaxRadius &&
+                   fills_chip_once(ctx, fd::kTTITiles[2].height())
+               ? 2
+               : 0;
+}
 
 void tile_grid(const fd_ctx* ctx, int tile_y, int zchunk_opt, int radius, int ngroups,
                fd::AcousticStep* a, fd::TTIStep* t) {
@@ -932,9 +953,16 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
     ctx->max_points = max_points;
     ctx->cur = 1;
     ctx->variant = 0;
-    ctx->tile_cfg = tti ? tti_default_tile(ctx->radius)
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            ncu = 0;
+        ctx->ncu = ncu;
+    }
+    ctx->tile_cfg = tti ? tti_default_tile(ctx)
                     : vti ? 0
-                    : nshots > 1 ? shots_tile(ctx->radius) : default_tile(ctx->radius);
+                    : nshots > 1 ? shots_tile(ctx->radius) : default_tile(ctx);
     ctx->zchunk_opt = 0;
     ctx->tile_y = tti ? fd::tti_tile_y(ctx->tile_cfg)
                       : vti ? fd::vti_tile_y() : fd::acoustic_tile_y(ctx->tile_cfg);
@@ -1028,7 +1056,7 @@ int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value) {
         case FD_OPT_TILE: {
             if (ctx->vti) return fail(ctx, FD_ERR_UNSUPPORTED, "the VTI kernel has one tile shape");
             if (ctx->tti) {
-                const int v = value < 0 ? tti_default_tile(ctx->radius) : (int)value;
+                const int v = value < 0 ? tti_default_tile(ctx) : (int)value;
                 if (v > 2) return fail(ctx, FD_ERR_INVALID_ARG, "TTI tile configuration is 0..2");
                 if (v == 2 && ctx->radius > fd::kTTITallMaxRadius)
                     return fail(ctx, FD_ERR_UNSUPPORTED,
@@ -1039,7 +1067,7 @@ int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value) {
                 return FD_OK;
             }
             const int v = value < 0 ? (ctx->nshots > 1 ? shots_tile(ctx->radius)
-                                                       : default_tile(ctx->radius))
+                                                       : default_tile(ctx))
                                     : (int)value;
             if (v < 0 || v > 4) return fail(ctx, FD_ERR_INVALID_ARG, "tile configuration is 0..4");
             if (ctx->nshots > 1 && ctx->shots_per_block > 1 && v != 0 && v != 2)

@@ -235,8 +235,9 @@ constexpr TileShape kAcousticTiles[5] = {{4, 2}, {4, 4}, {8, 1}, {8, 2}, {12, 2}
 // there, 64 x 8 above)
 constexpr TileShape kTTITiles[3] = {{8, 1}, {4, 1}, {16, 1}};
 constexpr int kTTITallMaxRadius = 4;
-// VTI: 64 x 16
-constexpr TileShape kVTITile = {8, 2};
+// VTI: 64 x 16, one row per wave (1024 threads; up to 110 registers per lane
+// at radius 8, so the block fits a CU at every order)
+constexpr TileShape kVTITile = {16, 1};
 // The smallest tile height of any tiled kernel: the damping flags are sized
 // for it.
 constexpr int kMinTileRows = 4;

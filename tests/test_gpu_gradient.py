@@ -187,18 +187,19 @@ def test_misfit_vs_oracle():
     assert abs(got_J - Jref) <= 2e-4 * Jref
 
 
-@pytest.mark.parametrize("so,interval", [(8, 0), (8, 7), (8, 1), (4, 7)])
-def test_fused_imaging_gives_the_same_bits(so, interval):
+@pytest.mark.parametrize("so,tile,interval", [(8, 0, 0), (8, 0, 7), (8, 0, 1), (4, 4, 7)])
+def test_fused_imaging_gives_the_same_bits(so, tile, interval):
     """The imaging term fused into the adjoint stencil launch and the separate
     imaging kernel give bitwise equal gradients (same terms, same order, same
     fmaf), for several checkpoint intervals (1: every segment one step) and
-    both default tiles (64 x 8 at so 8, 64 x 24 at so 4)."""
+    both single-shot tiles built with it (64 x 8 and 64 x 24)."""
     p = with_sources(acoustic_problem(3, (75, 30, 34), 6, so, 50, seed=77), nsrc=2)
     dobs = observed(p)
-    say(f"case: fused imaging, so{so} interval {interval}")
+    say(f"case: fused imaging, so{so} tile{tile} interval {interval}")
     out = []
     for fused in (1, 0):
         s = from_problem(p)
+        s.set_option(P.FD_OPT_TILE, tile)
         s.set_option(P.FD_OPT_FUSED_IMAGING, fused)
         tr = s.forward_checkpointed(p.nt, p.src, p.wavelet, p.rec, interval=interval)
         res = tr - torch.from_numpy(dobs.astype(np.float32)).to(tr.device)
