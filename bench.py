@@ -9,10 +9,11 @@ A step is one time step of the whole path for one order: the stencil update
 with damping, the source injection and the receiver sampling.  Each order runs
 ``--warmup`` untimed steps and then ``--steps`` timed steps (inputs resident
 in HBM, timed with events on the launch stream between two synchronisations).
-Before the warm-up steps the stencil runs untimed for 60 ms of wall time
-(`settle`): the host-side setup of a problem leaves the GPU idle for seconds,
-and the first ~25 launches after it run 4-10 % slower while the GPU leaves
-its idle state.
+A zero-step call first uploads the point tables; then, before the warm-up
+steps, the full step runs untimed for 60 ms of wall time (`settle`): host
+work that leaves the GPU idle for milliseconds (a problem's setup, building
+the point tables of 262,144 receivers) makes the next ~25 launches run 4-10 %
+slower while the GPU leaves its idle state.
 
 Printed (one JSON line): value = Gpt/s over the sweep (total point updates /
 total time), the per-order figures, the roofline of the stencil kernel
@@ -172,11 +173,11 @@ def profile_pass(args):
 
 
 def settle(step, seconds: float = 0.06):
-    """Untimed GPU work right after a problem's setup: `step` (a few
-    stencil-only steps) repeated, with a synchronisation after each, for
-    `seconds` of wall time, so that the warm-up and timed steps that follow
-    run at the GPU's working clocks (after the seconds of host-side setup the
-    first ~25 stencil launches run 4-10 % slower)."""
+    """Untimed GPU work after a problem's setup and point upload: `step` (a
+    few steps) repeated, with a synchronisation after each, for `seconds` of
+    wall time, so that the warm-up and timed steps that follow run at the
+    GPU's working clocks (after milliseconds of host work with the GPU idle
+    the next ~25 stencil launches run 4-10 % slower)."""
     import torch
 
     t0 = time.perf_counter()
@@ -287,8 +288,11 @@ def tti_bench(args, physics="tti"):
                epsilon=p.eps, delta=p.delta, theta=p.theta, phi=p.phi,
                max_points=1 + p.rec.shape[0], device=dev)
     ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-    settle(lambda: s.forward(4, zero_state=False))
-    s.forward(args.warmup, p.src, wav[:args.warmup], p.rec, traces=traces[:args.warmup])
+    s.forward(0, p.src, wav[:0], p.rec)
+    settle(lambda: s.forward(4, p.src, wav[:4], p.rec, zero_state=False, traces=traces[:4],
+                             keep_points=True))
+    s.forward(args.warmup, p.src, wav[:args.warmup], p.rec, traces=traces[:args.warmup],
+              keep_points=True)
     tw = timed(lambda: s.forward(args.steps, p.src, wav[args.warmup:], p.rec, zero_state=False,
                                  traces=traces[args.warmup:], keep_points=True), ev)
     s.forward(args.warmup, zero_state=False)
@@ -623,10 +627,12 @@ def shots_bench(args):
     s = Solver(3, p.shape, p.spacing, p.nbl, p.so, p.dt, p.vel, p.eta, nshots=S,
                max_points=S * (1 + p.rec.shape[0]), device=dev)
     none, w0 = [None] * S, [np.zeros((1, 0), np.float32)] * S
-    settle(lambda: s.forward_shots(2, none, w0, none, zero_state=False))
-    s.forward_shots(args.warmup, srcs, [wav[:args.warmup]] * S, recs)
+    s.forward_shots(0, srcs, [wav[:0]] * S, recs)
+    settle(lambda: s.forward_shots(2, srcs, [wav[:2]] * S, recs, zero_state=False,
+                                   keep_points=True))
+    s.forward_shots(args.warmup, srcs, [wav[:args.warmup]] * S, recs, keep_points=True)
     tw = timed(lambda: s.forward_shots(args.steps, srcs, [wav[args.warmup:]] * S, recs,
-                                       zero_state=False), ev)
+                                       zero_state=False, keep_points=True), ev)
     s.forward_shots(args.warmup, none, w0, none, zero_state=False)
     tk = timed(lambda: s.forward_shots(args.steps, none, w0, none, zero_state=False), ev)
     s.close()
@@ -635,10 +641,11 @@ def shots_bench(args):
     # one shot at a time (a single-shot context, same kernels with one shot per block)
     s1 = Solver(3, p.shape, p.spacing, p.nbl, p.so, p.dt, p.vel, p.eta,
                 max_points=1 + p.rec.shape[0], device=dev)
-    settle(lambda: s1.forward(4, zero_state=False))
-    s1.forward(args.warmup, srcs[0], wav[:args.warmup], p.rec)
+    s1.forward(0, srcs[0], wav[:0], p.rec)
+    settle(lambda: s1.forward(4, srcs[0], wav[:4], p.rec, zero_state=False, keep_points=True))
+    s1.forward(args.warmup, srcs[0], wav[:args.warmup], p.rec, keep_points=True)
     t1 = timed(lambda: s1.forward(args.steps, srcs[0], wav[args.warmup:], p.rec,
-                                  zero_state=False), ev)
+                                  zero_state=False, keep_points=True), ev)
     s1.close()
     kernel_s = tk / args.steps
     ach = (12 * S + 4) * npts / kernel_s / 1e9
@@ -887,9 +894,12 @@ def main():
         s = Solver(3, prob.shape, prob.spacing, prob.nbl, so, dt, prob.vel, prob.eta,
                    max_points=1 + rec.shape[0], device=dev)
         ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-        settle(lambda: s.forward(4, zero_state=False))
-        # warm-up (also uploads the point tables)
-        s.forward(args.warmup, prob.src, wav[:args.warmup], rec, traces=traces[:args.warmup])
+        # upload the point tables (no steps), settle the GPU, warm up
+        s.forward(0, prob.src, wav[:0], rec)
+        settle(lambda: s.forward(4, prob.src, wav[:4], rec, zero_state=False, traces=traces[:4],
+                                 keep_points=True))
+        s.forward(args.warmup, prob.src, wav[:args.warmup], rec, traces=traces[:args.warmup],
+                  keep_points=True)
         tw = timed(lambda: s.forward(args.steps, prob.src, wav[args.warmup:], rec,
                                      zero_state=False, traces=traces[args.warmup:],
                                      keep_points=True), ev)

@@ -150,10 +150,13 @@ class Solver:
         self._keep_adj = d
         return out
 
-    def forward_shots(self, nt, src_list, wavelet_list, rec_list, zero_state=True):
+    def forward_shots(self, nt, src_list, wavelet_list, rec_list, zero_state=True,
+                      keep_points=False):
         """nt steps of every shot: ``src_list[k]`` / ``rec_list[k]`` are shot
         k's source and receiver coordinates, ``wavelet_list[k]`` its wavelets
-        [nt][nsrc_k].  Returns the list of per-shot traces [nt][nrec_k]."""
+        [nt][nsrc_k].  Returns the list of per-shot traces [nt][nrec_k].
+        keep_points: the points are the previous call's (FD_KEEP_POINTS; the
+        coordinates are only counted, not passed)."""
         ns = self.nshots
         srcs = [self._coords(c) if c is not None else np.zeros((0, self.ndim)) for c in src_list]
         recs = [self._coords(c) if c is not None else np.zeros((0, self.ndim)) for c in rec_list]
@@ -161,8 +164,12 @@ class Solver:
             raise ValueError("one source set, wavelet and receiver set per shot")
         sc = np.array([len(c) for c in srcs], np.int32)
         rc = np.array([len(c) for c in recs], np.int32)
-        src = np.concatenate(srcs) if sc.sum() else None
-        rec = np.concatenate(recs) if rc.sum() else None
+        if keep_points:
+            src = int(sc.sum()) if sc.sum() else None
+            rec = int(rc.sum()) if rc.sum() else None
+        else:
+            src = np.concatenate(srcs) if sc.sum() else None
+            rec = np.concatenate(recs) if rc.sum() else None
         q = None
         if src is not None:
             q = torch.cat([_dev(w, self.device).reshape(nt, int(k))
@@ -172,7 +179,8 @@ class Solver:
                            q.data_ptr() if q is not None else 0, rec,
                            rc if rec is not None else None,
                            traces.data_ptr() if rec is not None else 0,
-                           B.FD_ZERO_STATE if zero_state else 0, self.stream)
+                           (B.FD_ZERO_STATE if zero_state else 0)
+                           | (B.FD_KEEP_POINTS if keep_points else 0), self.stream)
         self._keep_q = q
         bounds = np.concatenate([[0], np.cumsum(rc)])
         return [traces[:, bounds[k]:bounds[k + 1]] for k in range(ns)]

@@ -159,6 +159,33 @@ def test_shots_full_size_one_step_sampled():
     oracle.set_threads(1)
 
 
+def test_shots_keep_points_equals_passing_the_coordinates():
+    """forward_shots with FD_KEEP_POINTS reuses the last upload's point table
+    and shot counts: a zero-step upload, then two runs that keep the points,
+    give the same bits as one run that passes the coordinates; a different
+    total count is rejected."""
+    p = acoustic_problem(3, (70, 24, 30), 5, 8, 30, seed=41)
+    srcs, wavs, recs = survey(p, 3, seed=5)
+    say("case: shots keep points")
+    n = sum(len(a) for a in srcs) + sum(len(a) for a in recs) + 1
+    s = Solver(3, p.shape, p.spacing, p.nbl, p.so, p.dt, p.vel, p.eta, nshots=3, max_points=n)
+    s.forward_shots(0, srcs, [w[:0] for w in wavs], recs)
+    a = s.forward_shots(12, srcs, [w[:12] for w in wavs], recs, keep_points=True)
+    b = s.forward_shots(18, srcs, [w[12:] for w in wavs], recs, zero_state=False, keep_points=True)
+    keep = [np.concatenate([x.cpu().numpy(), y.cpu().numpy()]) for x, y in zip(a, b)]
+    u_keep = [s.get_field(P.FD_FIELD_CUR, shot=k).cpu().numpy() for k in range(3)]
+    full = [t.cpu().numpy() for t in s.forward_shots(30, srcs, wavs, recs)]
+    u_full = [s.get_field(P.FD_FIELD_CUR, shot=k).cpu().numpy() for k in range(3)]
+    with pytest.raises(P.FdError) as e:
+        s.forward_shots(2, srcs, [w[:2] for w in wavs], [recs[0], recs[1], recs[2][:-1]],
+                        zero_state=False, keep_points=True)
+    assert e.value.code == P.FD_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    s.close()
+    for k in range(3):
+        assert np.array_equal(keep[k], full[k]) and np.array_equal(u_keep[k], u_full[k])
+
+
 def test_shots_error_paths():
     p = acoustic_problem(3, (20, 20, 20), 4, 4, 5, seed=8)
     say("case: shots error paths")
