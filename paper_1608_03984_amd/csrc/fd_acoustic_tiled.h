@@ -83,9 +83,24 @@ constexpr uint32_t kOOB = 0x80000000u;  // any offset at or past the record limi
 constexpr int kRecords = 0x7fffffff;
 
 
+// Operand buffering of the tiled acoustic kernel: true = two register slots,
+// each step's operands loaded two steps ahead; false = one slot, the next
+// head plane loaded right after the current one is staged and the next
+// output plane's operands right after the update (half the operand
+// registers and fewer spilled scalar registers, about one step of latency
+// hiding).  Measured at 592^3 (same bits either way): one slot is faster
+// for the 64 x 24 tile (so 4: 576 against 585 us) and one shot per block at
+// radius 6 and 8 (so 12 / 16: 669 / 709 against 673 / 717 us), two slots
+// at radius 4 (so 8: 625 against 655 us, where the deeper prefetch matters
+// and the registers do not change the occupancy).
+template <int R, int NW, int VY, int SB>
+constexpr bool acoustic_double_buffer() { return !(NW == 12 || (SB == 1 && R >= 6)); }
+
 template <int R, int NW, int VY, int SB, bool ACC, bool SEP, bool IMG>
 struct TiledAcoustic {
     static_assert(!IMG || !ACC, "fused imaging is an adjoint step (no acceleration output)");
+    static constexpr bool DB = acoustic_double_buffer<R, NW, VY, SB>();
+    static constexpr int NS = DB ? 2 : 1;  // operand register slots
     static constexpr int TY = NW * VY;
     static constexpr int LW = kTileX + 2 * R;
     static constexpr int LH = TY + 2 * R + 1;  // last row: sink for idle halo lanes
@@ -104,7 +119,7 @@ struct TiledAcoustic {
     float* cb[SB];        // same for the acceleration output (ACC), per shot
     const float* iab[SB]; // IMG: the acceleration the output point's u^n images with
     float* igb[SB];       // IMG: the FP32 partial sum of the imaging condition
-    float ia[2][SB][VY], ig[2][SB][VY];
+    float ia[NS][SB][VY], ig[NS][SB][VY];
     const float* ab;      // same for A (shared by the shots)
     const float* sb;      // same for the damping coefficient
     const float* zpl;     // an all-zero plane (ghost plane of A) at the tile origin
@@ -116,22 +131,22 @@ struct TiledAcoustic {
     uint32_t oc[VY], ohy[NYH], ohx[NXH];  // byte offsets inside the tile (kOOB outside)
     int ly_[NYH], lx_[NXH];
     float q[SB][U][VY];  // centre values, planes z-R .. z+R
-    float nxt[2][SB][VY], prv[2][SB][VY], hy[2][SB][NYH], hx[2][SB][NXH];
-    float aa[2][VY], sg[2][VY];
-    int damp[2];
+    float nxt[NS][SB][VY], prv[NS][SB][VY], hy[NS][SB][NYH], hx[NS][SB][NXH];
+    float aa[NS][VY], sg[NS][VY];
+    int damp[NS];
     // SEP: damping from the per-axis profiles (p.sx, p.sy, p.sz), evaluated at
     // use; the z value of a step is a scalar load issued with its operands
     float sxl, syv[VY];   // this lane's x profile value and its rows' y values
-    float ezs[2];
+    float ezs[NS];
     const __attribute__((address_space(4))) float* szc;
 
     __device__ TiledAcoustic(const AcousticStep& ps, float* l) : p(ps), lds(l) {}
 
-    // staging tile of shot s, register slot S; LDS ring of Lx + Ly of shot s
-    // (planes z .. z+R, slot (plane - zs) mod (R+1), each lane reading back
-    // only what it wrote)
-    __device__ __forceinline__ float* tile_of(int s, int S) const {
-        return lds + (2 * s + S) * LDS_FLOATS;
+    // staging tile of shot s, buffer T (the step's parity); LDS ring of
+    // Lx + Ly of shot s (planes z .. z+R, slot (plane - zs) mod (R+1), each
+    // lane reading back only what it wrote)
+    __device__ __forceinline__ float* tile_of(int s, int T) const {
+        return lds + (2 * s + T) * LDS_FLOATS;
     }
     __device__ __forceinline__ float* ring_of(int s) const {
         return lds + 2 * SB * LDS_FLOATS + s * LQ_FLOATS;
@@ -143,12 +158,12 @@ struct TiledAcoustic {
     }
 
     // Operands of the step whose output plane is zc: the head plane zc + R
-    // (centre and halo) of every shot and u^{n-1} of plane zc, with A and
-    // damping of plane zc loaded once for all shots.  Head planes beyond the
-    // grid are zero ghost planes of the volume; the operands of a step
-    // without output come from the all-zero plane.
+    // (centre and halo) of every shot (fetch_head) and u^{n-1} of plane zc,
+    // with A and damping of plane zc loaded once for all shots (fetch_out).
+    // Head planes beyond the grid are zero ghost planes of the volume; the
+    // operands of a step without output come from the all-zero plane.
     template <int S>
-    __device__ __forceinline__ void fetch(int zc) {
+    __device__ __forceinline__ void fetch_head(int zc) {
 #pragma unroll
         for (int s = 0; s < SB; ++s) {
             const auto rh = rsrc(ub[s] + (int64_t)(zc + R) * plane);
@@ -159,6 +174,14 @@ struct TiledAcoustic {
 #pragma unroll
             for (int k = 0; k < NXH; ++k) hx[S][s][k] = bload(rh, ohx[k]);
         }
+    }
+    template <int S>
+    __device__ __forceinline__ void fetch(int zc) {
+        fetch_head<S>(zc);
+        fetch_out<S>(zc);
+    }
+    template <int S>
+    __device__ __forceinline__ void fetch_out(int zc) {
         const bool out = zc >= z0 && zc < z1;
         const int64_t zo = (int64_t)zc * plane;
         const auto ra = rsrc(out ? ab + zo : zpl);
@@ -197,14 +220,15 @@ struct TiledAcoustic {
     template <int K>
     __device__ __forceinline__ bool step(int z) {
         if (z >= z1) return false;
-        constexpr int S = K & 1;
+        constexpr int S = DB ? (K & 1) : 0;  // operand register slot
+        constexpr int T = K & 1;             // LDS staging buffer
         constexpr int H = (K + 2 * R) % U;  // head plane z + R
         constexpr int C = (K + R) % U;      // output plane z
 #pragma unroll
         for (int s = 0; s < SB; ++s) {
 #pragma unroll
             for (int v = 0; v < VY; ++v) q[s][H][v] = nxt[S][s][v];
-            float* tile = tile_of(s, S);
+            float* tile = tile_of(s, T);
 #pragma unroll
             for (int v = 0; v < VY; ++v) tile[(R + w * VY + v) * LW + R + lane] = q[s][H][v];
 #pragma unroll
@@ -212,12 +236,14 @@ struct TiledAcoustic {
 #pragma unroll
             for (int k = 0; k < NXH; ++k) tile[lx_[k]] = hx[S][s][k];
         }
+        // one slot: the next head plane's registers are free once staged
+        if constexpr (!DB) fetch_head<0>(z + 1);
         __syncthreads();
 
         // in-plane Laplacian of the head plane
 #pragma unroll
         for (int s = 0; s < SB; ++s) {
-            const float* tile = tile_of(s, S);
+            const float* tile = tile_of(s, T);
             float cw[VY + 2 * R];
 #pragma unroll
             for (int k = 0; k < VY + 2 * R; ++k) cw[k] = tile[(w * VY + k) * LW + R + lane];
@@ -277,7 +303,10 @@ struct TiledAcoustic {
                     bstore_nt(rg, oc[v], fmaf(q[s][C][v], ia[S][s][v], ig[S][s][v]));
             }
         }
-        fetch<S>(z + 2);
+        if constexpr (DB)
+            fetch<S>(z + 2);
+        else
+            fetch_out<0>(z + 1);
         return true;
     }
 
@@ -401,7 +430,7 @@ struct TiledAcoustic {
             }
         flagbuf = flag_of(zs);
         fetch<0>(zs);
-        fetch<1>(zs + 1);
+        if constexpr (DB) fetch<1>(zs + 1);
         for (int zb_ = zs; period(zb_, std::make_integer_sequence<int, U>{}); zb_ += U) {
         }
     }

@@ -49,8 +49,8 @@ struct AcousticStep {
     const float* __restrict__ A;   // dt^2 v^2
     const float* __restrict__ sig; // eta dt / 2, or nullptr
     const int32_t* __restrict__ dflag; // per (z, tile): 1 if the tile-plane holds damping
-    // Imaging fused into an adjoint step (tiled kernel, 64 x 8 tiles, one
-    // shot): when img_a is set, img_g[p] = fmaf(u^n[p], img_a[p], img_g[p])
+    // Imaging fused into an adjoint step (tiled kernel, the configurations
+    // img_built names): when img_a is set, img_g[p] = fmaf(u^n[p], img_a[p], img_g[p])
     // at every output point (img_a: the step's stored acceleration, img_g: the
     // FP32 partial sum, both padded volumes).
     const float* img_a;
