@@ -58,6 +58,8 @@ extern "C" {
 #define FD_ERR_WORKSPACE 4   /* workspace too small or misaligned */
 #define FD_ERR_DEVICE 5      /* a HIP runtime call failed */
 #define FD_ERR_NONFINITE 6   /* non-finite or non-positive model values */
+#define FD_ERR_HOST 7        /* host memory for the setup's or a point table's host-side work
+                                could not be obtained (nothing is left half set up) */
 
 /* Physics. */
 #define FD_ACOUSTIC 0 /* Eq. (Acou), 2D or 3D */

@@ -18,6 +18,7 @@ FD_ERR_UNSUPPORTED = 3
 FD_ERR_WORKSPACE = 4
 FD_ERR_DEVICE = 5
 FD_ERR_NONFINITE = 6
+FD_ERR_HOST = 7
 
 FD_ACOUSTIC = 0
 FD_TTI = 1

@@ -12,8 +12,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -76,6 +78,26 @@ struct fd_ctx {
 };
 
 namespace {
+
+// Runs an entry point's body; a C++ exception from its host-side work (the
+// host copies of the FP64 setup, point tables, injection plans) becomes
+// FD_ERR_HOST instead of crossing the C boundary.
+template <class F>
+int32_t guarded(fd_ctx* ctx, F&& body) {
+    try {
+        return body();
+    } catch (const std::exception& ex) {
+        if (ctx) {
+            try {
+                ctx->err = ex.what();
+            } catch (...) {
+            }
+        }
+        return FD_ERR_HOST;
+    } catch (...) {
+        return FD_ERR_HOST;
+    }
+}
 
 int32_t fail(fd_ctx* ctx, int32_t code, const std::string& msg) {
     if (ctx) ctx->err = msg;
@@ -717,8 +739,9 @@ int host_threads(int64_t n) {
     return n < ((int64_t)1 << 16) ? 1 : nt;
 }
 
-// Runs f(t, i0, i1) for thread t = 0 .. host_threads(n) - 1 over consecutive
-// ranges covering [0, n).
+// Runs f(t, i0, i1) for t = 0 .. host_threads(n) - 1 over consecutive ranges
+// covering [0, n), each on a thread of its own; a range whose thread cannot
+// be started runs on the calling thread.
 template <class F>
 void parallel_for(int64_t n, F f) {
     const int nt = host_threads(n);
@@ -727,10 +750,18 @@ void parallel_for(int64_t n, F f) {
         return;
     }
     std::vector<std::thread> th;
+    th.reserve((size_t)nt);
     const int64_t chunk = (n + nt - 1) / nt;
     for (int t = 0; t < nt; ++t) {
         const int64_t a = t * chunk, b = std::min(n, a + chunk);
-        if (a < b) th.emplace_back(f, t, a, b);
+        if (a >= b) continue;
+        bool started = false;
+        try {
+            th.emplace_back(f, t, a, b);
+            started = true;
+        } catch (const std::system_error&) {
+        }
+        if (!started) f(t, a, b);
     }
     for (auto& t : th) t.join();
 }
@@ -986,9 +1017,17 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
         return FD_ERR_DEVICE;
     }
     // coefficients in FP64 on the host (the first wavefield level is the
-    // staging area of the uploads and is cleared again afterwards)
+    // staging area of the uploads and is cleared again afterwards); the
+    // host copies of the model are volume-sized
     ModelCheck chk;
-    he = derive_coefficients(ctx, model, ctx->u[0], s, chk);
+    if (guarded(nullptr, [&]() -> int32_t {
+            he = derive_coefficients(ctx, model, ctx->u[0], s, chk);
+            return FD_OK;
+        }) != FD_OK) {
+        hipStreamSynchronize(s);
+        delete ctx;
+        return FD_ERR_HOST;
+    }
     if (he == hipSuccess) he = fd::launch_fill_zero(ctx->u[0], L.volume * nshots, s);
     if (he == hipSuccess) he = refresh_flags(ctx, s);
     const bool try_sep = ctx->damping && grid->ndim == 3;
@@ -1105,157 +1144,159 @@ int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value) {
 
 int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_points* rec,
                    int32_t flags, void* stream) {
-    if (!ctx) return FD_ERR_INVALID_ARG;
-    ctx->err.clear();
-    if (ctx->nshots > 1)
-        return fail(ctx, FD_ERR_INVALID_ARG, "a context of several shots steps with fd_forward_shots");
-    if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
-    const bool keep = (flags & FD_KEEP_POINTS) != 0;
-    int32_t rc = check_points_arg(ctx, nt, src, "source", keep);
-    if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver", keep);
-    if (rc != FD_OK) return rc;
-    const int nsrc = src ? src->n : 0, nrec = rec ? rec->n : 0;
-    if ((int64_t)nsrc + nrec > ctx->max_points)
-        return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int nd = ctx->g.ndim;
-    rc = keep ? keep_points(ctx, nsrc, nrec)
-              : sync_points(ctx, nsrc, src ? src->coords : nullptr, nrec,
-                            rec ? rec->coords : nullptr, "source", "receiver", s);
-    if (rc != FD_OK) return rc;
+    return guarded(ctx, [&]() -> int32_t {
+        if (!ctx) return FD_ERR_INVALID_ARG;
+        ctx->err.clear();
+        if (ctx->nshots > 1)
+            return fail(ctx, FD_ERR_INVALID_ARG, "a context of several shots steps with fd_forward_shots");
+        if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
+        const bool keep = (flags & FD_KEEP_POINTS) != 0;
+        int32_t rc = check_points_arg(ctx, nt, src, "source", keep);
+        if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver", keep);
+        if (rc != FD_OK) return rc;
+        const int nsrc = src ? src->n : 0, nrec = rec ? rec->n : 0;
+        if ((int64_t)nsrc + nrec > ctx->max_points)
+            return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int nd = ctx->g.ndim;
+        rc = keep ? keep_points(ctx, nsrc, nrec)
+                  : sync_points(ctx, nsrc, src ? src->coords : nullptr, nrec,
+                                rec ? rec->coords : nullptr, "source", "receiver", s);
+        if (rc != FD_OK) return rc;
 
-    hipError_t he = hipSuccess;
-    if (ctx->flags_stale) {
-        he = refresh_flags(ctx, s);
-        if (he != hipSuccess) return hip_fail(ctx, he, "damping flags");
-        ctx->flags_stale = false;
-    }
-    if (flags & FD_ZERO_STATE) {
-        for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume, s);
-        if (ctx->r[0])
-            for (int k = 0; k < 2 && he == hipSuccess; ++k)
-                he = fd::launch_fill_zero(ctx->r[k], ctx->L.volume, s);
-        if (he != hipSuccess) return hip_fail(ctx, he, "zero state");
-    }
-    const float scale = (float)(1.0 / cell_volume(ctx));
-    const SparsePoint* spts = ctx->pts;
-    const SparsePoint* rpts = ctx->pts + nsrc;
-    const float* sig = ctx->damping ? ctx->sig : nullptr;
+        hipError_t he = hipSuccess;
+        if (ctx->flags_stale) {
+            he = refresh_flags(ctx, s);
+            if (he != hipSuccess) return hip_fail(ctx, he, "damping flags");
+            ctx->flags_stale = false;
+        }
+        if (flags & FD_ZERO_STATE) {
+            for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume, s);
+            if (ctx->r[0])
+                for (int k = 0; k < 2 && he == hipSuccess; ++k)
+                    he = fd::launch_fill_zero(ctx->r[k], ctx->L.volume, s);
+            if (he != hipSuccess) return hip_fail(ctx, he, "zero state");
+        }
+        const float scale = (float)(1.0 / cell_volume(ctx));
+        const SparsePoint* spts = ctx->pts;
+        const SparsePoint* rpts = ctx->pts + nsrc;
+        const float* sig = ctx->damping ? ctx->sig : nullptr;
 
-    if (ctx->vti) {
-        fd::VTIStep p;
-        std::memset(&p, 0, sizeof(p));
-        p.A = ctx->A;
-        p.sig = sig;
-        p.dflag = nd == 3 ? ctx->dflag : nullptr;
-        p.e = ctx->e;
-        p.d = ctx->d;
-        if (nd == 3 && ctx->damping && ctx->sep_ok && ctx->sep_use) {
-            p.sx = ctx->prof;
-            p.sy = ctx->prof + ctx->L.nx;
-            p.sz = ctx->prof + ctx->L.nx + ctx->L.ny;
-        }
-        p.L = ctx->L;
-        p.c0h = (float)((double)ctx->w2[0][0] + (nd == 3 ? (double)ctx->w2[1][0] : 0.0));
-        p.c0z = ctx->w2[2][0];
-        for (int j = 0; j <= fd::kMaxRadius; ++j) {
-            p.cx[j] = ctx->w2[0][j];
-            p.cy[j] = ctx->w2[1][j];
-            p.cz[j] = ctx->w2[2][j];
-        }
-        fd::TTIStep grid_only;
-        tile_grid(ctx, ctx->tile_y, ctx->zchunk_opt, ctx->radius, 1, nullptr, &grid_only);
-        p.ntx = grid_only.ntx;
-        p.nty = grid_only.nty;
-        p.nzc = grid_only.nzc;
-        p.zchunk = grid_only.zchunk;
-        p.ntiles = grid_only.ntiles;
-        p.nblocks = grid_only.nblocks;
-        for (int n = 0; n < nt; ++n) {
-            float* pn = ctx->u[1 - ctx->cur];
-            float* rn = ctx->r[1 - ctx->cur];
-            p.pc = ctx->u[ctx->cur];
-            p.rc = ctx->r[ctx->cur];
-            p.pp = pn;
-            p.rp = rn;
-            he = fd::launch_vti(p, nd, ctx->radius, ctx->variant, s);
-            if (he == hipSuccess && nsrc) {
-                const float* q = src->data + (size_t)n * nsrc;
-                he = fd::launch_inject(pn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L, nd,
-                                       ctx->L.volume, s);
-                if (he == hipSuccess)
-                    he = fd::launch_inject(rn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L,
+        if (ctx->vti) {
+            fd::VTIStep p;
+            std::memset(&p, 0, sizeof(p));
+            p.A = ctx->A;
+            p.sig = sig;
+            p.dflag = nd == 3 ? ctx->dflag : nullptr;
+            p.e = ctx->e;
+            p.d = ctx->d;
+            if (nd == 3 && ctx->damping && ctx->sep_ok && ctx->sep_use) {
+                p.sx = ctx->prof;
+                p.sy = ctx->prof + ctx->L.nx;
+                p.sz = ctx->prof + ctx->L.nx + ctx->L.ny;
+            }
+            p.L = ctx->L;
+            p.c0h = (float)((double)ctx->w2[0][0] + (nd == 3 ? (double)ctx->w2[1][0] : 0.0));
+            p.c0z = ctx->w2[2][0];
+            for (int j = 0; j <= fd::kMaxRadius; ++j) {
+                p.cx[j] = ctx->w2[0][j];
+                p.cy[j] = ctx->w2[1][j];
+                p.cz[j] = ctx->w2[2][j];
+            }
+            fd::TTIStep grid_only;
+            tile_grid(ctx, ctx->tile_y, ctx->zchunk_opt, ctx->radius, 1, nullptr, &grid_only);
+            p.ntx = grid_only.ntx;
+            p.nty = grid_only.nty;
+            p.nzc = grid_only.nzc;
+            p.zchunk = grid_only.zchunk;
+            p.ntiles = grid_only.ntiles;
+            p.nblocks = grid_only.nblocks;
+            for (int n = 0; n < nt; ++n) {
+                float* pn = ctx->u[1 - ctx->cur];
+                float* rn = ctx->r[1 - ctx->cur];
+                p.pc = ctx->u[ctx->cur];
+                p.rc = ctx->r[ctx->cur];
+                p.pp = pn;
+                p.rp = rn;
+                he = fd::launch_vti(p, nd, ctx->radius, ctx->variant, s);
+                if (he == hipSuccess && nsrc) {
+                    const float* q = src->data + (size_t)n * nsrc;
+                    he = fd::launch_inject(pn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L, nd,
+                                           ctx->L.volume, s);
+                    if (he == hipSuccess)
+                        he = fd::launch_inject(rn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L,
+                                               nd, ctx->L.volume, s);
+                }
+                if (he == hipSuccess && nrec)
+                    he = fd::launch_record(pn, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
                                            nd, ctx->L.volume, s);
+                if (he != hipSuccess) return hip_fail(ctx, he, "step");
+                ctx->cur = 1 - ctx->cur;
             }
-            if (he == hipSuccess && nrec)
-                he = fd::launch_record(pn, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
-                                       nd, ctx->L.volume, s);
-            if (he != hipSuccess) return hip_fail(ctx, he, "step");
-            ctx->cur = 1 - ctx->cur;
-        }
-    } else if (!ctx->tti) {
-        fd::AcousticStep p = acoustic_params(ctx, 1);
-        for (int n = 0; n < nt; ++n) {
-            float* un = ctx->u[1 - ctx->cur];  // holds u^{n-1}, receives u^{n+1}
-            he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, 1, s);
-            if (he == hipSuccess && nsrc)
-                he = fd::launch_inject(un, ctx->A, sig, spts, ctx->plan[0],
-                                       src->data + (size_t)n * nsrc, scale, ctx->L, nd,
-                                       ctx->L.volume, s);
-            if (he == hipSuccess && nrec)
-                he = fd::launch_record(un, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
-                                       nd, ctx->L.volume, s);
-            if (he != hipSuccess) return hip_fail(ctx, he, "step");
-            ctx->cur = 1 - ctx->cur;
-        }
-    } else {
-        fd::TTIStep p;
-        std::memset(&p, 0, sizeof(p));
-        p.A = ctx->A;
-        p.sig = sig;
-        p.dflag = ctx->dflag;
-        p.e = ctx->e;
-        p.d = ctx->d;
-        for (int k = 0; k < 6; ++k) p.c[k] = ctx->c[k];
-        if (ctx->damping && ctx->sep_ok && ctx->sep_use) {
-            p.sx = ctx->prof;
-            p.sy = ctx->prof + ctx->L.nx;
-            p.sz = ctx->prof + ctx->L.nx + ctx->L.ny;
-        }
-        p.L = ctx->L;
-        for (int j = 0; j <= fd::kMaxRadius; ++j) {
-            p.w2x[j] = ctx->w2[0][j];
-            p.w2y[j] = ctx->w2[1][j];
-            p.w2z[j] = ctx->w2[2][j];
-            p.w1x[j] = ctx->w1[0][j];
-            p.w1y[j] = ctx->w1[1][j];
-            p.w1z[j] = ctx->w1[2][j];
-        }
-        tile_grid(ctx, ctx->tile_y, ctx->zchunk_opt, ctx->radius, 1, nullptr, &p);
-        for (int n = 0; n < nt; ++n) {
-            float* pn = ctx->u[1 - ctx->cur];
-            float* rn = ctx->r[1 - ctx->cur];
-            p.pc = ctx->u[ctx->cur];
-            p.rc = ctx->r[ctx->cur];
-            p.pp = pn;
-            p.rp = rn;
-            he = fd::launch_tti(p, ctx->radius, ctx->variant, ctx->tile_cfg, s);
-            if (he == hipSuccess && nsrc) {
-                const float* q = src->data + (size_t)n * nsrc;
-                he = fd::launch_inject(pn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L, 3,
-                                       ctx->L.volume, s);
-                if (he == hipSuccess)
-                    he = fd::launch_inject(rn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L,
+        } else if (!ctx->tti) {
+            fd::AcousticStep p = acoustic_params(ctx, 1);
+            for (int n = 0; n < nt; ++n) {
+                float* un = ctx->u[1 - ctx->cur];  // holds u^{n-1}, receives u^{n+1}
+                he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, 1, s);
+                if (he == hipSuccess && nsrc)
+                    he = fd::launch_inject(un, ctx->A, sig, spts, ctx->plan[0],
+                                           src->data + (size_t)n * nsrc, scale, ctx->L, nd,
+                                           ctx->L.volume, s);
+                if (he == hipSuccess && nrec)
+                    he = fd::launch_record(un, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
+                                           nd, ctx->L.volume, s);
+                if (he != hipSuccess) return hip_fail(ctx, he, "step");
+                ctx->cur = 1 - ctx->cur;
+            }
+        } else {
+            fd::TTIStep p;
+            std::memset(&p, 0, sizeof(p));
+            p.A = ctx->A;
+            p.sig = sig;
+            p.dflag = ctx->dflag;
+            p.e = ctx->e;
+            p.d = ctx->d;
+            for (int k = 0; k < 6; ++k) p.c[k] = ctx->c[k];
+            if (ctx->damping && ctx->sep_ok && ctx->sep_use) {
+                p.sx = ctx->prof;
+                p.sy = ctx->prof + ctx->L.nx;
+                p.sz = ctx->prof + ctx->L.nx + ctx->L.ny;
+            }
+            p.L = ctx->L;
+            for (int j = 0; j <= fd::kMaxRadius; ++j) {
+                p.w2x[j] = ctx->w2[0][j];
+                p.w2y[j] = ctx->w2[1][j];
+                p.w2z[j] = ctx->w2[2][j];
+                p.w1x[j] = ctx->w1[0][j];
+                p.w1y[j] = ctx->w1[1][j];
+                p.w1z[j] = ctx->w1[2][j];
+            }
+            tile_grid(ctx, ctx->tile_y, ctx->zchunk_opt, ctx->radius, 1, nullptr, &p);
+            for (int n = 0; n < nt; ++n) {
+                float* pn = ctx->u[1 - ctx->cur];
+                float* rn = ctx->r[1 - ctx->cur];
+                p.pc = ctx->u[ctx->cur];
+                p.rc = ctx->r[ctx->cur];
+                p.pp = pn;
+                p.rp = rn;
+                he = fd::launch_tti(p, ctx->radius, ctx->variant, ctx->tile_cfg, s);
+                if (he == hipSuccess && nsrc) {
+                    const float* q = src->data + (size_t)n * nsrc;
+                    he = fd::launch_inject(pn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L, 3,
+                                           ctx->L.volume, s);
+                    if (he == hipSuccess)
+                        he = fd::launch_inject(rn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L,
+                                               3, ctx->L.volume, s);
+                }
+                if (he == hipSuccess && nrec)
+                    he = fd::launch_record(pn, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
                                            3, ctx->L.volume, s);
+                if (he != hipSuccess) return hip_fail(ctx, he, "step");
+                ctx->cur = 1 - ctx->cur;
             }
-            if (he == hipSuccess && nrec)
-                he = fd::launch_record(pn, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
-                                       3, ctx->L.volume, s);
-            if (he != hipSuccess) return hip_fail(ctx, he, "step");
-            ctx->cur = 1 - ctx->cur;
         }
-    }
-    return FD_OK;
+        return FD_OK;
+    });
 }
 
 int32_t fd_checkpoint_bytes(const fd_ctx* ctx, int32_t nt, int32_t interval, uint64_t* bytes,
@@ -1368,55 +1409,57 @@ int32_t fd_forward_checkpointed_shots(fd_ctx* ctx, int32_t nt, const fd_points* 
                                       const int32_t* src_counts, const fd_points* rec,
                                       const int32_t* rec_counts, int32_t interval, void* store,
                                       uint64_t store_bytes, void* stream) {
-    if (!ctx) return FD_ERR_INVALID_ARG;
-    ctx->err.clear();
-    if (ctx->tti || ctx->vti)
-        return fail(ctx, FD_ERR_UNSUPPORTED, "gradients are built for acoustic only");
-    if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
-    int32_t rc = check_points_arg(ctx, nt, src, "source");
-    if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver");
-    if (rc != FD_OK) return rc;
-    const int nsrc = src ? src->n : 0, nrec = rec ? rec->n : 0;
-    if ((int64_t)nsrc + nrec > ctx->max_points)
-        return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
-    rc = check_counts(ctx, src_counts, nsrc, "source");
-    if (rc == FD_OK) rc = check_counts(ctx, rec_counts, nrec, "receiver");
-    if (rc != FD_OK) return rc;
-    const int I = resolve_interval(ctx, nt, interval);
-    rc = check_store(ctx, nt, I, store, store_bytes);
-    if (rc != FD_OK) return rc;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const bool multi = ctx->nshots > 1;
-    rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nrec, rec ? rec->coords : nullptr,
-                     "source", "receiver", s, multi && nsrc ? src_counts : nullptr,
-                     multi && nrec ? rec_counts : nullptr);
-    if (rc != FD_OK) return rc;
-    ctx->ck_store = nullptr;
-    hipError_t he = hipSuccess;
-    if (ctx->flags_stale) {
-        he = refresh_flags(ctx, s);
-        if (he != hipSuccess) return hip_fail(ctx, he, "damping flags");
-        ctx->flags_stale = false;
-    }
-    for (int k = 0; k < 2 && he == hipSuccess; ++k)
-        he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume * ctx->nshots, s);
-    const Store st = plan_store(ctx, nt, I, static_cast<char*>(store));
-    const int sb = grad_sb(ctx);
-    fd::AcousticStep p = acoustic_params(ctx, sb);
-    for (int j = 0; j < st.nck && he == hipSuccess; ++j) {
-        const int n0 = j * I, n1 = n0 + I < nt ? n0 + I : nt;
-        he = pack_shots(ctx, ctx->u[1 - ctx->cur], st, 2 * j, s);
-        if (he == hipSuccess) he = pack_shots(ctx, ctx->u[ctx->cur], st, 2 * j + 1, s);
-        if (he == hipSuccess)
-            he = forward_segment(ctx, p, sb, j == st.nck - 1 ? &st : nullptr, n0, n1, src, nsrc,
-                                 rec, nrec, s);
-    }
-    if (he != hipSuccess) return hip_fail(ctx, he, "checkpointed forward");
-    ctx->ck_store = store;
-    ctx->ck_nt = nt;
-    ctx->ck_interval = I;
-    ctx->ck_last_acc = true;
-    return FD_OK;
+    return guarded(ctx, [&]() -> int32_t {
+        if (!ctx) return FD_ERR_INVALID_ARG;
+        ctx->err.clear();
+        if (ctx->tti || ctx->vti)
+            return fail(ctx, FD_ERR_UNSUPPORTED, "gradients are built for acoustic only");
+        if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
+        int32_t rc = check_points_arg(ctx, nt, src, "source");
+        if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver");
+        if (rc != FD_OK) return rc;
+        const int nsrc = src ? src->n : 0, nrec = rec ? rec->n : 0;
+        if ((int64_t)nsrc + nrec > ctx->max_points)
+            return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
+        rc = check_counts(ctx, src_counts, nsrc, "source");
+        if (rc == FD_OK) rc = check_counts(ctx, rec_counts, nrec, "receiver");
+        if (rc != FD_OK) return rc;
+        const int I = resolve_interval(ctx, nt, interval);
+        rc = check_store(ctx, nt, I, store, store_bytes);
+        if (rc != FD_OK) return rc;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const bool multi = ctx->nshots > 1;
+        rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nrec, rec ? rec->coords : nullptr,
+                         "source", "receiver", s, multi && nsrc ? src_counts : nullptr,
+                         multi && nrec ? rec_counts : nullptr);
+        if (rc != FD_OK) return rc;
+        ctx->ck_store = nullptr;
+        hipError_t he = hipSuccess;
+        if (ctx->flags_stale) {
+            he = refresh_flags(ctx, s);
+            if (he != hipSuccess) return hip_fail(ctx, he, "damping flags");
+            ctx->flags_stale = false;
+        }
+        for (int k = 0; k < 2 && he == hipSuccess; ++k)
+            he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume * ctx->nshots, s);
+        const Store st = plan_store(ctx, nt, I, static_cast<char*>(store));
+        const int sb = grad_sb(ctx);
+        fd::AcousticStep p = acoustic_params(ctx, sb);
+        for (int j = 0; j < st.nck && he == hipSuccess; ++j) {
+            const int n0 = j * I, n1 = n0 + I < nt ? n0 + I : nt;
+            he = pack_shots(ctx, ctx->u[1 - ctx->cur], st, 2 * j, s);
+            if (he == hipSuccess) he = pack_shots(ctx, ctx->u[ctx->cur], st, 2 * j + 1, s);
+            if (he == hipSuccess)
+                he = forward_segment(ctx, p, sb, j == st.nck - 1 ? &st : nullptr, n0, n1, src, nsrc,
+                                     rec, nrec, s);
+        }
+        if (he != hipSuccess) return hip_fail(ctx, he, "checkpointed forward");
+        ctx->ck_store = store;
+        ctx->ck_nt = nt;
+        ctx->ck_interval = I;
+        ctx->ck_last_acc = true;
+        return FD_OK;
+    });
 }
 
 int32_t fd_forward_checkpointed(fd_ctx* ctx, int32_t nt, const fd_points* src,
@@ -1435,111 +1478,113 @@ int32_t fd_gradient_shots(fd_ctx* ctx, int32_t nt, const fd_points* src,
                           const int32_t* adj_counts, int32_t interval, void* store,
                           uint64_t store_bytes, int32_t wrt, float* grad, float* wavelet_grad,
                           void* stream) {
-    if (!ctx) return FD_ERR_INVALID_ARG;
-    ctx->err.clear();
-    if (ctx->tti || ctx->vti)
-        return fail(ctx, FD_ERR_UNSUPPORTED, "gradients are built for acoustic only");
-    const bool accumulate = (wrt & FD_GRAD_ACCUMULATE) != 0;
-    wrt &= ~FD_GRAD_ACCUMULATE;
-    if (wrt != FD_WRT_M && wrt != FD_WRT_VEL) return fail(ctx, FD_ERR_INVALID_ARG, "wrt");
-    if (!grad) return fail(ctx, FD_ERR_INVALID_ARG, "grad is NULL");
-    const int I = resolve_interval(ctx, nt, interval);
-    if (!ctx->ck_store || store != ctx->ck_store || nt != ctx->ck_nt || I != ctx->ck_interval)
-        return fail(ctx, FD_ERR_INVALID_ARG,
-                    "store, nt and interval must match the last fd_forward_checkpointed");
-    int32_t rc = check_points_arg(ctx, nt, src, "source");
-    if (rc == FD_OK) rc = check_points_arg(ctx, nt, adj, "adjoint source");
-    if (rc != FD_OK) return rc;
-    const int nsrc = src ? src->n : 0, nadj = adj ? adj->n : 0;
-    if ((int64_t)nsrc + nadj > ctx->max_points)
-        return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
-    rc = check_counts(ctx, src_counts, nsrc, "source");
-    if (rc == FD_OK) rc = check_counts(ctx, adj_counts, nadj, "adjoint source");
-    if (rc != FD_OK) return rc;
-    rc = check_store(ctx, nt, I, store, store_bytes);
-    if (rc != FD_OK) return rc;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const bool multi = ctx->nshots > 1;
-    rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nadj, adj ? adj->coords : nullptr,
-                     "source", "adjoint source", s, multi && nsrc ? src_counts : nullptr,
-                     multi && nadj ? adj_counts : nullptr);
-    if (rc != FD_OK) return rc;
-    const Store st = plan_store(ctx, nt, I, static_cast<char*>(store));
-    const int S = ctx->nshots;
-    const int64_t vol = ctx->L.volume;
-    hipError_t he = hipSuccess;
-    for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(st.mu[k], vol * S, s);
-    if (he == hipSuccess) he = fd::launch_fill_zero(st.gpart, vol * S, s);
-    if (he == hipSuccess) he = fd::launch_fill_zero(st.gsum, st.dense * S, s);
-    int pending = 0;  // adjoint steps accumulated in gpart since the last flush
-    auto imaged = [&]() -> hipError_t {  // one more term in gpart: flush every kFlushSteps
-        if (++pending < kFlushSteps) return hipSuccess;
-        pending = 0;
-        hipError_t e = hipSuccess;
-        for (int i = 0; i < S && e == hipSuccess; ++i)
-            e = fd::launch_flush_gradient(st.gpart + i * vol, st.gsum + i * st.dense, ctx->L, s);
-        return e;
-    };
-    // the separate imaging kernel, shot by shot: gpart += mu a
-    auto image = [&](const float* mu, const float* acc) -> hipError_t {
-        hipError_t e = hipSuccess;
-        for (int i = 0; i < S && e == hipSuccess; ++i)
-            e = fd::launch_image(mu + i * vol, acc + i * vol, st.gpart + i * vol, ctx->L, s);
-        return e;
-    };
-    const int sb = grad_sb(ctx);
-    fd::AcousticStep p = acoustic_params(ctx, sb);
-    // The imaging term mu^{k+1} a^{k+1} is fused into the adjoint step that
-    // produces mu^k (its centre field is mu^{k+1}) where the tiled kernel has
-    // that variant; the first step of a segment has no a^{k+1} in the
-    // segment, so the segment's last term, mu^{n0+1} a^{n0+1}, is imaged by
-    // the separate kernel before the next segment's recomputation overwrites
-    // the slots.  The terms enter gpart in the same order and with the same
-    // fmaf as the unfused loop, so both give the same bits.
-    const bool fuse = ctx->fuse_image && ctx->g.ndim == 3 && ctx->variant == 0 &&
-                      fd::img_built(ctx->tile_cfg, sb);
-    int m = 0;  // st.mu[m] holds mu^{k+1}, st.mu[1-m] mu^{k+2}
-    for (int j = st.nck - 1; j >= 0 && he == hipSuccess; --j) {
-        const int n0 = j * I, n1 = n0 + I < nt ? n0 + I : nt;
-        if (!(j == st.nck - 1 && ctx->ck_last_acc)) {
-            he = unpack_shots(ctx, st, 2 * j, ctx->u[1 - ctx->cur], s);
-            if (he == hipSuccess) he = unpack_shots(ctx, st, 2 * j + 1, ctx->u[ctx->cur], s);
-            if (he == hipSuccess)
-                he = forward_segment(ctx, p, sb, &st, n0, n1, src, nsrc, nullptr, 0, s);
-        }
-        for (int k = n1; k > n0 && he == hipSuccess; --k) {
-            const bool fused = fuse && k < n1;
-            if (fused) {
-                p.img_a = st.slot(ctx, k - n0);  // a^{k+1}
-                p.img_g = st.gpart;
+    return guarded(ctx, [&]() -> int32_t {
+        if (!ctx) return FD_ERR_INVALID_ARG;
+        ctx->err.clear();
+        if (ctx->tti || ctx->vti)
+            return fail(ctx, FD_ERR_UNSUPPORTED, "gradients are built for acoustic only");
+        const bool accumulate = (wrt & FD_GRAD_ACCUMULATE) != 0;
+        wrt &= ~FD_GRAD_ACCUMULATE;
+        if (wrt != FD_WRT_M && wrt != FD_WRT_VEL) return fail(ctx, FD_ERR_INVALID_ARG, "wrt");
+        if (!grad) return fail(ctx, FD_ERR_INVALID_ARG, "grad is NULL");
+        const int I = resolve_interval(ctx, nt, interval);
+        if (!ctx->ck_store || store != ctx->ck_store || nt != ctx->ck_nt || I != ctx->ck_interval)
+            return fail(ctx, FD_ERR_INVALID_ARG,
+                        "store, nt and interval must match the last fd_forward_checkpointed");
+        int32_t rc = check_points_arg(ctx, nt, src, "source");
+        if (rc == FD_OK) rc = check_points_arg(ctx, nt, adj, "adjoint source");
+        if (rc != FD_OK) return rc;
+        const int nsrc = src ? src->n : 0, nadj = adj ? adj->n : 0;
+        if ((int64_t)nsrc + nadj > ctx->max_points)
+            return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
+        rc = check_counts(ctx, src_counts, nsrc, "source");
+        if (rc == FD_OK) rc = check_counts(ctx, adj_counts, nadj, "adjoint source");
+        if (rc != FD_OK) return rc;
+        rc = check_store(ctx, nt, I, store, store_bytes);
+        if (rc != FD_OK) return rc;
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const bool multi = ctx->nshots > 1;
+        rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nadj, adj ? adj->coords : nullptr,
+                         "source", "adjoint source", s, multi && nsrc ? src_counts : nullptr,
+                         multi && nadj ? adj_counts : nullptr);
+        if (rc != FD_OK) return rc;
+        const Store st = plan_store(ctx, nt, I, static_cast<char*>(store));
+        const int S = ctx->nshots;
+        const int64_t vol = ctx->L.volume;
+        hipError_t he = hipSuccess;
+        for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(st.mu[k], vol * S, s);
+        if (he == hipSuccess) he = fd::launch_fill_zero(st.gpart, vol * S, s);
+        if (he == hipSuccess) he = fd::launch_fill_zero(st.gsum, st.dense * S, s);
+        int pending = 0;  // adjoint steps accumulated in gpart since the last flush
+        auto imaged = [&]() -> hipError_t {  // one more term in gpart: flush every kFlushSteps
+            if (++pending < kFlushSteps) return hipSuccess;
+            pending = 0;
+            hipError_t e = hipSuccess;
+            for (int i = 0; i < S && e == hipSuccess; ++i)
+                e = fd::launch_flush_gradient(st.gpart + i * vol, st.gsum + i * st.dense, ctx->L, s);
+            return e;
+        };
+        // the separate imaging kernel, shot by shot: gpart += mu a
+        auto image = [&](const float* mu, const float* acc) -> hipError_t {
+            hipError_t e = hipSuccess;
+            for (int i = 0; i < S && e == hipSuccess; ++i)
+                e = fd::launch_image(mu + i * vol, acc + i * vol, st.gpart + i * vol, ctx->L, s);
+            return e;
+        };
+        const int sb = grad_sb(ctx);
+        fd::AcousticStep p = acoustic_params(ctx, sb);
+        // The imaging term mu^{k+1} a^{k+1} is fused into the adjoint step that
+        // produces mu^k (its centre field is mu^{k+1}) where the tiled kernel has
+        // that variant; the first step of a segment has no a^{k+1} in the
+        // segment, so the segment's last term, mu^{n0+1} a^{n0+1}, is imaged by
+        // the separate kernel before the next segment's recomputation overwrites
+        // the slots.  The terms enter gpart in the same order and with the same
+        // fmaf as the unfused loop, so both give the same bits.
+        const bool fuse = ctx->fuse_image && ctx->g.ndim == 3 && ctx->variant == 0 &&
+                          fd::img_built(ctx->tile_cfg, sb);
+        int m = 0;  // st.mu[m] holds mu^{k+1}, st.mu[1-m] mu^{k+2}
+        for (int j = st.nck - 1; j >= 0 && he == hipSuccess; --j) {
+            const int n0 = j * I, n1 = n0 + I < nt ? n0 + I : nt;
+            if (!(j == st.nck - 1 && ctx->ck_last_acc)) {
+                he = unpack_shots(ctx, st, 2 * j, ctx->u[1 - ctx->cur], s);
+                if (he == hipSuccess) he = unpack_shots(ctx, st, 2 * j + 1, ctx->u[ctx->cur], s);
+                if (he == hipSuccess)
+                    he = forward_segment(ctx, p, sb, &st, n0, n1, src, nsrc, nullptr, 0, s);
             }
-            he = adjoint_step(ctx, p, sb, st.mu[m], st.mu[1 - m], k, nsrc, wavelet_grad, adj,
-                              nadj, s);
-            p.img_a = nullptr;
-            p.img_g = nullptr;
-            if (he == hipSuccess && fused) he = imaged();  // mu^{k+1} a^{k+1}
-            if (he == hipSuccess && !fuse) {
-                he = image(st.mu[1 - m], st.slot(ctx, k - 1 - n0));
+            for (int k = n1; k > n0 && he == hipSuccess; --k) {
+                const bool fused = fuse && k < n1;
+                if (fused) {
+                    p.img_a = st.slot(ctx, k - n0);  // a^{k+1}
+                    p.img_g = st.gpart;
+                }
+                he = adjoint_step(ctx, p, sb, st.mu[m], st.mu[1 - m], k, nsrc, wavelet_grad, adj,
+                                  nadj, s);
+                p.img_a = nullptr;
+                p.img_g = nullptr;
+                if (he == hipSuccess && fused) he = imaged();  // mu^{k+1} a^{k+1}
+                if (he == hipSuccess && !fuse) {
+                    he = image(st.mu[1 - m], st.slot(ctx, k - 1 - n0));
+                    if (he == hipSuccess) he = imaged();
+                }
+                m = 1 - m;
+            }
+            if (he == hipSuccess && fuse && n1 > n0) {  // mu^{n0+1} a^{n0+1}
+                he = image(st.mu[m], st.slot(ctx, 0));
                 if (he == hipSuccess) he = imaged();
             }
-            m = 1 - m;
         }
-        if (he == hipSuccess && fuse && n1 > n0) {  // mu^{n0+1} a^{n0+1}
-            he = image(st.mu[m], st.slot(ctx, 0));
-            if (he == hipSuccess) he = imaged();
-        }
-    }
-    ctx->ck_last_acc = false;  // the segment slots now hold the first segment
-    if (he == hipSuccess && pending)
+        ctx->ck_last_acc = false;  // the segment slots now hold the first segment
+        if (he == hipSuccess && pending)
+            for (int i = 0; i < S && he == hipSuccess; ++i)
+                he = fd::launch_flush_gradient(st.gpart + i * vol, st.gsum + i * st.dense, ctx->L, s);
+        // shot by shot into grad: the bits of one fd_gradient per shot with
+        // FD_GRAD_ACCUMULATE from the second shot on
         for (int i = 0; i < S && he == hipSuccess; ++i)
-            he = fd::launch_flush_gradient(st.gpart + i * vol, st.gsum + i * st.dense, ctx->L, s);
-    // shot by shot into grad: the bits of one fd_gradient per shot with
-    // FD_GRAD_ACCUMULATE from the second shot on
-    for (int i = 0; i < S && he == hipSuccess; ++i)
-        he = fd::launch_finish_gradient(st.gsum + i * st.dense, ctx->A, grad, ctx->L, ctx->g.dt,
-                                        wrt == FD_WRT_VEL, (accumulate || i > 0) ? 1 : 0, s);
-    if (he != hipSuccess) return hip_fail(ctx, he, "gradient");
-    return FD_OK;
+            he = fd::launch_finish_gradient(st.gsum + i * st.dense, ctx->A, grad, ctx->L, ctx->g.dt,
+                                            wrt == FD_WRT_VEL, (accumulate || i > 0) ? 1 : 0, s);
+        if (he != hipSuccess) return hip_fail(ctx, he, "gradient");
+        return FD_OK;
+    });
 }
 
 int32_t fd_gradient(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_points* adj,
@@ -1562,97 +1607,101 @@ int32_t fd_misfit(const float* d, const float* d_obs, int64_t n, float* res, dou
 
 int32_t fd_adjoint(fd_ctx* ctx, int32_t nt, const fd_points* adj, const fd_points* out,
                    void* stream) {
-    if (!ctx) return FD_ERR_INVALID_ARG;
-    ctx->err.clear();
-    if (ctx->nshots > 1)
-        return fail(ctx, FD_ERR_INVALID_ARG, "a context of several shots steps with fd_forward_shots");
-    if (ctx->tti || ctx->vti)
-        return fail(ctx, FD_ERR_UNSUPPORTED, "the adjoint is built for acoustic only");
-    if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
-    int32_t rc = check_points_arg(ctx, nt, adj, "adjoint source");
-    if (rc == FD_OK) rc = check_points_arg(ctx, nt, out, "source");
-    if (rc != FD_OK) return rc;
-    const int nadj = adj ? adj->n : 0, nsrc = out ? out->n : 0;
-    if ((int64_t)nsrc + nadj > ctx->max_points)
-        return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    rc = sync_points(ctx, nsrc, out ? out->coords : nullptr, nadj, adj ? adj->coords : nullptr,
-                     "source", "adjoint source", s);
-    if (rc != FD_OK) return rc;
-    hipError_t he = hipSuccess;
-    if (ctx->flags_stale) {
-        he = refresh_flags(ctx, s);
-        if (he != hipSuccess) return hip_fail(ctx, he, "damping flags");
-        ctx->flags_stale = false;
-    }
-    for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume, s);
-    fd::AcousticStep p = acoustic_params(ctx, 1);
-    for (int k = nt; k >= 1 && he == hipSuccess; --k) {
-        he = adjoint_step(ctx, p, 1, ctx->u[ctx->cur], ctx->u[1 - ctx->cur], k, nsrc,
-                          out ? out->data : nullptr, adj, nadj, s);
-        ctx->cur = 1 - ctx->cur;
-    }
-    if (he != hipSuccess) return hip_fail(ctx, he, "adjoint");
-    return FD_OK;
+    return guarded(ctx, [&]() -> int32_t {
+        if (!ctx) return FD_ERR_INVALID_ARG;
+        ctx->err.clear();
+        if (ctx->nshots > 1)
+            return fail(ctx, FD_ERR_INVALID_ARG, "a context of several shots steps with fd_forward_shots");
+        if (ctx->tti || ctx->vti)
+            return fail(ctx, FD_ERR_UNSUPPORTED, "the adjoint is built for acoustic only");
+        if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
+        int32_t rc = check_points_arg(ctx, nt, adj, "adjoint source");
+        if (rc == FD_OK) rc = check_points_arg(ctx, nt, out, "source");
+        if (rc != FD_OK) return rc;
+        const int nadj = adj ? adj->n : 0, nsrc = out ? out->n : 0;
+        if ((int64_t)nsrc + nadj > ctx->max_points)
+            return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        rc = sync_points(ctx, nsrc, out ? out->coords : nullptr, nadj, adj ? adj->coords : nullptr,
+                         "source", "adjoint source", s);
+        if (rc != FD_OK) return rc;
+        hipError_t he = hipSuccess;
+        if (ctx->flags_stale) {
+            he = refresh_flags(ctx, s);
+            if (he != hipSuccess) return hip_fail(ctx, he, "damping flags");
+            ctx->flags_stale = false;
+        }
+        for (int k = 0; k < 2 && he == hipSuccess; ++k) he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume, s);
+        fd::AcousticStep p = acoustic_params(ctx, 1);
+        for (int k = nt; k >= 1 && he == hipSuccess; --k) {
+            he = adjoint_step(ctx, p, 1, ctx->u[ctx->cur], ctx->u[1 - ctx->cur], k, nsrc,
+                              out ? out->data : nullptr, adj, nadj, s);
+            ctx->cur = 1 - ctx->cur;
+        }
+        if (he != hipSuccess) return hip_fail(ctx, he, "adjoint");
+        return FD_OK;
+    });
 }
 
 int32_t fd_forward_shots(fd_ctx* ctx, int32_t nt, const fd_points* src, const int32_t* src_counts,
                          const fd_points* rec, const int32_t* rec_counts, int32_t flags,
                          void* stream) {
-    if (!ctx) return FD_ERR_INVALID_ARG;
-    ctx->err.clear();
-    if (ctx->tti || ctx->vti)
-        return fail(ctx, FD_ERR_UNSUPPORTED, "several shots are built for acoustic only");
-    if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
-    const bool keep = (flags & FD_KEEP_POINTS) != 0;
-    int32_t rc = check_points_arg(ctx, nt, src, "source", keep);
-    if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver", keep);
-    if (rc != FD_OK) return rc;
-    const int nsrc = src ? src->n : 0, nrec = rec ? rec->n : 0;
-    if ((int64_t)nsrc + nrec > ctx->max_points)
-        return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int nd = ctx->g.ndim;
-    if (keep) {
-        // the shots of the points are those of the last upload
-        rc = keep_points(ctx, nsrc, nrec);
-    } else {
-        rc = check_counts(ctx, src_counts, nsrc, "source");
-        if (rc == FD_OK) rc = check_counts(ctx, rec_counts, nrec, "receiver");
-        if (rc == FD_OK)
-            rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nrec,
-                             rec ? rec->coords : nullptr, "source", "receiver", s,
-                             nsrc ? src_counts : nullptr, nrec ? rec_counts : nullptr);
-    }
-    if (rc != FD_OK) return rc;
-    hipError_t he = hipSuccess;
-    if (ctx->flags_stale) {
-        he = refresh_flags(ctx, s);
-        if (he != hipSuccess) return hip_fail(ctx, he, "damping flags");
-        ctx->flags_stale = false;
-    }
-    if (flags & FD_ZERO_STATE)
-        for (int k = 0; k < 2 && he == hipSuccess; ++k)
-            he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume * ctx->nshots, s);
-    if (he != hipSuccess) return hip_fail(ctx, he, "zero state");
-    const float scale = (float)(1.0 / cell_volume(ctx));
-    const float* sig = ctx->damping ? ctx->sig : nullptr;
-    const int sb = ctx_sb(ctx);
-    fd::AcousticStep p = acoustic_params(ctx, sb);
-    for (int n = 0; n < nt; ++n) {
-        float* un = ctx->u[1 - ctx->cur];
-        he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, sb, s);
-        if (he == hipSuccess && nsrc)
-            he = fd::launch_inject(un, ctx->A, sig, ctx->pts, ctx->plan[0],
-                                   src->data + (size_t)n * nsrc, scale, ctx->L, nd,
-                                   ctx->L.volume, s);
-        if (he == hipSuccess && nrec)
-            he = fd::launch_record(un, ctx->pts + nsrc, nrec, rec->data + (size_t)n * nrec, 1.f,
-                                   ctx->L, nd, ctx->L.volume, s);
-        if (he != hipSuccess) return hip_fail(ctx, he, "step");
-        ctx->cur = 1 - ctx->cur;
-    }
-    return FD_OK;
+    return guarded(ctx, [&]() -> int32_t {
+        if (!ctx) return FD_ERR_INVALID_ARG;
+        ctx->err.clear();
+        if (ctx->tti || ctx->vti)
+            return fail(ctx, FD_ERR_UNSUPPORTED, "several shots are built for acoustic only");
+        if (nt < 0) return fail(ctx, FD_ERR_INVALID_ARG, "nt < 0");
+        const bool keep = (flags & FD_KEEP_POINTS) != 0;
+        int32_t rc = check_points_arg(ctx, nt, src, "source", keep);
+        if (rc == FD_OK) rc = check_points_arg(ctx, nt, rec, "receiver", keep);
+        if (rc != FD_OK) return rc;
+        const int nsrc = src ? src->n : 0, nrec = rec ? rec->n : 0;
+        if ((int64_t)nsrc + nrec > ctx->max_points)
+            return fail(ctx, FD_ERR_INVALID_ARG, "more points than max_points");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        const int nd = ctx->g.ndim;
+        if (keep) {
+            // the shots of the points are those of the last upload
+            rc = keep_points(ctx, nsrc, nrec);
+        } else {
+            rc = check_counts(ctx, src_counts, nsrc, "source");
+            if (rc == FD_OK) rc = check_counts(ctx, rec_counts, nrec, "receiver");
+            if (rc == FD_OK)
+                rc = sync_points(ctx, nsrc, src ? src->coords : nullptr, nrec,
+                                 rec ? rec->coords : nullptr, "source", "receiver", s,
+                                 nsrc ? src_counts : nullptr, nrec ? rec_counts : nullptr);
+        }
+        if (rc != FD_OK) return rc;
+        hipError_t he = hipSuccess;
+        if (ctx->flags_stale) {
+            he = refresh_flags(ctx, s);
+            if (he != hipSuccess) return hip_fail(ctx, he, "damping flags");
+            ctx->flags_stale = false;
+        }
+        if (flags & FD_ZERO_STATE)
+            for (int k = 0; k < 2 && he == hipSuccess; ++k)
+                he = fd::launch_fill_zero(ctx->u[k], ctx->L.volume * ctx->nshots, s);
+        if (he != hipSuccess) return hip_fail(ctx, he, "zero state");
+        const float scale = (float)(1.0 / cell_volume(ctx));
+        const float* sig = ctx->damping ? ctx->sig : nullptr;
+        const int sb = ctx_sb(ctx);
+        fd::AcousticStep p = acoustic_params(ctx, sb);
+        for (int n = 0; n < nt; ++n) {
+            float* un = ctx->u[1 - ctx->cur];
+            he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, sb, s);
+            if (he == hipSuccess && nsrc)
+                he = fd::launch_inject(un, ctx->A, sig, ctx->pts, ctx->plan[0],
+                                       src->data + (size_t)n * nsrc, scale, ctx->L, nd,
+                                       ctx->L.volume, s);
+            if (he == hipSuccess && nrec)
+                he = fd::launch_record(un, ctx->pts + nsrc, nrec, rec->data + (size_t)n * nrec, 1.f,
+                                       ctx->L, nd, ctx->L.volume, s);
+            if (he != hipSuccess) return hip_fail(ctx, he, "step");
+            ctx->cur = 1 - ctx->cur;
+        }
+        return FD_OK;
+    });
 }
 
 static float* field_ptr(fd_ctx* ctx, int32_t shot, int32_t which) {
@@ -1845,6 +1894,7 @@ const char* fd_strerror(int32_t status) {
         case FD_ERR_WORKSPACE: return "workspace too small or misaligned";
         case FD_ERR_DEVICE: return "HIP runtime error";
         case FD_ERR_NONFINITE: return "non-finite or non-positive model values";
+        case FD_ERR_HOST: return "host memory could not be obtained";
         default: return "unknown status";
     }
 }

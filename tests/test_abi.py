@@ -124,9 +124,20 @@ def test_null_context_and_strings():
     assert lib.fd_set_option(None, 1, 0) == P.FD_ERR_INVALID_ARG
     assert lib.fd_destroy(None) == P.FD_OK
     assert P.fd_last_error(None) == ""
-    for c in range(7):
-        assert len(P.fd_strerror(c)) > 3
+    for c in range(8):
+        assert len(P.fd_strerror(c)) > 3 and P.fd_strerror(c) != "unknown status"
+    assert "host" in P.fd_strerror(P.FD_ERR_HOST)
     assert P.fd_strerror(99) == "unknown status"
+
+
+def test_binding_status_codes_match_the_header():
+    """Every FD_ERR_* status the header defines has the same value in the
+    binding."""
+    hdr = (Path(__file__).resolve().parent.parent / "include" / "fd.h").read_text()
+    codes = dict(re.findall(r"#define (FD_(?:OK|ERR_[A-Z_]+)) (\d+)", hdr))
+    assert "FD_ERR_HOST" in codes
+    for name, value in codes.items():
+        assert getattr(P, name) == int(value), name
 
 
 def test_triad_config_rejects_bad_shapes():
