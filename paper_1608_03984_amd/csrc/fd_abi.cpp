@@ -546,6 +546,9 @@ int32_t sync_points(fd_ctx* ctx, int n1, const double* c1, int n2, const double*
         if (set == 0) nt1 = (int32_t)tg.size() - t0;
     }
     st.push_back((int32_t)en.size());
+    // the device tables change from here on: until they are complete no later
+    // call may take them for the previous upload's
+    ctx->nsrc_dev = ctx->nrec_dev = -1;
     if (!host.empty()) {
         hipError_t he = hipMemcpyAsync(ctx->pts, host.data(), host.size() * sizeof(SparsePoint),
                                        hipMemcpyHostToDevice, s);
