@@ -469,8 +469,8 @@ int32_t fd_restrict(fd_ctx* ctx, int32_t which, int32_t stride, float* dst, void
  *   4 = 64x24 with 768, -1 = the default for the space order, shot count and
  *   grid (one shot: 4 up to space order 6 when its x-y tiles number 90-100 %
  *   of the device's compute units, else 0); of the tiled TTI
- *   kernel: 0 = 64x8 with 512 threads, 1 = 64x4 with 256, 2 = 64x16 with
- *   1024 (space orders up to 8, else FD_ERR_UNSUPPORTED), -1 = the default
+ *   kernel: 0 = 64x8 with 512 threads, 1 = 64x4 with 256, 2 = 64x15 with
+ *   960 (space orders up to 8, else FD_ERR_UNSUPPORTED), -1 = the default
  *   (2 up to space order 8 when its x-y tiles number 90-100 % of the
  *   device's compute units, else 0).
  *   FD_ERR_UNSUPPORTED for VTI (one tile shape).

@@ -375,12 +375,13 @@ int default_shots_per_block(int radius, int nshots) {
 }
 int shots_tile(int radius) { return radius <= 6 ? 2 : 0; }
 
-// TTI (measured at 464^3, so 8): 64 x 16 tiles of 1024 threads where they
-// fit 128 registers per lane (radius up to 4) and fill the chip once, 1.15
+// TTI (measured at 464^3, so 8): 64 x 15 tiles of 960 threads where they
+// fit 128 registers per lane (radius up to 4) and fill the chip once, 1.12
 // ms per step against 1.33 for 64 x 8 of 512 threads: the y halo is 8 rows
-// per 16 instead of per 8, and the 232 column blocks each hold a CU alone,
+// per 15 instead of per 8, and the 248 column blocks each hold a CU alone,
 // so no block is slowed by a neighbour on its CU and neighbouring tiles keep
-// marching through the same planes.  64 x 8 otherwise.
+// marching through the same planes (64 x 16 tiles, 232 blocks, took 1.15
+// ms).  64 x 8 otherwise.
 int tti_default_tile(const fd_ctx* ctx) {
     return ctx->radius <= fd::kTTITallMaxRadius &&
                    fills_chip_once(ctx, fd::kTTITiles[2].height())
@@ -1027,7 +1028,7 @@ int32_t fd_setup_shots(const fd_grid* grid, const fd_model* model, int32_t nshot
             he = derive_coefficients(ctx, model, ctx->u[0], s, chk);
             return FD_OK;
         }) != FD_OK) {
-        hipStreamSynchronize(s);
+        (void)hipStreamSynchronize(s);  // no upload may still read the host copies
         delete ctx;
         return FD_ERR_HOST;
     }
@@ -1102,7 +1103,7 @@ int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value) {
                 if (v > 2) return fail(ctx, FD_ERR_INVALID_ARG, "TTI tile configuration is 0..2");
                 if (v == 2 && ctx->radius > fd::kTTITallMaxRadius)
                     return fail(ctx, FD_ERR_UNSUPPORTED,
-                                "the 64x16 TTI tile is built for space orders up to 8");
+                                "the 64x15 TTI tile is built for space orders up to 8");
                 ctx->tile_cfg = v;
                 ctx->tile_y = fd::tti_tile_y(v);
                 ctx->flags_stale = true;  // rebuilt on the caller's stream by fd_forward

@@ -230,10 +230,10 @@ struct TileShape {
 // acoustic FD_OPT_TILE configurations 0..4: 64 x 8, 64 x 16, 64 x 8, 64 x 16,
 // 64 x 24
 constexpr TileShape kAcousticTiles[5] = {{4, 2}, {4, 4}, {8, 1}, {8, 2}, {12, 2}};
-// TTI FD_OPT_TILE configurations 0..2: 64 x 8, 64 x 4, 64 x 16 (radius up to
-// 4: a 1024-thread block must fit in 128 registers per lane; the default
+// TTI FD_OPT_TILE configurations 0..2: 64 x 8, 64 x 4, 64 x 15 (radius up to
+// 4: a 960-thread block must fit in 128 registers per lane; the default
 // there, 64 x 8 above)
-constexpr TileShape kTTITiles[3] = {{8, 1}, {4, 1}, {16, 1}};
+constexpr TileShape kTTITiles[3] = {{8, 1}, {4, 1}, {15, 1}};
 constexpr int kTTITallMaxRadius = 4;
 // VTI: 64 x 16, one row per wave (1024 threads; up to 110 registers per lane
 // at radius 8, so the block fits a CU at every order)

@@ -440,7 +440,7 @@ struct TiledTTI {
 // Waves per SIMD the compiler is asked to fit (register budget 512 / waves):
 // radius up to 4 with 64 x 8 tiles fits four (128 registers) without
 // spilling, so two blocks share a CU and a 464^3 grid's 464 column blocks
-// are all resident at once; 64 x 16 tiles (16 waves) need four to fit one
+// are all resident at once; 64 x 15 tiles (15 waves) need four to fit one
 // block; the other shapes keep the compiler's choice.
 template <int R, int NW>
 constexpr int tti_waves_per_simd() { return (R <= 4 && NW >= 8) ? 4 : 1; }

@@ -37,7 +37,7 @@ def gpu_run(p, variant=0, damping_profile=None, tile=None):
 def test_tti_multi_tile_full_run(so, variant, tile):
     """60 steps on a grid of several tiles in x and y (ragged in both) with
     the damping layer: the tiled kernel with 64 x 8 (tile 0), 64 x 4 (tile 1)
-    and 64 x 16 (tile 2) tiles and the direct kernel (variant 1)."""
+    and 64 x 15 (tile 2) tiles and the direct kernel (variant 1)."""
     p = tti_problem((80, 26, 22), 6, so, 60, seed=200 + so)
     say(f"case: tti {p.padded} so{so} variant{variant} tile{tile}")
     tr, u, r = gpu_run(p, variant, tile=tile)
@@ -66,9 +66,9 @@ def test_tti_damping_profiles(tile):
 @pytest.mark.parametrize("tile", [0, 1, 2])
 def test_tti_one_step_from_common_state(so, tile):
     """One step from a common noise state at every point, for every tile
-    shape of the tiled kernel (64 x 8, 64 x 4, and 64 x 16 up to so 8)."""
+    shape of the tiled kernel (64 x 8, 64 x 4, and 64 x 15 up to so 8)."""
     if tile == 2 and so > 8:
-        pytest.skip("the 64 x 16 tile is built for space orders up to 8")
+        pytest.skip("the 64 x 15 tile is built for space orders up to 8")
     p = tti_problem((70, 18, 20), 4, so, 1, seed=so)
     shape = p.padded
     st = [noise_state(shape, 20 + k) for k in range(4)]
@@ -120,7 +120,7 @@ def test_tti_full_size_one_step_sampled():
 
 
 def test_tti_tall_tile_limited_to_so8():
-    """The 64 x 16 tile is refused above so 8 (its 1024-thread blocks fit
+    """The 64 x 15 tile is refused above so 8 (its 960-thread blocks fit
     128 registers per lane only up to radius 4) and out-of-range tiles are
     refused; the context keeps its previous tile, and -1 (the default for
     the order) is accepted."""
