@@ -44,6 +44,7 @@ ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_PEAK_TFLOPS = 78.6        # MI355X FP32 vector arithmetic without packed instructions
 TRAFFIC_SUMMARY = ROOT / "profiles" / "acoustic3d_tiled_592cubed_traffic.md"
 KERNEL_SOURCES = [ROOT / "paper_1608_03984_amd" / "csrc" / f
                   for f in ("fd_acoustic_tiled.h", "fd_acoustic.hip", "fd_acoustic_hi.hip",
@@ -315,6 +316,15 @@ def tti_bench(args, physics="tti"):
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": f"{name} stencil ({nbytes} B per point update)"},
         "gflops_paper": round(nflops * npts / kernel_s / 1e9, 1),
+        # the paper's FLOP count against the FP32 vector roofs (non-packed,
+        # as built, and packed): above 1 means the kernel does less arithmetic
+        # than the count (symmetric pairs summed first, first derivatives of
+        # the mixed terms formed once and reused)
+        "alu": {"flops_per_pt_paper": nflops,
+                "tflops_paper": round(nflops * npts / kernel_s / 1e12, 2),
+                "peak_fp32_tflops": FP32_PEAK_TFLOPS, "peak_packed_fp32_tflops": 157.3,
+                "frac": round(nflops * npts / kernel_s / 1e12 / FP32_PEAK_TFLOPS, 4),
+                "frac_packed": round(nflops * npts / kernel_s / 1e12 / 157.3, 4)},
         "stencil_ms": round(kernel_s * 1e3, 4), "finite": ok,
     }
     print(json.dumps(line), flush=True)
