@@ -497,6 +497,13 @@ int32_t fd_restrict(fd_ctx* ctx, int32_t which, int32_t stride, float* dst, void
 #define FD_OPT_FUSED_IMAGING 6
 int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value);
 
+/* The value an option has on ctx: the caller's last setting, or the default
+ * the context chose for its grid, order, shot count and device (for
+ * FD_OPT_TILE the configuration number; for FD_OPT_ZCHUNK 0 = automatic).
+ * *value is written only on FD_OK; an unknown option is FD_ERR_INVALID_ARG.
+ * Pure host. */
+int32_t fd_get_option(const fd_ctx* ctx, int32_t option, int64_t* value);
+
 /* Frees the host context (not the workspace). NULL is accepted. */
 int32_t fd_destroy(fd_ctx* ctx);
 

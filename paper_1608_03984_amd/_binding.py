@@ -64,6 +64,7 @@ EXPORTS = (
     "fd_cnn_wgrad_scratch", "fd_cnn_wgrad", "fd_cnn_loss_grad", "fd_cnn_adam", "fd_cnn_features",
     "fd_cnn_correct", "fd_cnn_residual", "fd_restrict", "fd_triad_config",
     "fd_cnn_wgrad_noalloc", "fd_forward_checkpointed_shots", "fd_gradient_shots",
+    "fd_get_option",
 )
 
 
@@ -122,6 +123,7 @@ def lib() -> ctypes.CDLL:
             "fd_stencil_weights": (i32, [i32, i32, ctypes.POINTER(ctypes.c_double)]),
             "fd_cfl_dt": (i32, [gp, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]),
             "fd_set_option": (i32, [vp, i32, ctypes.c_int64]),
+            "fd_get_option": (i32, [vp, i32, ctypes.POINTER(ctypes.c_int64)]),
             "fd_destroy": (i32, [vp]),
             "fd_strerror": (ctypes.c_char_p, [i32]),
             "fd_last_error": (ctypes.c_char_p, [vp]),
@@ -257,6 +259,12 @@ def fd_set_field(ctx, which: int, src_ptr: int, stream: int):
 
 def fd_set_option(ctx, option: int, value: int):
     _check(lib().fd_set_option(ctx, int(option), int(value)), "fd_set_option", ctx)
+
+
+def fd_get_option(ctx, option: int) -> int:
+    v = ctypes.c_int64(0)
+    _check(lib().fd_get_option(ctx, int(option), ctypes.byref(v)), "fd_get_option", ctx)
+    return int(v.value)
 
 
 def fd_destroy(ctx):

@@ -1146,6 +1146,19 @@ int32_t fd_set_option(fd_ctx* ctx, int32_t option, int64_t value) {
     }
 }
 
+int32_t fd_get_option(const fd_ctx* ctx, int32_t option, int64_t* value) {
+    if (!ctx || !value) return FD_ERR_INVALID_ARG;
+    switch (option) {
+        case FD_OPT_KERNEL: *value = ctx->variant; return FD_OK;
+        case FD_OPT_ZCHUNK: *value = ctx->zchunk_opt; return FD_OK;
+        case FD_OPT_TILE: *value = ctx->tile_cfg; return FD_OK;
+        case FD_OPT_SHOTS_PER_BLOCK: *value = ctx->shots_per_block; return FD_OK;
+        case FD_OPT_DAMPING_PROFILE: *value = ctx->sep_use ? 1 : 0; return FD_OK;
+        case FD_OPT_FUSED_IMAGING: *value = ctx->fuse_image ? 1 : 0; return FD_OK;
+        default: return FD_ERR_INVALID_ARG;
+    }
+}
+
 int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_points* rec,
                    int32_t flags, void* stream) {
     return guarded(ctx, [&]() -> int32_t {

@@ -270,6 +270,9 @@ class Solver:
     def set_option(self, option, value):
         B.fd_set_option(self.ctx, option, value)
 
+    def get_option(self, option):
+        return B.fd_get_option(self.ctx, option)
+
     def close(self):
         if getattr(self, "ctx", None):
             B.fd_destroy(self.ctx)

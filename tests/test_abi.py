@@ -122,6 +122,7 @@ def test_null_context_and_strings():
     assert lib.fd_forward(None, 1, None, None, 0, None) == P.FD_ERR_INVALID_ARG
     assert lib.fd_get_field(None, 0, None, None) == P.FD_ERR_INVALID_ARG
     assert lib.fd_set_option(None, 1, 0) == P.FD_ERR_INVALID_ARG
+    assert lib.fd_get_option(None, 1, None) == P.FD_ERR_INVALID_ARG
     assert lib.fd_destroy(None) == P.FD_OK
     assert P.fd_last_error(None) == ""
     for c in range(8):
