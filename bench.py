@@ -93,10 +93,15 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+# (waves per block, rows per lane) of the tiled acoustic kernel's tile
+# configurations, as FD_OPT_TILE numbers them
+ACOUSTIC_TILES = {0: (4, 2), 1: (4, 4), 2: (8, 1), 3: (8, 2), 4: (12, 2)}
+
+
 def committed_traffic(phys: int):
-    """Per-order HBM bytes per launch from the committed counter summary, or
-    None when the summary is missing, for another size, or older than the
-    kernel source."""
+    """Per-order (kernel, HBM bytes per launch) from the committed counter
+    summary, or None when the summary is missing, for another size, or older
+    than the kernel source."""
     if phys != 512 or not TRAFFIC_SUMMARY.exists():
         return None
     m = re.search(r"<!-- machine-readable: (.*) -->", TRAFFIC_SUMMARY.read_text())
@@ -105,7 +110,18 @@ def committed_traffic(phys: int):
     data = json.loads(m.group(1))
     if data["source_sha256_16"] != kernel_source_hash():
         return None
-    return {int(k): v["traffic_bytes"] for k, v in data["per_order"].items()}
+    return {int(k): (v["kernel"], v["traffic_bytes"]) for k, v in data["per_order"].items()}
+
+
+def traffic_of(traffic, so: int, tile: int):
+    """The committed bytes of order so if they were counted for the kernel
+    the context launches (radius, waves, rows of its tile, one shot), else
+    None."""
+    if not traffic or so not in traffic or tile not in ACOUSTIC_TILES:
+        return None
+    kernel, nbytes = traffic[so]
+    nw, vy = ACOUSTIC_TILES[tile]
+    return nbytes if kernel.startswith(f"acoustic3d_tiled<{so // 2}, {nw}, {vy}, 1,") else None
 
 
 TRIAD_SWEEP = [(u, b, f) for f in (0, 1) for u in (1, 2, 4, 8) for b in (0, 2048, 4096, 8192)]
@@ -903,6 +919,7 @@ def main():
         traces = torch.empty((nt, rec.shape[0]), dtype=torch.float32, device=dev)
         s = Solver(3, prob.shape, prob.spacing, prob.nbl, so, dt, prob.vel, prob.eta,
                    max_points=1 + rec.shape[0], device=dev)
+        tile = s.get_option(P.FD_OPT_TILE)
         ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
         # upload the point tables (no steps), settle the GPU, warm up
         s.forward(0, prob.src, wav[:0], rec)
@@ -926,7 +943,7 @@ def main():
         per.append({"so": so, "gpts": round(gpts, 2), "ms_per_step": round(tw / args.steps * 1e3, 4),
                     "stencil_ms": round(kernel_ms, 4), "stencil_gbs": round(achieved, 1),
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": traffic.get(so) if traffic else None,
+                    "traffic": traffic_of(traffic, so, tile),
                     "gflops_paper": round(paper_flops(so) * npts / (kernel_ms / 1e3) / 1e9, 1),
                     "finite": ok})
         print(f"# so{so}: {gpts:.1f} Gpt/s, stencil {kernel_ms:.3f} ms = {achieved:.0f} GB/s",
@@ -937,8 +954,9 @@ def main():
     value = tot_pts / tot_time / 1e9
     ach = BYTES_PER_POINT * tot_pts / tot_kernel / 1e9
     tgbs, tcfg = triad_gbs(torch, P)
-    mean_traffic = (round(sum(traffic[so] for so in orders) / len(orders))
-                    if traffic and all(so in traffic for so in orders) else None)
+    counted = [o["traffic"] for o in per]
+    mean_traffic = (round(sum(counted) / len(counted))
+                    if counted and all(c is not None for c in counted) else None)
     line = {
         "metric": "Gpt/s, % roofline (3D acoustic SO4-16)",
         "value": round(value, 3),

@@ -467,7 +467,7 @@ int32_t fd_restrict(fd_ctx* ctx, int32_t which, int32_t stride, float* dst, void
  * FD_OPT_TILE: (x, y) tile of the tiled 3D acoustic kernel: 0 = 64x8 with 256
  *   threads, 1 = 64x16 with 256, 2 = 64x8 with 512, 3 = 64x16 with 512,
  *   4 = 64x24 with 768, -1 = the default for the space order, shot count and
- *   grid (one shot: 4 up to space order 6 when its x-y tiles number 90-100 %
+ *   grid (one shot: 4 up to space order 8 when its x-y tiles number 90-100 %
  *   of the device's compute units, else 0); of the tiled TTI
  *   kernel: 0 = 64x8 with 512 threads, 1 = 64x4 with 256, 2 = 64x15 with
  *   960 (space orders up to 8, else FD_ERR_UNSUPPORTED), -1 = the default

@@ -351,16 +351,16 @@ bool fills_chip_once(const fd_ctx* ctx, int tile_y) {
 
 // Tile shape of the tiled acoustic kernel (measured on the 592^3 workload
 // with the damping layer evaluated from its profiles, whole columns):
-// 64 x 24 with 768 threads up to radius 3 where its blocks fill the chip
+// 64 x 24 with 768 threads up to radius 4 where its blocks fill the chip
 // once (250 blocks at 592^3, one per CU, fewer halo rows per point: 582 /
-// 585 / 608 us at so 2 / 4 / 6 against 621 / 621 / 631 for 64 x 8), else
-// 64 x 8 with 256 threads (740 blocks at 592^3, up to three per CU, all
-// resident at once: 624 / 670 / 715 us at so 8 / 12 / 16 against 628 / 663
-// / 741 for 64 x 24, whose single block per CU lines all its waves up at
+// 576 / 608 / 616 us at so 2 / 4 / 6 / 8 against 621 / 603 / 631 / 626 for
+// 64 x 8), else 64 x 8 with 256 threads (740 blocks at 592^3, up to three
+// per CU, all resident at once: 668 / 706 us at so 12 / 16 against 668 /
+// 746 for 64 x 24, whose single block per CU lines all its waves up at
 // every barrier while the longer steps of these orders need independent
 // blocks to overlap).
 int default_tile(const fd_ctx* ctx) {
-    return ctx->radius <= 3 && fills_chip_once(ctx, fd::kAcousticTiles[4].height()) ? 4 : 0;
+    return ctx->radius <= 4 && fills_chip_once(ctx, fd::kAcousticTiles[4].height()) ? 4 : 0;
 }
 
 // Several shots (measured with 16 shots on the 336^3 survey grid, three z

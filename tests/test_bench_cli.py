@@ -1,8 +1,9 @@
 """The benchmark's command line without a GPU: more than one GPU is refused
 with a message and a non-zero status (the solver has no multi-GPU path), the
 gradient byte count that the gradient benches report against matches its
-terms, and the hash that ties the committed traffic counters to the kernel
-covers the sources and their per-source build flags."""
+terms, the hash that ties the committed traffic counters to the kernel
+covers the sources and their per-source build flags, and a counted byte
+figure is reported only for the kernel it was counted for."""
 import json
 import subprocess
 import sys
@@ -52,3 +53,20 @@ def test_kernel_hash_covers_sources_and_build_flags():
         _build.EXTRA.clear()
         _build.EXTRA.update(saved)
     assert bench.kernel_source_hash() == h
+
+
+def test_traffic_is_used_only_for_the_launched_kernel():
+    """A committed per-order byte count is reported only when it was counted
+    for the kernel the context launches (radius, waves and rows of its tile)."""
+    sys.path.insert(0, str(ROOT))
+    import bench
+
+    t = {4: ("acoustic3d_tiled<2, 12, 2, 1, false, true, false>", 100),
+         8: ("acoustic3d_tiled<4, 4, 2, 1, false, true, false>", 200)}
+    assert bench.traffic_of(t, 4, 4) == 100
+    assert bench.traffic_of(t, 4, 0) is None        # counted for 64 x 24, launched 64 x 8
+    assert bench.traffic_of(t, 8, 0) == 200
+    assert bench.traffic_of(t, 8, 4) is None
+    assert bench.traffic_of(t, 12, 0) is None       # not counted
+    assert bench.traffic_of(None, 4, 4) is None
+    assert bench.traffic_of(t, 4, 9) is None        # no such tile

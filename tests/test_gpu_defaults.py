@@ -1,6 +1,6 @@
 """The launch configuration a context chooses by itself, read back with
 fd_get_option: tiles of one block per compute unit (acoustic 64 x 24 up to
-so 6, TTI 64 x 15 up to so 8) only where their x-y tiles number 90-100 % of
+so 8, TTI 64 x 15 up to so 8) only where their x-y tiles number 90-100 % of
 the device's compute units, the smaller tiles otherwise; a setting is read
 back as set, and -1 returns to the default."""
 import pytest
@@ -38,7 +38,7 @@ def test_acoustic_default_tile(phys_xy, so):
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
     s, n = context(phys_xy, so)
     say(f"case: acoustic default tile {n}^2 x-y so{so}, {ncu} CUs")
-    want = 4 if so <= 6 and fills_once(n, 24, ncu) else 0
+    want = 4 if so <= 8 and fills_once(n, 24, ncu) else 0
     assert s.get_option(P.FD_OPT_TILE) == want
     assert s.get_option(P.FD_OPT_SHOTS_PER_BLOCK) == 1
     assert s.get_option(P.FD_OPT_ZCHUNK) == 0
