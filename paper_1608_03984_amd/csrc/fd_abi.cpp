@@ -54,6 +54,9 @@ struct fd_ctx {
     int32_t* plan_start;
     int32_t* plan_entry;
     fd::InjectPlan plan[2];
+    // smallest and largest target of each plan (meaningful for one shot,
+    // where the targets are sorted by index)
+    int64_t plan_lo[2], plan_hi[2];
     int cur;  // index of the level holding u^n in u[]/r[]
     // derived stencil coefficients (float, already divided by h or h^2)
     float w2[3][fd::kMaxRadius + 1];
@@ -572,6 +575,10 @@ int32_t sync_points(fd_ctx* ctx, int n1, const double* c1, int n2, const double*
     ctx->plan[0] = {ctx->plan_target, ctx->plan_shot, ctx->plan_start, ctx->plan_entry, nt1};
     ctx->plan[1] = {ctx->plan_target + nt1, ctx->plan_shot + nt1, ctx->plan_start + nt1,
                     ctx->plan_entry, ntot - nt1};
+    ctx->plan_lo[0] = nt1 > 0 ? tg[0] : 0;
+    ctx->plan_hi[0] = nt1 > 0 ? tg[(size_t)nt1 - 1] : -1;
+    ctx->plan_lo[1] = ntot > nt1 ? tg[(size_t)nt1] : 0;
+    ctx->plan_hi[1] = ntot > nt1 ? tg[(size_t)ntot - 1] : -1;
     ctx->src_coords.swap(a);
     ctx->rec_coords.swap(b);
     ctx->src_counts.swap(k1);
@@ -1252,18 +1259,44 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
             }
         } else if (!ctx->tti) {
             fd::AcousticStep p = acoustic_params(ctx, 1);
+            // 2D (the direct kernel, bound by launches): step n's stencil
+            // launch also injects the sources into the u^{n+1} it writes and
+            // samples the receivers of step n - 1 from the level it reads;
+            // one launch after the loop samples the last step
+            const bool fuse_rec = nd == 2 && nrec > 0;
+            const bool fuse_inj = nd == 2 && nsrc > 0;
+            if (fuse_inj) {
+                p.inj = ctx->plan[0];
+                p.inj_pts = spts;
+                p.inj_scale = scale;
+                p.inj_lo = ctx->plan_lo[0];
+                p.inj_hi = ctx->plan_hi[0];
+            }
             for (int n = 0; n < nt; ++n) {
                 float* un = ctx->u[1 - ctx->cur];  // holds u^{n-1}, receives u^{n+1}
+                p.rec_n = 0;
+                if (fuse_rec && n > 0) {
+                    p.rec_pts = rpts;
+                    p.rec_out = rec->data + (size_t)(n - 1) * nrec;
+                    p.rec_n = nrec;
+                }
+                if (fuse_inj) p.inj_q = src->data + (size_t)n * nsrc;
                 he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, 1, s);
-                if (he == hipSuccess && nsrc)
+                if (he == hipSuccess && nsrc && !fuse_inj)
                     he = fd::launch_inject(un, ctx->A, sig, spts, ctx->plan[0],
                                            src->data + (size_t)n * nsrc, scale, ctx->L, nd,
                                            ctx->L.volume, s);
-                if (he == hipSuccess && nrec)
+                if (he == hipSuccess && nrec && !fuse_rec)
                     he = fd::launch_record(un, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
                                            nd, ctx->L.volume, s);
                 if (he != hipSuccess) return hip_fail(ctx, he, "step");
                 ctx->cur = 1 - ctx->cur;
+            }
+            if (fuse_rec && nt > 0) {
+                he = fd::launch_record(ctx->u[ctx->cur], rpts, nrec,
+                                       rec->data + (size_t)(nt - 1) * nrec, 1.f, ctx->L, nd,
+                                       ctx->L.volume, s);
+                if (he != hipSuccess) return hip_fail(ctx, he, "step");
             }
         } else {
             fd::TTIStep p;

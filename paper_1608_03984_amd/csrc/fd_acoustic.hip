@@ -16,6 +16,14 @@ namespace {
 // ---------------------------------------------------------------------------
 template <int DIM, int R>
 __global__ __launch_bounds__(256) void acoustic_direct(AcousticStep p) {
+    if (p.rec_n > 0) {
+        // the previous step's receiver samples (u^n is only read here)
+        const int64_t nthr = (int64_t)gridDim.x * gridDim.y * gridDim.z * 256;
+        const int64_t g = (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 256 +
+                          threadIdx.y * 64 + threadIdx.x;
+        for (int64_t j = g; j < p.rec_n; j += nthr)
+            p.rec_out[j] = sample_point(p.uc, p.rec_pts[j], p.L, DIM);
+    }
     const int x = blockIdx.x * kTileX + threadIdx.x;
     const int y = DIM == 3 ? (int)(blockIdx.y * 4 + threadIdx.y) : 0;
     const int z = DIM == 3 ? (int)blockIdx.z : (int)(blockIdx.y * 4 + threadIdx.y);
@@ -36,7 +44,22 @@ __global__ __launch_bounds__(256) void acoustic_direct(AcousticStep p) {
     const float lap = fmaf(p.c0, c, lx + ly + lz);
     const float s = p.sig ? p.sig[i] : 0.f;
     const float a = p.A[i];
-    p.up[i] = update(c, p.up[i], a, lap, s);
+    float un = update(c, p.up[i], a, lap, s);
+    if (p.inj.ntarget > 0 && i >= p.inj_lo && i <= p.inj_hi) {
+        // a target of the plan (sorted): add its sources as the injection
+        // kernel would, to the value about to be stored
+        int lo = 0, hi = p.inj.ntarget - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (p.inj.target[mid] < i)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        if (p.inj.target[lo] == i)
+            un = inject_target(un, p.inj, lo, p.inj_pts, p.inj_q, p.inj_scale, a, s, DIM);
+    }
+    p.up[i] = un;
     if (p.acc) p.acc[i] = a * lap;
 }
 

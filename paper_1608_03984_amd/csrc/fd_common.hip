@@ -135,18 +135,7 @@ __global__ __launch_bounds__(kBlock) void inject_kernel(float* u, const float* _
     float* up = u + plan.shot[m] * shot_stride + i;
     const float a = A[i];
     const float sg = sig ? sig[i] : 0.f;
-    float uv = *up;
-    for (int e = plan.start[m]; e < plan.start[m + 1]; ++e) {
-        const int s = plan.entry[e] >> 3, c = plan.entry[e] & 7;
-        const SparsePoint P = pts[s];
-        const int dx = c & 1;
-        const int dy = ndim == 3 ? (c >> 1) & 1 : 0;
-        const int dz = ndim == 3 ? c >> 2 : c >> 1;
-        const float w =
-            (dx ? P.fx : 1.f - P.fx) * (dy ? P.fy : 1.f - P.fy) * (dz ? P.fz : 1.f - P.fz);
-        uv += w * a * q[s] * scale / (1.f + sg);
-    }
-    *up = uv;
+    *up = inject_target(*up, plan, m, pts, q, scale, a, sg, ndim);
 }
 
 __global__ __launch_bounds__(kBlock) void record_kernel(const float* __restrict__ u,
@@ -157,18 +146,7 @@ __global__ __launch_bounds__(kBlock) void record_kernel(const float* __restrict_
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
     const SparsePoint P = pts[j];
-    const int ncorner = ndim == 3 ? 8 : 4;
-    const float* us = u + P.shot * shot_stride;
-    float acc = 0.f;
-    for (int c = 0; c < ncorner; ++c) {
-        const int dx = c & 1;
-        const int dy = ndim == 3 ? (c >> 1) & 1 : 0;
-        const int dz = ndim == 3 ? c >> 2 : c >> 1;
-        const float w =
-            (dx ? P.fx : 1.f - P.fx) * (dy ? P.fy : 1.f - P.fy) * (dz ? P.fz : 1.f - P.fz);
-        if (w != 0.f) acc += w * us[P.base + dx + (int64_t)dy * L.pitch + (int64_t)dz * L.plane];
-    }
-    out[j] = acc * scale;
+    out[j] = sample_point(u + P.shot * shot_stride, P, L, ndim) * scale;
 }
 
 int grid_for(int64_t n) {

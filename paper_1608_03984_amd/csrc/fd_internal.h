@@ -40,6 +40,58 @@ struct SparsePoint {
     int32_t shot;
 };
 
+// The multilinear sample of field us at point P (2^ndim corners, zero
+// weights skipped), with one rounding per corner: every kernel that records
+// receivers forms it with this function, so they give the same bits.
+__device__ __forceinline__ float sample_point(const float* __restrict__ us, const SparsePoint& P,
+                                              const Layout& L, int ndim) {
+    const int ncorner = ndim == 3 ? 8 : 4;
+    float acc = 0.f;
+    for (int c = 0; c < ncorner; ++c) {
+        const int dx = c & 1;
+        const int dy = ndim == 3 ? (c >> 1) & 1 : 0;
+        const int dz = ndim == 3 ? c >> 2 : c >> 1;
+        const float w =
+            (dx ? P.fx : 1.f - P.fx) * (dy ? P.fy : 1.f - P.fy) * (dz ? P.fz : 1.f - P.fz);
+        if (w != 0.f) acc = fmaf(w, us[P.base + dx + (int64_t)dy * L.pitch + (int64_t)dz * L.plane], acc);
+    }
+    return acc;
+}
+
+// Injection plan of one point set: the distinct (shot, corner) targets that
+// its points' non-zero multilinear weights reach, each with its
+// contributions (point index within the set << 3 | corner) in point order, so
+// that one thread adds every contribution to a target in a fixed order: the
+// result does not depend on scheduling (no atomics).
+struct InjectPlan {
+    const int64_t* target;  // [ntarget] flat index of the corner within its volume
+    const int32_t* shot;    // [ntarget] volume (shot) of the target
+    const int32_t* start;   // [ntarget + 1] first contribution of each target
+    const int32_t* entry;   // [start[ntarget]] contributions
+    int32_t ntarget;
+};
+
+// Value uv of target m's point after its contributions: each point's
+// multilinear weight times dt^2 v^2 (a), its wavelet sample q[point] and
+// scale, over 1 + sigma (sg), added in point order.  Every kernel that
+// injects forms it with this function, so they give the same bits.
+__device__ __forceinline__ float inject_target(float uv, const InjectPlan& plan, int m,
+                                               const SparsePoint* __restrict__ pts,
+                                               const float* __restrict__ q, float scale, float a,
+                                               float sg, int ndim) {
+    for (int e = plan.start[m]; e < plan.start[m + 1]; ++e) {
+        const int s = plan.entry[e] >> 3, c = plan.entry[e] & 7;
+        const SparsePoint P = pts[s];
+        const int dx = c & 1;
+        const int dy = ndim == 3 ? (c >> 1) & 1 : 0;
+        const int dz = ndim == 3 ? c >> 2 : c >> 1;
+        const float w =
+            (dx ? P.fx : 1.f - P.fx) * (dy ? P.fy : 1.f - P.fy) * (dz ? P.fz : 1.f - P.fz);
+        uv += w * a * q[s] * scale / (1.f + sg);
+    }
+    return uv;
+}
+
 // Acoustic step: u^{n+1} = [2u^n - (1-s)u^{n-1} + A L u^n]/(1+s), written
 // over u^{n-1}.  L u = c0 u + sum_j cx[j](u[x+j]+u[x-j]) + (y) + (z).
 struct AcousticStep {
@@ -72,6 +124,21 @@ struct AcousticStep {
     // consecutive x-y tiles of every pass, and passes run in order
     int32_t slab;
     int64_t shot_stride;            // floats between the volumes of consecutive shots
+    // Direct kernel only: when rec_n > 0 the launch also records rec_n
+    // receivers (rec_pts) from u^n -- the previous step's u^{n+1}, which it
+    // only reads -- into rec_out (one sample per receiver).
+    const SparsePoint* rec_pts;
+    float* rec_out;
+    int32_t rec_n;
+    // Direct kernel, one shot only: when inj.ntarget > 0 the launch also
+    // injects the plan's points (inj_pts, wavelet samples inj_q, scale
+    // inj_scale) into the u^{n+1} it writes; the plan's targets, all of
+    // shot 0, are sorted and lie in [inj_lo, inj_hi].
+    InjectPlan inj;
+    const SparsePoint* inj_pts;
+    const float* inj_q;
+    float inj_scale;
+    int64_t inj_lo, inj_hi;
 };
 
 // TTI step (3D).  Per point the coefficient fields are
@@ -139,18 +206,6 @@ hipError_t launch_damping_profiles(const float* sig, const Layout& L, float* sx,
 hipError_t launch_damping_flags(const float* sig, int32_t* flags, const Layout& L, int tile_y,
                                 int ntx, int nty, hipStream_t s);
 
-// Injection plan of one point set: the distinct (shot, corner) targets that
-// its points' non-zero multilinear weights reach, each with its
-// contributions (point index within the set << 3 | corner) in point order, so
-// that one thread adds every contribution to a target in a fixed order: the
-// result does not depend on scheduling (no atomics).
-struct InjectPlan {
-    const int64_t* target;  // [ntarget] flat index of the corner within its volume
-    const int32_t* shot;    // [ntarget] volume (shot) of the target
-    const int32_t* start;   // [ntarget + 1] first contribution of each target
-    const int32_t* entry;   // [start[ntarget]] contributions
-    int32_t ntarget;
-};
 
 // sparse points
 // Shot k of a point writes / reads the volume u + k * shot_stride.
