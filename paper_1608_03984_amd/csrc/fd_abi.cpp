@@ -3,7 +3,9 @@
 // Validates problems, derives stencil weights (Fornberg's recursion, in
 // double, rounded once to float), lays the volumes out in the caller's
 // workspace, and enqueues the per-step launch sequence of Algorithm 1:
-// stencil update -> source injection -> receiver sampling -> level swap.
+// stencil update -> source injection -> receiver sampling -> level swap (the
+// acoustic forward run merges launches: a step samples the previous step's
+// receivers from the level it only reads).
 #include "fd.h"
 
 #include <hip/hip_runtime.h>
@@ -1259,11 +1261,13 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
             }
         } else if (!ctx->tti) {
             fd::AcousticStep p = acoustic_params(ctx, 1);
-            // 2D (the direct kernel, bound by launches): step n's stencil
-            // launch also injects the sources into the u^{n+1} it writes and
-            // samples the receivers of step n - 1 from the level it reads;
-            // one launch after the loop samples the last step
-            const bool fuse_rec = nd == 2 && nrec > 0;
+            // The receivers of step n - 1 are sampled during step n from the
+            // level u^n, which step n only reads, and one launch after the
+            // loop samples the last step.  2D (the direct kernel, bound by
+            // launches): step n's stencil launch also injects the sources
+            // into the u^{n+1} it writes and does that sampling.  3D: one
+            // launch after the stencil injects and samples.
+            const bool fuse_rec = nrec > 0;
             const bool fuse_inj = nd == 2 && nsrc > 0;
             if (fuse_inj) {
                 p.inj = ctx->plan[0];
@@ -1275,20 +1279,24 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
             for (int n = 0; n < nt; ++n) {
                 float* un = ctx->u[1 - ctx->cur];  // holds u^{n-1}, receives u^{n+1}
                 p.rec_n = 0;
-                if (fuse_rec && n > 0) {
+                if (nd == 2 && fuse_rec && n > 0) {
                     p.rec_pts = rpts;
                     p.rec_out = rec->data + (size_t)(n - 1) * nrec;
                     p.rec_n = nrec;
                 }
                 if (fuse_inj) p.inj_q = src->data + (size_t)n * nsrc;
-                he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, 1, s);
-                if (he == hipSuccess && nsrc && !fuse_inj)
-                    he = fd::launch_inject(un, ctx->A, sig, spts, ctx->plan[0],
-                                           src->data + (size_t)n * nsrc, scale, ctx->L, nd,
-                                           ctx->L.volume, s);
-                if (he == hipSuccess && nrec && !fuse_rec)
-                    he = fd::launch_record(un, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
-                                           nd, ctx->L.volume, s);
+                const float* uc = ctx->u[ctx->cur];
+                he = acoustic_stencil(ctx, p, uc, un, nullptr, 1, s);
+                if (he == hipSuccess && nd == 3) {
+                    const fd::InjectPlan none{};
+                    const bool rec_prev = nrec > 0 && n > 0;
+                    he = fd::launch_inject_record(
+                        un, ctx->A, sig, spts, nsrc ? ctx->plan[0] : none,
+                        nsrc ? src->data + (size_t)n * nsrc : nullptr, scale, uc, rpts,
+                        rec_prev ? nrec : 0,
+                        rec_prev ? rec->data + (size_t)(n - 1) * nrec : nullptr, ctx->L, nd,
+                        ctx->L.volume, s);
+                }
                 if (he != hipSuccess) return hip_fail(ctx, he, "step");
                 ctx->cur = 1 - ctx->cur;
             }
