@@ -656,6 +656,29 @@ fd::AcousticStep acoustic_params(const fd_ctx* ctx, int sb) {
     return p;
 }
 
+// The sparse-point work of forward step n in one launch: the sources of step
+// n into the new level un (and rn, the second field of the anisotropic
+// equations, when not null), and the receivers of step n - 1 from uc = u^n,
+// which step n only reads.  The last step's receivers are recorded after the
+// loop (forward_last_record).
+hipError_t forward_points(const fd_ctx* ctx, int n, float* un, float* rn, const float* uc,
+                          const fd_points* src, int nsrc, const fd_points* rec, int nrec,
+                          const float* sig, float scale, hipStream_t s) {
+    const fd::InjectPlan none{};
+    const bool rec_prev = nrec > 0 && n > 0;
+    return fd::launch_inject_record(un, rn, ctx->A, sig, ctx->pts, nsrc ? ctx->plan[0] : none,
+                                    nsrc ? src->data + (size_t)n * nsrc : nullptr, scale, uc,
+                                    ctx->pts + nsrc, rec_prev ? nrec : 0,
+                                    rec_prev ? rec->data + (size_t)(n - 1) * nrec : nullptr, ctx->L,
+                                    ctx->g.ndim, ctx->L.volume, s);
+}
+hipError_t forward_last_record(const fd_ctx* ctx, int nt, const float* u, const fd_points* rec,
+                               int nsrc, int nrec, hipStream_t s) {
+    if (nt <= 0 || nrec <= 0) return hipSuccess;
+    return fd::launch_record(u, ctx->pts + nsrc, nrec, rec->data + (size_t)(nt - 1) * nrec, 1.f,
+                             ctx->L, ctx->g.ndim, ctx->L.volume, s);
+}
+
 // One acoustic stencil launch over every shot: up <- step(uc, up),
 // optionally storing A L uc (volumes of shot k at + k * volume).
 hipError_t acoustic_stencil(const fd_ctx* ctx, fd::AcousticStep& p, const float* uc, float* up,
@@ -1245,20 +1268,13 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
                 p.pp = pn;
                 p.rp = rn;
                 he = fd::launch_vti(p, nd, ctx->radius, ctx->variant, s);
-                if (he == hipSuccess && nsrc) {
-                    const float* q = src->data + (size_t)n * nsrc;
-                    he = fd::launch_inject(pn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L, nd,
-                                           ctx->L.volume, s);
-                    if (he == hipSuccess)
-                        he = fd::launch_inject(rn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L,
-                                               nd, ctx->L.volume, s);
-                }
-                if (he == hipSuccess && nrec)
-                    he = fd::launch_record(pn, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
-                                           nd, ctx->L.volume, s);
+                if (he == hipSuccess)
+                    he = forward_points(ctx, n, pn, rn, p.pc, src, nsrc, rec, nrec, sig, scale, s);
                 if (he != hipSuccess) return hip_fail(ctx, he, "step");
                 ctx->cur = 1 - ctx->cur;
             }
+            he = forward_last_record(ctx, nt, ctx->u[ctx->cur], rec, nsrc, nrec, s);
+            if (he != hipSuccess) return hip_fail(ctx, he, "step");
         } else if (!ctx->tti) {
             fd::AcousticStep p = acoustic_params(ctx, 1);
             // The receivers of step n - 1 are sampled during step n from the
@@ -1287,25 +1303,13 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
                 if (fuse_inj) p.inj_q = src->data + (size_t)n * nsrc;
                 const float* uc = ctx->u[ctx->cur];
                 he = acoustic_stencil(ctx, p, uc, un, nullptr, 1, s);
-                if (he == hipSuccess && nd == 3) {
-                    const fd::InjectPlan none{};
-                    const bool rec_prev = nrec > 0 && n > 0;
-                    he = fd::launch_inject_record(
-                        un, ctx->A, sig, spts, nsrc ? ctx->plan[0] : none,
-                        nsrc ? src->data + (size_t)n * nsrc : nullptr, scale, uc, rpts,
-                        rec_prev ? nrec : 0,
-                        rec_prev ? rec->data + (size_t)(n - 1) * nrec : nullptr, ctx->L, nd,
-                        ctx->L.volume, s);
-                }
+                if (he == hipSuccess && nd == 3)
+                    he = forward_points(ctx, n, un, nullptr, uc, src, nsrc, rec, nrec, sig, scale, s);
                 if (he != hipSuccess) return hip_fail(ctx, he, "step");
                 ctx->cur = 1 - ctx->cur;
             }
-            if (fuse_rec && nt > 0) {
-                he = fd::launch_record(ctx->u[ctx->cur], rpts, nrec,
-                                       rec->data + (size_t)(nt - 1) * nrec, 1.f, ctx->L, nd,
-                                       ctx->L.volume, s);
-                if (he != hipSuccess) return hip_fail(ctx, he, "step");
-            }
+            he = forward_last_record(ctx, nt, ctx->u[ctx->cur], rec, nsrc, nrec, s);
+            if (he != hipSuccess) return hip_fail(ctx, he, "step");
         } else {
             fd::TTIStep p;
             std::memset(&p, 0, sizeof(p));
@@ -1338,20 +1342,13 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
                 p.pp = pn;
                 p.rp = rn;
                 he = fd::launch_tti(p, ctx->radius, ctx->variant, ctx->tile_cfg, s);
-                if (he == hipSuccess && nsrc) {
-                    const float* q = src->data + (size_t)n * nsrc;
-                    he = fd::launch_inject(pn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L, 3,
-                                           ctx->L.volume, s);
-                    if (he == hipSuccess)
-                        he = fd::launch_inject(rn, ctx->A, sig, spts, ctx->plan[0], q, scale, ctx->L,
-                                               3, ctx->L.volume, s);
-                }
-                if (he == hipSuccess && nrec)
-                    he = fd::launch_record(pn, rpts, nrec, rec->data + (size_t)n * nrec, 1.f, ctx->L,
-                                           3, ctx->L.volume, s);
+                if (he == hipSuccess)
+                    he = forward_points(ctx, n, pn, rn, p.pc, src, nsrc, rec, nrec, sig, scale, s);
                 if (he != hipSuccess) return hip_fail(ctx, he, "step");
                 ctx->cur = 1 - ctx->cur;
             }
+            he = forward_last_record(ctx, nt, ctx->u[ctx->cur], rec, nsrc, nrec, s);
+            if (he != hipSuccess) return hip_fail(ctx, he, "step");
         }
         return FD_OK;
     });

@@ -214,10 +214,11 @@ hipError_t launch_inject(float* u, const float* A, const float* sig, const Spars
                          int ndim, int64_t shot_stride, hipStream_t s);
 hipError_t launch_record(const float* u, const SparsePoint* pts, int n, float* out, float scale,
                          const Layout& L, int ndim, int64_t shot_stride, hipStream_t s);
-// One launch doing both: injection into un (as launch_inject) and, from the
-// level uc that the injection does not touch, recording (as launch_record
-// with scale 1); either part may be empty.
-hipError_t launch_inject_record(float* un, const float* A, const float* sig,
+// One launch doing both: injection into un, and into un2 when it is not
+// null (as launch_inject on each), and, from the level uc that the injection
+// does not touch, recording (as launch_record with scale 1); either part may
+// be empty.
+hipError_t launch_inject_record(float* un, float* un2, const float* A, const float* sig,
                                 const SparsePoint* spts, const InjectPlan& plan, const float* q,
                                 float scale, const float* uc, const SparsePoint* rpts, int nrec,
                                 float* out, const Layout& L, int ndim, int64_t shot_stride,
