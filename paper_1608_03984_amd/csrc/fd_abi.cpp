@@ -657,26 +657,32 @@ fd::AcousticStep acoustic_params(const fd_ctx* ctx, int sb) {
 }
 
 // The sparse-point work of forward step n in one launch: the sources of step
-// n into the new level un (and rn, the second field of the anisotropic
-// equations, when not null), and the receivers of step n - 1 from uc = u^n,
-// which step n only reads.  The last step's receivers are recorded after the
-// loop (forward_last_record).
-hipError_t forward_points(const fd_ctx* ctx, int n, float* un, float* rn, const float* uc,
-                          const fd_points* src, int nsrc, const fd_points* rec, int nrec,
-                          const float* sig, float scale, hipStream_t s) {
+// n into the new level un and, when not null, into rn (the second field of
+// the anisotropic equations, damped like un; or the stored acceleration of
+// a checkpointed run, which carries the source term without the damping
+// divisor: rn_damped false), and the receivers of step n - 1 from uc = u^n,
+// which step n only reads (nothing in the loop's first step, n_first).  The
+// loop's last step is recorded after it (forward_last_record).
+hipError_t forward_points(const fd_ctx* ctx, int n, int n_first, float* un, float* rn,
+                          bool rn_damped, const float* uc, const fd_points* src, int nsrc,
+                          const fd_points* rec, int nrec, const float* sig, float scale,
+                          hipStream_t s) {
     const fd::InjectPlan none{};
-    const bool rec_prev = nrec > 0 && n > 0;
-    return fd::launch_inject_record(un, rn, ctx->A, sig, ctx->pts, nsrc ? ctx->plan[0] : none,
+    const bool rec_prev = nrec > 0 && n > n_first;
+    return fd::launch_inject_record(un, rn, rn_damped, ctx->A, sig, ctx->pts,
+                                    nsrc ? ctx->plan[0] : none,
                                     nsrc ? src->data + (size_t)n * nsrc : nullptr, scale, uc,
                                     ctx->pts + nsrc, rec_prev ? nrec : 0,
                                     rec_prev ? rec->data + (size_t)(n - 1) * nrec : nullptr, ctx->L,
                                     ctx->g.ndim, ctx->L.volume, s);
 }
-hipError_t forward_last_record(const fd_ctx* ctx, int nt, const float* u, const fd_points* rec,
-                               int nsrc, int nrec, hipStream_t s) {
-    if (nt <= 0 || nrec <= 0) return hipSuccess;
-    return fd::launch_record(u, ctx->pts + nsrc, nrec, rec->data + (size_t)(nt - 1) * nrec, 1.f,
-                             ctx->L, ctx->g.ndim, ctx->L.volume, s);
+// The receivers of step n_end - 1 (the last of a loop over [n_first, n_end))
+// from u = u^{n_end}.
+hipError_t forward_last_record(const fd_ctx* ctx, int n_first, int n_end, const float* u,
+                               const fd_points* rec, int nsrc, int nrec, hipStream_t s) {
+    if (n_end <= n_first || nrec <= 0) return hipSuccess;
+    return fd::launch_record(u, ctx->pts + nsrc, nrec, rec->data + (size_t)(n_end - 1) * nrec,
+                             1.f, ctx->L, ctx->g.ndim, ctx->L.volume, s);
 }
 
 // One acoustic stencil launch over every shot: up <- step(uc, up),
@@ -1269,11 +1275,12 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
                 p.rp = rn;
                 he = fd::launch_vti(p, nd, ctx->radius, ctx->variant, s);
                 if (he == hipSuccess)
-                    he = forward_points(ctx, n, pn, rn, p.pc, src, nsrc, rec, nrec, sig, scale, s);
+                    he = forward_points(ctx, n, 0, pn, rn, true, p.pc, src, nsrc, rec, nrec, sig,
+                                        scale, s);
                 if (he != hipSuccess) return hip_fail(ctx, he, "step");
                 ctx->cur = 1 - ctx->cur;
             }
-            he = forward_last_record(ctx, nt, ctx->u[ctx->cur], rec, nsrc, nrec, s);
+            he = forward_last_record(ctx, 0, nt, ctx->u[ctx->cur], rec, nsrc, nrec, s);
             if (he != hipSuccess) return hip_fail(ctx, he, "step");
         } else if (!ctx->tti) {
             fd::AcousticStep p = acoustic_params(ctx, 1);
@@ -1304,11 +1311,12 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
                 const float* uc = ctx->u[ctx->cur];
                 he = acoustic_stencil(ctx, p, uc, un, nullptr, 1, s);
                 if (he == hipSuccess && nd == 3)
-                    he = forward_points(ctx, n, un, nullptr, uc, src, nsrc, rec, nrec, sig, scale, s);
+                    he = forward_points(ctx, n, 0, un, nullptr, true, uc, src, nsrc, rec, nrec, sig,
+                                        scale, s);
                 if (he != hipSuccess) return hip_fail(ctx, he, "step");
                 ctx->cur = 1 - ctx->cur;
             }
-            he = forward_last_record(ctx, nt, ctx->u[ctx->cur], rec, nsrc, nrec, s);
+            he = forward_last_record(ctx, 0, nt, ctx->u[ctx->cur], rec, nsrc, nrec, s);
             if (he != hipSuccess) return hip_fail(ctx, he, "step");
         } else {
             fd::TTIStep p;
@@ -1343,11 +1351,12 @@ int32_t fd_forward(fd_ctx* ctx, int32_t nt, const fd_points* src, const fd_point
                 p.rp = rn;
                 he = fd::launch_tti(p, ctx->radius, ctx->variant, ctx->tile_cfg, s);
                 if (he == hipSuccess)
-                    he = forward_points(ctx, n, pn, rn, p.pc, src, nsrc, rec, nrec, sig, scale, s);
+                    he = forward_points(ctx, n, 0, pn, rn, true, p.pc, src, nsrc, rec, nrec, sig,
+                                        scale, s);
                 if (he != hipSuccess) return hip_fail(ctx, he, "step");
                 ctx->cur = 1 - ctx->cur;
             }
-            he = forward_last_record(ctx, nt, ctx->u[ctx->cur], rec, nsrc, nrec, s);
+            he = forward_last_record(ctx, 0, nt, ctx->u[ctx->cur], rec, nsrc, nrec, s);
             if (he != hipSuccess) return hip_fail(ctx, he, "step");
         }
         return FD_OK;
@@ -1399,28 +1408,23 @@ int32_t check_counts(fd_ctx* ctx, const int32_t* k, int n, const char* what) {
 hipError_t forward_segment(fd_ctx* ctx, fd::AcousticStep& p, int sb, const Store* slots, int n0,
                            int n1, const fd_points* src, int nsrc, const fd_points* rec, int nrec,
                            hipStream_t s) {
-    const int nd = ctx->g.ndim;
     const float scale = (float)(1.0 / cell_volume(ctx));
     const float* sig = ctx->damping ? ctx->sig : nullptr;
     hipError_t he = hipSuccess;
     for (int n = n0; n < n1 && he == hipSuccess; ++n) {
         float* un = ctx->u[1 - ctx->cur];
+        const float* uc = ctx->u[ctx->cur];
         float* acc = slots ? slots->slot(ctx, n - n0) : nullptr;
-        he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, acc, sb, s);
-        if (he == hipSuccess && nsrc) {
-            const float* q = src->data + (size_t)n * nsrc;
-            he = fd::launch_inject(un, ctx->A, sig, ctx->pts, ctx->plan[0], q, scale, ctx->L, nd,
-                                   ctx->L.volume, s);
-            // the acceleration carries the source term without the damping divisor
-            if (he == hipSuccess && acc)
-                he = fd::launch_inject(acc, ctx->A, nullptr, ctx->pts, ctx->plan[0], q, scale,
-                                       ctx->L, nd, ctx->L.volume, s);
-        }
-        if (he == hipSuccess && nrec)
-            he = fd::launch_record(un, ctx->pts + nsrc, nrec, rec->data + (size_t)n * nrec, 1.f,
-                                   ctx->L, nd, ctx->L.volume, s);
+        he = acoustic_stencil(ctx, p, uc, un, acc, sb, s);
+        // the acceleration carries the source term without the damping
+        // divisor; the receivers of step n - 1 come from u^n (the first
+        // step of a segment records nothing: the previous segment's last
+        // step is recorded at its end)
+        if (he == hipSuccess)
+            he = forward_points(ctx, n, n0, un, acc, false, uc, src, nsrc, rec, nrec, sig, scale, s);
         ctx->cur = 1 - ctx->cur;
     }
+    if (he == hipSuccess) he = forward_last_record(ctx, n0, n1, ctx->u[ctx->cur], rec, nsrc, nrec, s);
     return he;
 }
 
@@ -1744,17 +1748,16 @@ int32_t fd_forward_shots(fd_ctx* ctx, int32_t nt, const fd_points* src, const in
         fd::AcousticStep p = acoustic_params(ctx, sb);
         for (int n = 0; n < nt; ++n) {
             float* un = ctx->u[1 - ctx->cur];
-            he = acoustic_stencil(ctx, p, ctx->u[ctx->cur], un, nullptr, sb, s);
-            if (he == hipSuccess && nsrc)
-                he = fd::launch_inject(un, ctx->A, sig, ctx->pts, ctx->plan[0],
-                                       src->data + (size_t)n * nsrc, scale, ctx->L, nd,
-                                       ctx->L.volume, s);
-            if (he == hipSuccess && nrec)
-                he = fd::launch_record(un, ctx->pts + nsrc, nrec, rec->data + (size_t)n * nrec, 1.f,
-                                       ctx->L, nd, ctx->L.volume, s);
+            const float* uc = ctx->u[ctx->cur];
+            he = acoustic_stencil(ctx, p, uc, un, nullptr, sb, s);
+            if (he == hipSuccess)
+                he = forward_points(ctx, n, 0, un, nullptr, true, uc, src, nsrc, rec, nrec, sig,
+                                    scale, s);
             if (he != hipSuccess) return hip_fail(ctx, he, "step");
             ctx->cur = 1 - ctx->cur;
         }
+        he = forward_last_record(ctx, 0, nt, ctx->u[ctx->cur], rec, nsrc, nrec, s);
+        if (he != hipSuccess) return hip_fail(ctx, he, "step");
         return FD_OK;
     });
 }

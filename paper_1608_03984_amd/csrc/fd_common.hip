@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void record_kernel(const float* __restrict_
 // Blocks [0, ninj) inject into un, the others record from uc (a different
 // level, so the two parts are independent).
 __global__ __launch_bounds__(kBlock) void inject_record_kernel(
-    float* un, float* un2, const float* __restrict__ A, const float* __restrict__ sig,
+    float* un, float* un2, int un2_damped, const float* __restrict__ A, const float* __restrict__ sig,
     const SparsePoint* __restrict__ spts, InjectPlan plan, const float* __restrict__ q,
     float scale, int ninj, const float* __restrict__ uc, const SparsePoint* __restrict__ rpts,
     int nrec, float* __restrict__ out, Layout L, int ndim, int64_t shot_stride) {
@@ -164,7 +164,8 @@ __global__ __launch_bounds__(kBlock) void inject_record_kernel(
         const float a = A[i];
         const float sg = sig ? sig[i] : 0.f;
         un[o] = inject_target(un[o], plan, m, spts, q, scale, a, sg, ndim);
-        if (un2) un2[o] = inject_target(un2[o], plan, m, spts, q, scale, a, sg, ndim);
+        if (un2)
+            un2[o] = inject_target(un2[o], plan, m, spts, q, scale, a, un2_damped ? sg : 0.f, ndim);
         return;
     }
     const int j = (blockIdx.x - ninj) * kBlock + threadIdx.x;
@@ -229,7 +230,8 @@ hipError_t launch_inject(float* u, const float* A, const float* sig, const Spars
     return hipGetLastError();
 }
 
-hipError_t launch_inject_record(float* un, float* un2, const float* A, const float* sig,
+hipError_t launch_inject_record(float* un, float* un2, bool un2_damped, const float* A,
+                                const float* sig,
                                 const SparsePoint* spts, const InjectPlan& plan, const float* q,
                                 float scale, const float* uc, const SparsePoint* rpts, int nrec,
                                 float* out, const Layout& L, int ndim, int64_t shot_stride,
@@ -237,7 +239,8 @@ hipError_t launch_inject_record(float* un, float* un2, const float* A, const flo
     const int ninj = plan.ntarget > 0 ? (plan.ntarget + kBlock - 1) / kBlock : 0;
     const int nrb = nrec > 0 ? (nrec + kBlock - 1) / kBlock : 0;
     if (ninj + nrb == 0) return hipSuccess;
-    hipLaunchKernelGGL(inject_record_kernel, dim3(ninj + nrb), dim3(kBlock), 0, s, un, un2, A, sig,
+    hipLaunchKernelGGL(inject_record_kernel, dim3(ninj + nrb), dim3(kBlock), 0, s, un, un2,
+                       un2_damped ? 1 : 0, A, sig,
                        spts, plan, q, scale, ninj, uc, rpts, nrec, out, L, ndim, shot_stride);
     return hipGetLastError();
 }

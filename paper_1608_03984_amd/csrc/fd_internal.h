@@ -215,10 +215,12 @@ hipError_t launch_inject(float* u, const float* A, const float* sig, const Spars
 hipError_t launch_record(const float* u, const SparsePoint* pts, int n, float* out, float scale,
                          const Layout& L, int ndim, int64_t shot_stride, hipStream_t s);
 // One launch doing both: injection into un, and into un2 when it is not
-// null (as launch_inject on each), and, from the level uc that the injection
-// does not touch, recording (as launch_record with scale 1); either part may
-// be empty.
-hipError_t launch_inject_record(float* un, float* un2, const float* A, const float* sig,
+// null (as launch_inject on each; into un2 without the damping divisor when
+// un2_damped is false), and, from the level uc that the injection does not
+// touch, recording (as launch_record with scale 1); either part may be
+// empty.
+hipError_t launch_inject_record(float* un, float* un2, bool un2_damped, const float* A,
+                                const float* sig,
                                 const SparsePoint* spts, const InjectPlan& plan, const float* q,
                                 float scale, const float* uc, const SparsePoint* rpts, int nrec,
                                 float* out, const Layout& L, int ndim, int64_t shot_stride,

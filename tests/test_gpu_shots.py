@@ -214,10 +214,11 @@ def test_shots_error_paths():
     assert e.value.code == P.FD_ERR_UNSUPPORTED
 
 
-def test_2d_fused_step_equals_separate_launches():
+def test_2d_fused_step_equals_the_sparse_point_launch():
     """In 2D, fd_forward's stencil launch also injects the sources and
     records the previous step's receivers; fd_forward_shots on a one-shot
-    context launches injection and recording separately.  Sources that share
+    context leaves both to a launch of their own after each stencil
+    launch.  Sources that share
     corners, sit on grid nodes (zero-weight corners) and at the first and
     last points of the padded grid, receivers on those points too, and runs
     of 1, 7 and 0 steps that keep the points give the same bits."""
