@@ -1,0 +1,62 @@
+"""GPU: a forward run split into several calls gives the bits of one call.
+
+After each stencil launch one launch injects the step's sources and records
+the previous step's receivers from the level the stencil only read (in 2D
+acoustic runs the stencil launch itself does both), and a call records its
+last step when it ends.  So a run made of calls of 1, 7, 0 and the remaining
+steps, each keeping the points of the first, must give the traces and the
+final fields of one call of all the steps, for every physics.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1608_03984_amd as P  # noqa: E402
+from paper_1608_03984_amd.solver import from_problem  # noqa: E402
+from tests._gpu_util import acoustic_problem, say, tti_problem, vti_problem  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "acoustic-3d": lambda: acoustic_problem(3, (70, 30, 34), 5, 8, 24, seed=81, nrec=9),
+    "acoustic-2d": lambda: acoustic_problem(2, (61, 1, 43), 6, 4, 24, seed=82, nrec=9),
+    "vti-3d": lambda: vti_problem(3, (40, 30, 28), 5, 8, 24, seed=83, nrec=9),
+    "vti-2d": lambda: vti_problem(2, (61, 1, 43), 6, 8, 24, seed=84, nrec=9),
+    "tti-3d": lambda: tti_problem((40, 30, 28), 5, 8, 24, seed=85, nrec=9),
+}
+
+
+def fields(s, aniso):
+    which = [P.FD_FIELD_CUR, P.FD_FIELD_PREV]
+    if aniso:
+        which += [P.FD_FIELD_R_CUR, P.FD_FIELD_R_PREV]
+    return [s.get_field(w).cpu().numpy() for w in which]
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_split_run_equals_one_run(case):
+    p = CASES[case]()
+    aniso = p.physics != "acoustic"
+    # one receiver on the source point: it records the injection of its step
+    rec = np.concatenate([p.src, p.rec])
+    q = (p.wavelet * 1e3).astype(np.float32)
+    say(f"case: split run {case} {p.padded}")
+    a = from_problem(p)
+    whole = a.forward(p.nt, p.src, q, rec).cpu().numpy()
+    fa = fields(a, aniso)
+    torch.cuda.synchronize()
+    a.close()
+    b = from_problem(p)
+    parts = [b.forward(1, p.src, q[:1], rec)]
+    parts.append(b.forward(7, p.src, q[1:8], rec, zero_state=False, keep_points=True))
+    parts.append(b.forward(0, p.src, q[8:8], rec, zero_state=False, keep_points=True))
+    parts.append(b.forward(p.nt - 8, p.src, q[8:], rec, zero_state=False, keep_points=True))
+    split = np.concatenate([t.cpu().numpy().reshape(-1, len(rec)) for t in parts])
+    fb = fields(b, aniso)
+    torch.cuda.synchronize()
+    b.close()
+    assert np.abs(whole).max() > 0
+    assert np.array_equal(whole, split)
+    for x, y in zip(fa, fb):
+        assert np.array_equal(x, y)
