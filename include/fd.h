@@ -144,6 +144,9 @@ int32_t fd_setup(const fd_grid* grid, const fd_model* model, void* workspace,
  * every point (with the damping layer), then the source term q[n] added to
  * the new level (Algorithm 1, "Add Source"; for TTI into both p and r), then
  * receivers sampled from the new level into rec->data[n] (TTI: from p).
+ * The sampling of step n is launched with step n + 1's work, which only
+ * reads that level, and the last step's when the call's steps end: every
+ * row of rec->data is written once the call's work on `stream` completes.
  * The point-source amplitude q enters as dt^2 v^2 q / (prod h) / (1 + eta dt/2)
  * spread over the multilinear corners; where several points share a corner
  * their contributions are added in point order, so runs are bitwise
