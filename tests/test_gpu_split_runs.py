@@ -60,3 +60,53 @@ def test_split_run_equals_one_run(case):
     assert np.array_equal(whole, split)
     for x, y in zip(fa, fb):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("case", ["acoustic-3d", "acoustic-2d", "tti-3d"])
+def test_one_kind_of_point_only(case):
+    """Receivers without sources (from a noise state) and sources without
+    receivers: the step launch then has only its recording or only its
+    injection part.  A run split over calls equals one call bit for bit,
+    and the sources-only run ends in the same fields as the same run that
+    also records."""
+    from workloads import noise_state
+    p = CASES[case]()
+    aniso = p.physics != "acoustic"
+    say(f"case: one kind of point {case} {p.padded}")
+
+    def noise_run(split):
+        s = from_problem(p)
+        s.set_field(P.FD_FIELD_PREV, noise_state(p.padded, 5))
+        s.set_field(P.FD_FIELD_CUR, noise_state(p.padded, 6))
+        if split:
+            parts = [s.forward(3, None, None, p.rec, zero_state=False)]
+            parts.append(s.forward(p.nt - 3, None, None, p.rec, zero_state=False,
+                                   keep_points=True))
+            tr = np.concatenate([t.cpu().numpy() for t in parts])
+        else:
+            tr = s.forward(p.nt, None, None, p.rec, zero_state=False).cpu().numpy()
+        f = fields(s, aniso)
+        torch.cuda.synchronize()
+        s.close()
+        return tr, f
+
+    t1, f1 = noise_run(False)
+    t2, f2 = noise_run(True)
+    assert np.abs(t1).max() > 0 and np.array_equal(t1, t2)
+    for x, y in zip(f1, f2):
+        assert np.array_equal(x, y)
+
+    q = (p.wavelet * 1e3).astype(np.float32)
+    s = from_problem(p)
+    assert s.forward(p.nt, p.src, q, None) is None
+    fs = fields(s, aniso)
+    torch.cuda.synchronize()
+    s.close()
+    s = from_problem(p)
+    s.forward(p.nt, p.src, q, p.rec)
+    fr = fields(s, aniso)
+    torch.cuda.synchronize()
+    s.close()
+    assert np.abs(fs[0]).max() > 0
+    for x, y in zip(fs, fr):
+        assert np.array_equal(x, y)
